@@ -1,0 +1,119 @@
+"""The CPU oracle against brute force, closed forms, invariants and the
+paper's printed worked example (all CPU-only)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle_pins as pins
+from oracle import ic, spectral
+
+
+@pytest.mark.parametrize("name", sorted(pins.FAST_PINS))
+def test_fast_pin(name):
+    err = pins.FAST_PINS[name]()
+    assert err <= pins.TOL[name], f"{name}: {err:.3e} > {pins.TOL[name]:.0e}"
+
+
+def test_rk4_fourth_order():
+    r = pins.rk4_order_ratio()
+    assert pins.TOL["rk4_order_lo"] <= r <= pins.TOL["rk4_order_hi"], r
+
+
+@pytest.mark.slow
+def test_appendix_worked_example():
+    """Appendix TG solver, N = 128, 10 steps: final energy as printed."""
+    err = pins.appendix_error()
+    assert err <= pins.TOL["appendix"], err
+
+
+def test_wavenumbers_storage_order():
+    kx, ky, kz = spectral.wavenumbers(8)
+    assert list(kx) == [0, 1, 2, 3, -4, -3, -2, -1]
+    assert list(ky) == list(kx)
+    assert list(kz) == [0, 1, 2, 3, 4]          # last entry is +N/2
+
+
+def test_dealias_cutoffs(golden_dir):
+    with open(os.path.join(golden_dir, "dealias_cutoffs.json")) as f:
+        g = json.load(f)["largest_kept"]
+    for rule, table in g.items():
+        for n_str, kmax in table.items():
+            N = int(n_str)
+            mask = spectral.dealias_mask(N, rule)
+            kx, ky, kz = spectral.wavenumbers(N)
+            kept_x = np.abs(kx)[mask.any(axis=(1, 2))]
+            kept_z = np.abs(kz)[mask.any(axis=(0, 1))]
+            assert kept_x.max() == kmax and kept_z.max() == kmax, (rule, N)
+            # the mask is a cube: product of the three 1D masks
+            assert mask.sum() == (np.abs(kx) <= kmax).sum() ** 2 * (np.abs(kz) <= kmax).sum()
+
+
+def test_dft_matrix_entries_are_reduced_roots():
+    N = 64
+    F = spectral.dft_matrix(N)
+    roots = np.exp(-2j * np.pi * np.arange(N) / N)
+    m = np.arange(N)
+    r = np.outer(m, m) % N
+    assert np.max(np.abs(F - roots[r])) < 4e-16
+    assert np.all(F[:, 0] == 1.0) and np.all(F[0, :] == 1.0)
+    assert F[N // 4, 1] == -1j and F[N // 2, 1] == -1.0
+
+
+def test_hermitian_planes_of_real_field():
+    N = 16
+    uh = spectral.dft3(np.random.default_rng(2).standard_normal((3, N, N, N)))
+    mx = (-np.arange(N)) % N
+    for iz in (0, N // 2):
+        plane = uh[:, :, :, iz]
+        mirror = np.conj(plane[:, mx][:, :, mx])
+        assert np.max(np.abs(plane - mirror)) < 1e-12 * np.abs(plane).max()
+
+
+def test_splitmix64_published_outputs(golden_dir):
+    with open(os.path.join(golden_dir, "splitmix64.json")) as f:
+        g = json.load(f)
+    for s in g["streams"]:
+        vals = [int(v) for v in ic.splitmix64_stream(s["seed"], 5)]
+        if "outputs_hex" in s:
+            want = [int(h, 16) for h in s["outputs_hex"]]
+        else:
+            want = s["outputs"]
+        assert vals[: len(want)] == want
+
+
+@pytest.mark.parametrize("N", [16, 32])
+def test_random_isotropic_invariants(N):
+    uh = ic.random_isotropic(N, seed=1)
+    assert abs(spectral.energy(uh) - 0.5) < 1e-14
+    assert spectral.divergence_max(uh) < 1e-14
+    mask = spectral.dealias_mask(N)
+    assert np.all(uh[:, ~mask] == 0)
+    assert np.all(uh[:, 0, 0, 0] == 0)
+    # Hermitian planes: the field is the half spectrum of a real field
+    u = spectral.idft3(uh)
+    assert np.max(np.abs(spectral.dft3(u) - uh)) < 1e-13 * np.abs(uh).max()
+    # different seeds differ, same seed reproduces
+    assert np.array_equal(uh, ic.random_isotropic(N, seed=1))
+    assert not np.allclose(uh, ic.random_isotropic(N, seed=2))
+
+
+def test_random_isotropic_shell_spectrum():
+    """Energy per mode follows E(|k|) / (4 pi |k|^2) with
+    E(k) = k^4 exp(-2 (k/4)^2), up to sampling noise: the shell-summed
+    energy over the shell-summed model is flat across shells."""
+    N = 64
+    uh = ic.random_isotropic(N, seed=7)
+    K, K2, _ = spectral.wavenumber_mesh(N)
+    w = np.full(N // 2 + 1, 2.0)
+    w[0] = w[-1] = 1.0
+    e_mode = 0.5 * w * np.sum(np.abs(uh) ** 2, axis=0)
+    kmag = np.sqrt(K2.astype(float))
+    safe = np.where(K2 == 0, 1.0, kmag)
+    model = w * safe ** 4 * np.exp(-2.0 * (safe / 4.0) ** 2) / (4 * np.pi * safe ** 2)
+    model = np.where((K2 == 0) | ~spectral.dealias_mask(N), 0.0, model)
+    shell = np.rint(kmag).astype(int)
+    ks = np.arange(3, 13)
+    ratio = np.bincount(shell.ravel(), e_mode.ravel())[ks] / np.bincount(shell.ravel(), model.ravel())[ks]
+    assert np.std(ratio) / np.mean(ratio) < 0.1, ratio
