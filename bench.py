@@ -1,0 +1,151 @@
+"""Benchmark: ms per RK4 step of the Taylor-Green vortex at 512^3 on one
+MI355X, FP64 (headline) and FP32, through the C ABI of libdns.so.
+
+Prints ONE JSON line.  Inputs are resident in HBM before the timed region;
+the timed region is K graph-replayed RK4 steps bracketed by device
+synchronisation.  The roofline object reports the dominant kernel's
+algorithmic HBM bytes per launch over its mean duration (HIP events on the
+library's stream), against the 8 TB/s HBM peak.  The cpu_baseline object
+times the CPU oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ms per RK4 step at 512^3 (FP64 vs FP32) + HBM GB/s; ensemble steps/s"
+HBM_PEAK_GBPS = 8000.0
+N_DEFAULT, NU, DT = 512, 1.0 / 1600, 1e-3
+
+# Algorithmic HBM traffic of each kernel of one stage, in half-spectrum
+# fields C = N^2 (N/2+1) complex values (read + write); xrhs_rk4 averages
+# the four stages (N_hat reads 3C per stage plus RK4 state traffic 48C per
+# step).  One step moves 4 * 36 C + 60 C = 204 C.
+FIELDS_PER_LAUNCH = {"xinv_curl": 9.0, "yinv6": 12.0, "zcross": 9.0, "yfwd3": 6.0, "xrhs_rk4": 60.0 / 4}
+FIELDS_PER_STEP = 204.0
+
+
+def field_bytes(N, dtype):
+    return N * N * (N // 2 + 1) * (16 if dtype == "f64" else 8)
+
+
+def run_gpu(N, dtype, steps, warmup, prof_steps):
+    import torch
+    import workloads
+    from paper_1602_03638_amd import Solver
+
+    u0 = torch.from_numpy(workloads.taylor_green(N)).to(torch.float64 if dtype == "f64" else torch.float32)
+    u0 = u0.cuda().contiguous()
+    s = Solver(N, NU, DT, dtype=dtype)
+    s.set_velocity(u0)
+    del u0
+    s.step(warmup)
+    s.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.synchronize()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    E, W = s.diagnostics()
+    kern = s.profile_step(prof_steps) if prof_steps > 0 else {}
+    s.close()
+    torch.cuda.empty_cache()
+    C = field_bytes(N, dtype)
+    out = {"ms_per_step": ms, "model_GBps": FIELDS_PER_STEP * C / (ms * 1e-3) / 1e9,
+           "energy": E, "enstrophy": W, "kernels_ms": kern}
+    if kern:
+        achieved = {k: FIELDS_PER_LAUNCH[k] * C / (v * 1e-3) / 1e9 for k, v in kern.items()}
+        out["kernels_GBps"] = achieved
+    return out
+
+
+def cpu_baseline(N):
+    """Time the CPU oracle on a bounded sample of the workload: one inverse and
+    one forward 3D transform of one velocity component at N^3, scaled to one
+    RK4 step (4 stages x (6 inverse + 3 forward) transforms).  The
+    elementwise work of the RHS is excluded, so this is a lower bound on
+    the oracle's time per step."""
+    import numpy as np
+    import workloads
+    from oracle import spectral
+
+    u = workloads.taylor_green(N)[0]
+    t0 = time.perf_counter()
+    uh = spectral.dft3(u)
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    spectral.idft3(uh)
+    t_inv = time.perf_counter() - t0
+    ms = 4 * (6 * t_inv + 3 * t_fwd) * 1e3
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        threads = max([i.get("num_threads", 1) for i in info] or [threads])
+    except Exception:
+        pass
+    del np
+    return {"value": ms, "unit": "ms/step", "cores": threads, "kind": "oracle",
+            "sample": f"one forward ({t_fwd:.2f} s) and one inverse ({t_inv:.2f} s) 3D DFT of one "
+                      f"component at {N}^3 on the host, scaled by 4 stages x (6 inverse + 3 forward); "
+                      "RHS elementwise work excluded"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--N", type=int, default=N_DEFAULT)
+    ap.add_argument("--prof-steps", type=int, default=2)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the slab decomposition over several GPUs is described, not built)", file=sys.stderr)
+        return 2
+
+    f64 = run_gpu(a.N, "f64", a.steps, a.warmup, a.prof_steps)
+    f32 = None if a.no_fp32 else run_gpu(a.N, "f32", a.steps, a.warmup, a.prof_steps)
+
+    roof = None
+    if f64["kernels_ms"]:
+        dom = max(f64["kernels_ms"], key=f64["kernels_ms"].get)
+        C = field_bytes(a.N, "f64")
+        ach = f64["kernels_GBps"][dom]
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None,
+                "bytes_per_launch": FIELDS_PER_LAUNCH[dom] * C,
+                "mean_launch_ms": f64["kernels_ms"][dom]}
+    cpu = None if a.no_cpu_baseline else cpu_baseline(a.N)
+    line = {
+        "metric": METRIC, "value": round(f64["ms_per_step"], 4), "unit": "ms/step",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(f64["ms_per_step"], 4), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"taylor_green_{a.N}_rk4", "N": a.N, "nu": NU, "dt": DT,
+                   "dealias": "2/3 rule, kmax = N/3", "parallelism": "single_gpu"},
+        "model_GBps": round(f64["model_GBps"], 1),
+        "model_frac_of_hbm_peak": round(f64["model_GBps"] / HBM_PEAK_GBPS, 4),
+        "energy": f64["energy"], "enstrophy": f64["enstrophy"],
+        "kernels_ms": f64["kernels_ms"],
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if f32 is not None:
+        line["fp32"] = {"ms_per_step": round(f32["ms_per_step"], 4), "model_GBps": round(f32["model_GBps"], 1),
+                        "energy": f32["energy"], "enstrophy": f32["enstrophy"],
+                        "rel_energy_diff_vs_fp64": abs(f32["energy"] - f64["energy"]) / f64["energy"],
+                        "kernels_ms": f32["kernels_ms"]}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,169 @@
+/*
+ * dns.h - C ABI of the MI355X pseudo-spectral Navier-Stokes RK4 library.
+ *
+ * The library advances the incompressible Navier-Stokes equations in
+ * rotational form in the triply periodic box [0, 2 pi)^3 with the Fourier-
+ * Galerkin pseudo-spectral method of Mortensen & Langtangen, "High
+ * performance Python for direct numerical simulations of turbulent flows"
+ * (arXiv:1602.03638):
+ *
+ *   d u_hat/dt = N_hat - nu |k|^2 u_hat - k (k . N_hat) / |k|^2,
+ *   N_hat = dealias * F(u x omega),  omega = F^-1(i k x u_hat)
+ *
+ * (Sec. 2, eqs. NSfinal and curl_convection; Sec. 3.1 computeRHS listing),
+ * integrated with classic RK4 (Appendix solver).  All compute runs in HIP
+ * kernels for gfx950; there is no CPU fallback.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - N is the number of mesh points per axis, a power of two with
+ *   8 <= N <= 1024 (Sec. 3.1 requires N = 2^M).
+ * - Physical arrays: (3, N, N, N) real, C order, index [c][i][j][k] for the
+ *   point (x_i, y_j, z_k) = 2 pi (i, j, k) / N (Sec. 2, eq. realmesh).
+ * - Spectral arrays: (3, N, N, N/2+1) complex interleaved (re, im), C order,
+ *   index [c][ix][iy][iz] with kx = ix for ix < N/2 else ix - N (same for
+ *   ky) and kz = iz, so iz = N/2 is kz = +N/2 (Sec. 3.1 storage order).
+ *   Values are the unnormalised forward transform
+ *   u_hat(k) = sum_x u(x) exp(-i k.x) (Sec. 2, eq. iffteq), i.e. what
+ *   numpy.fft.rfftn(u, axes=(1,2,3)) returns.
+ * - The real type is the context's dtype: double for DNS_FP64, float for
+ *   DNS_FP32 (complex = two of them).  Energy and enstrophy are always
+ *   accumulated and returned in double.
+ * - Every data pointer is a DEVICE pointer owned by the caller; the library
+ *   copies from it on set and writes into it on get, and never frees it.
+ * - Calls are ordered on the context's stream (the stream given at creation,
+ *   or the null stream): dns_step and the set/get calls are asynchronous
+ *   with respect to the host; dns_energy, dns_enstrophy, dns_diagnostics,
+ *   dns_history and dns_synchronize wait for the stream.
+ * - Every function returns a dns_status; no C++ exception crosses the ABI.
+ *   After a failure dns_last_error(ctx) holds a message.  A context is not
+ *   thread-safe; distinct contexts are independent.
+ */
+#ifndef DNS_H
+#define DNS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dns_status {
+    DNS_OK = 0,
+    DNS_E_INVAL = -1,        /* bad argument (N, nu, dt, dtype, NULL pointer, size) */
+    DNS_E_NOMEM = -2,        /* device allocation failed */
+    DNS_E_HIP = -3,          /* a HIP runtime call or kernel launch failed */
+    DNS_E_STATE = -4,        /* call not valid in the context's state (no velocity set) */
+    DNS_E_NONFINITE = -5,    /* a diagnostic came out NaN or Inf */
+    DNS_E_UNSUPPORTED = -6   /* valid request this build does not provide */
+} dns_status;
+
+typedef enum dns_dtype { DNS_FP64 = 0, DNS_FP32 = 1 } dns_dtype;
+
+/* Dealiasing constant (Sec. 3.1 listing: kmax = N/3; Appendix: kmax =
+ * 2/3 (N/2+1)).  A mode is kept iff 3|k_i| < N (TEXT) or 3|k_i| < N + 2
+ * (APPENDIX) on all three axes. */
+typedef enum dns_dealias { DNS_DEALIAS_TEXT = 0, DNS_DEALIAS_APPENDIX = 1 } dns_dealias;
+
+typedef struct dns_opts {
+    int dealias;      /* dns_dealias; default DNS_DEALIAS_TEXT */
+    int diag_every;   /* record E and Omega after every k-th step into the
+                         history buffer (0 = never); default 0 */
+    int history_cap;  /* capacity of the history buffer in steps; default 4096 */
+    int use_graph;    /* 1 = replay each RK4 step as one captured HIP graph
+                         (default), 0 = launch kernels one by one */
+} dns_opts;
+
+typedef struct dns_ctx dns_t;
+
+/* Fill *opts with the defaults listed above. */
+void dns_default_opts(dns_opts* opts);
+
+/* Create a solver for N^3 points, viscosity nu >= 0, time step dt > 0 and
+ * dtype DNS_FP64 or DNS_FP32 (Sec. 3.1: float is a placeholder for single
+ * or double precision).  The library allocates its device state (15 half-
+ * spectrum fields of N*N*(N/2+1) complex values plus O(N) tables) on the
+ * current HIP device.  stream: a hipStream_t cast to void*, or NULL for the
+ * null stream.  opts may be NULL.  On success *out owns the context. */
+int dns_create(int N, double nu, double dt, int dtype, dns_t** out);
+int dns_create_ex(int N, double nu, double dt, int dtype, const dns_opts* opts,
+                  void* stream, dns_t** out);
+
+/* Release every allocation of ctx (device state, graphs, stream); NULL is a
+ * no-op.  Does not touch caller memory. */
+int dns_destroy(dns_t* ctx);
+
+/* Bytes of device memory a context of this size holds. */
+size_t dns_state_bytes(int N, int dtype);
+
+/* u_hat = F(u) for the physical (3, N, N, N) real field u_dev: real
+ * transform along z, then complex along y, then x (Sec. 2, eq. fft);
+ * unnormalised.  No masking or projection is applied (the Appendix solver
+ * transforms its initial condition as given).  Resets the step counter and
+ * the history. */
+int dns_set_velocity(dns_t* ctx, const void* u_dev);
+
+/* Load u_hat from a (3, N, N, N/2+1) complex array. */
+int dns_set_spectral(dns_t* ctx, const void* uhat_dev);
+
+/* Copy the current u_hat into a (3, N, N, N/2+1) complex array. */
+int dns_get_spectral(dns_t* ctx, void* uhat_dev);
+
+/* u = F^-1(u_hat) into a (3, N, N, N) real array: complex inverse along x,
+ * then y, then the inverse real transform along z, with 1/N^3 (Sec. 2,
+ * eq. ifft); the imaginary parts of the kz = 0 and kz = N/2 coefficients do
+ * not enter (numpy irfftn semantics). */
+int dns_get_velocity(dns_t* ctx, void* u_dev);
+
+/* Advance nsteps >= 0 classic RK4 steps (Appendix solver: a = 1/6, 1/3,
+ * 1/3, 1/6; b = 1/2, 1/2, 1).  Each stage evaluates eq. NSfinal: inverse
+ * transforms of u_hat and omega_hat = i k x u_hat, u x omega in physical
+ * space, forward transform, dealias mask, pressure projection and viscous
+ * term.  Asynchronous. */
+int dns_step(dns_t* ctx, int nsteps);
+
+/* One evaluation of the right-hand side of eq. NSfinal at the current
+ * state, written as a (3, N, N, N/2+1) complex array; the state is not
+ * changed.  For verification of a single stage. */
+int dns_rhs(dns_t* ctx, void* rhs_dev);
+
+/* E = mean over the mesh of |u|^2 / 2 (the Appendix's final energy) and
+ * Omega = mean of |omega|^2 / 2, evaluated from the spectrum by Parseval
+ * with FP64 accumulation in a fixed order.  Synchronous.  DNS_E_NONFINITE
+ * if the value is NaN or Inf (the value is still written). */
+int dns_energy(dns_t* ctx, double* E);
+int dns_enstrophy(dns_t* ctx, double* Omega);
+int dns_diagnostics(dns_t* ctx, double* E, double* Omega);
+
+/* Copy up to max recorded (E, Omega) pairs (one per diag_every steps since
+ * the last set) into host arrays E and Omega; *count receives the number
+ * recorded.  Synchronous. */
+int dns_history(dns_t* ctx, double* E, double* Omega, int max, int* count);
+
+/* Number of RK4 steps taken since the last set call. */
+int dns_steps_taken(const dns_t* ctx, long long* steps);
+
+/* Wait until all work the context enqueued has finished. */
+int dns_synchronize(dns_t* ctx);
+
+/* Time each kernel of one RK4 step: runs nsteps steps with kernels launched
+ * one by one on the context's stream, bracketed by HIP events, and writes
+ * the mean duration in milliseconds of each of the step's kernels (in
+ * launch order) into ms[0..*count-1] (at most max entries) and their names
+ * (static strings) into names when non-NULL.  Advances the state. */
+int dns_profile_step(dns_t* ctx, int nsteps, float* ms, const char** names, int max, int* count);
+
+/* Standalone 3D transforms on caller buffers, using the context's plan and
+ * work space (the state is not changed): forward real-to-complex
+ * (3, N, N, N) -> (3, N, N, N/2+1) and inverse complex-to-real. */
+int dns_forward(dns_t* ctx, const void* u_dev, void* uhat_dev);
+int dns_inverse(dns_t* ctx, const void* uhat_dev, void* u_dev);
+
+const char* dns_strerror(int status);
+const char* dns_last_error(const dns_t* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DNS_H */

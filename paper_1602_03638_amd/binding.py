@@ -1,0 +1,281 @@
+"""ctypes binding of libdns.so (declared in include/dns.h).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels
+of the library.  PyTorch provides device memory and the current stream.
+There is no fallback: if libdns.so has not been built, or no GPU is present,
+the calls raise.
+"""
+import ctypes
+import os
+import re
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+LIB_PATH = os.path.join(PKG, "libdns.so")
+HEADER = os.path.join(ROOT, "include", "dns.h")
+
+DNS_OK = 0
+DNS_E_INVAL = -1
+DNS_E_NOMEM = -2
+DNS_E_HIP = -3
+DNS_E_STATE = -4
+DNS_E_NONFINITE = -5
+DNS_E_UNSUPPORTED = -6
+DNS_FP64 = 0
+DNS_FP32 = 1
+DNS_DEALIAS_TEXT = 0
+DNS_DEALIAS_APPENDIX = 1
+
+
+class DnsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class dns_opts(ctypes.Structure):
+    _fields_ = [("dealias", ctypes.c_int), ("diag_every", ctypes.c_int),
+                ("history_cap", ctypes.c_int), ("use_graph", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libdns.so once.  torch is imported first so that the library
+    binds to the HIP runtime torch already loaded (same soname)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1602_03638_amd.build` "
+                           "(there is no CPU fallback)")
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path, mode=ctypes.RTLD_GLOBAL)
+    P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    sigs = {
+        "dns_default_opts": (None, [ctypes.POINTER(dns_opts)]),
+        "dns_state_bytes": (S, [I, I]),
+        "dns_create": (I, [I, D, D, I, PP]),
+        "dns_create_ex": (I, [I, D, D, I, ctypes.POINTER(dns_opts), P, PP]),
+        "dns_destroy": (I, [P]),
+        "dns_set_velocity": (I, [P, P]),
+        "dns_set_spectral": (I, [P, P]),
+        "dns_get_spectral": (I, [P, P]),
+        "dns_get_velocity": (I, [P, P]),
+        "dns_step": (I, [P, I]),
+        "dns_rhs": (I, [P, P]),
+        "dns_energy": (I, [P, ctypes.POINTER(D)]),
+        "dns_enstrophy": (I, [P, ctypes.POINTER(D)]),
+        "dns_diagnostics": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D)]),
+        "dns_history": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D), I, ctypes.POINTER(I)]),
+        "dns_steps_taken": (I, [P, ctypes.POINTER(ctypes.c_longlong)]),
+        "dns_synchronize": (I, [P]),
+        "dns_profile_step": (I, [P, I, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_char_p), I,
+                                 ctypes.POINTER(I)]),
+        "dns_forward": (I, [P, P, P]),
+        "dns_inverse": (I, [P, P, P]),
+        "dns_strerror": (ctypes.c_char_p, [I]),
+        "dns_last_error": (ctypes.c_char_p, [P]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def header_functions(header=HEADER):
+    """Names of every function declared in include/dns.h."""
+    with open(header) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dns_[a-z_0-9]+)\s*\(", text)))
+
+
+def _check(status, ctx=None, what=""):
+    if status != DNS_OK:
+        lib = load_library()
+        msg = lib.dns_strerror(status).decode()
+        if ctx:
+            detail = lib.dns_last_error(ctx).decode()
+            if detail:
+                msg += ": " + detail
+        raise DnsError(status, f"{what}: {msg}" if what else msg)
+
+
+def default_opts():
+    o = dns_opts()
+    load_library().dns_default_opts(ctypes.byref(o))
+    return o
+
+
+def state_bytes(N, dtype):
+    return int(load_library().dns_state_bytes(int(N), int(dtype)))
+
+
+class Solver:
+    """One pseudo-spectral DNS context on the current GPU (see include/dns.h).
+
+    dtype: "f64" or "f32".  Tensors passed in must be contiguous CUDA tensors:
+    physical (3, N, N, N) float64/float32, spectral (3, N, N, N/2+1)
+    complex128/complex64.  All work is ordered on torch's current stream at
+    construction time.
+    """
+
+    def __init__(self, N, nu, dt, dtype="f64", dealias="text", diag_every=0, use_graph=True,
+                 history_cap=4096, stream=None):
+        import torch
+        self._torch = torch
+        lib = load_library()
+        self.N, self.nu, self.dt = int(N), float(nu), float(dt)
+        self.dtype = dtype
+        self.code = {"f64": DNS_FP64, "f32": DNS_FP32}[dtype]
+        self.real = torch.float64 if dtype == "f64" else torch.float32
+        self.complex = torch.complex128 if dtype == "f64" else torch.complex64
+        o = default_opts()
+        o.dealias = {"text": DNS_DEALIAS_TEXT, "appendix": DNS_DEALIAS_APPENDIX}[dealias]
+        o.diag_every = int(diag_every)
+        o.use_graph = 1 if use_graph else 0
+        o.history_cap = int(history_cap)
+        self.history_cap = int(history_cap)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(lib.dns_create_ex(self.N, self.nu, self.dt, self.code, ctypes.byref(o),
+                                 ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)), None, "dns_create_ex")
+        self._h = h
+
+    # -- helpers ----------------------------------------------------------
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise RuntimeError("solver is closed")
+        return self._h
+
+    def _phys(self, t):
+        N = self.N
+        if (not t.is_cuda or t.dtype != self.real or tuple(t.shape) != (3, N, N, N)
+                or not t.is_contiguous()):
+            raise ValueError(f"expected a contiguous CUDA {self.real} tensor of shape (3, {N}, {N}, {N})")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _spec(self, t):
+        N = self.N
+        if (not t.is_cuda or t.dtype != self.complex or tuple(t.shape) != (3, N, N, N // 2 + 1)
+                or not t.is_contiguous()):
+            raise ValueError(f"expected a contiguous CUDA {self.complex} tensor of shape "
+                             f"(3, {N}, {N}, {N // 2 + 1})")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _empty_phys(self):
+        N = self.N
+        return self._torch.empty((3, N, N, N), dtype=self.real, device="cuda")
+
+    def _empty_spec(self):
+        N = self.N
+        return self._torch.empty((3, N, N, N // 2 + 1), dtype=self.complex, device="cuda")
+
+    # -- API ------------------------------------------------------------------
+    def set_velocity(self, u):
+        _check(load_library().dns_set_velocity(self.handle, self._phys(u)), self.handle, "dns_set_velocity")
+        return self
+
+    def set_spectral(self, uh):
+        _check(load_library().dns_set_spectral(self.handle, self._spec(uh)), self.handle, "dns_set_spectral")
+        return self
+
+    def get_spectral(self, out=None):
+        out = self._empty_spec() if out is None else out
+        _check(load_library().dns_get_spectral(self.handle, self._spec(out)), self.handle, "dns_get_spectral")
+        return out
+
+    def get_velocity(self, out=None):
+        out = self._empty_phys() if out is None else out
+        _check(load_library().dns_get_velocity(self.handle, self._phys(out)), self.handle, "dns_get_velocity")
+        return out
+
+    def forward(self, u, out=None):
+        out = self._empty_spec() if out is None else out
+        _check(load_library().dns_forward(self.handle, self._phys(u), self._spec(out)), self.handle,
+               "dns_forward")
+        return out
+
+    def inverse(self, uh, out=None):
+        out = self._empty_phys() if out is None else out
+        _check(load_library().dns_inverse(self.handle, self._spec(uh), self._phys(out)), self.handle,
+               "dns_inverse")
+        return out
+
+    def step(self, n=1):
+        _check(load_library().dns_step(self.handle, int(n)), self.handle, "dns_step")
+        return self
+
+    def rhs(self, out=None):
+        out = self._empty_spec() if out is None else out
+        _check(load_library().dns_rhs(self.handle, self._spec(out)), self.handle, "dns_rhs")
+        return out
+
+    def diagnostics(self):
+        E, W = ctypes.c_double(), ctypes.c_double()
+        _check(load_library().dns_diagnostics(self.handle, ctypes.byref(E), ctypes.byref(W)), self.handle,
+               "dns_diagnostics")
+        return E.value, W.value
+
+    def energy(self):
+        E = ctypes.c_double()
+        _check(load_library().dns_energy(self.handle, ctypes.byref(E)), self.handle, "dns_energy")
+        return E.value
+
+    def enstrophy(self):
+        W = ctypes.c_double()
+        _check(load_library().dns_enstrophy(self.handle, ctypes.byref(W)), self.handle, "dns_enstrophy")
+        return W.value
+
+    def history(self):
+        cap = self.history_cap
+        E = (ctypes.c_double * max(cap, 1))()
+        W = (ctypes.c_double * max(cap, 1))()
+        n = ctypes.c_int()
+        _check(load_library().dns_history(self.handle, E, W, cap, ctypes.byref(n)), self.handle, "dns_history")
+        m = min(n.value, cap)
+        return list(E[:m]), list(W[:m])
+
+    def steps_taken(self):
+        s = ctypes.c_longlong()
+        _check(load_library().dns_steps_taken(self.handle, ctypes.byref(s)), self.handle, "dns_steps_taken")
+        return s.value
+
+    def synchronize(self):
+        _check(load_library().dns_synchronize(self.handle), self.handle, "dns_synchronize")
+
+    def profile_step(self, nsteps=1):
+        ms = (ctypes.c_float * 16)()
+        names = (ctypes.c_char_p * 16)()
+        n = ctypes.c_int()
+        _check(load_library().dns_profile_step(self.handle, int(nsteps), ms, names, 16, ctypes.byref(n)),
+               self.handle, "dns_profile_step")
+        return {names[i].decode(): float(ms[i]) for i in range(n.value)}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().dns_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

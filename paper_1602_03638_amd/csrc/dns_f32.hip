@@ -1,0 +1,6 @@
+// FP32 instantiation of every kernel for N = 8 .. 1024.
+#include "dns_impl.hpp"
+
+namespace dns {
+const Ops* ops_f32(int N) { return ops_for<float>(N); }
+}  // namespace dns

@@ -1,0 +1,531 @@
+// HIP kernels of one RK4 stage of the pseudo-spectral solver and of the
+// standalone 3D real transforms (templated on real type R and grid size N).
+//
+// One stage (Sec. 2 eq. NSfinal, Sec. 3.1 computeRHS) runs as five passes
+// over HBM-resident half-spectrum fields in the internal layout of
+// dns_common.hpp:
+//   1. k_xinv      u_hat -> 6 fields: inverse x FFT of u_hat and of
+//                  omega_hat = i k x u_hat formed on the fly
+//   2. k_yline     inverse y FFT of the 6 fields (in place)
+//      k_yline_nyq same for the kz = N/2 plane
+//   3. k_zcross    per (x, y) line: 6 inverse real z FFTs, u x omega in
+//                  registers, 3 forward real z FFTs; physical fields never
+//                  leave the chip
+//   4. k_yline     forward y FFT of the 3 fields (+ k_yline_nyq)
+//   5. k_xrhs      forward x FFT, dealias mask, pressure projection,
+//                  viscous term and the RK4 stage update (+ diagnostics)
+#pragma once
+
+#include "fft_device.hpp"
+
+namespace dns {
+
+__device__ __forceinline__ int kfreq(int i, int n) { return i < n / 2 ? i : i - n; }
+
+// Column c of the x pass: c < N*N/2 is (iy, iz) = (c / (N/2), c % (N/2)) of
+// the main block; c >= N*N/2 is iy = c - N*N/2 of the Nyquist plane.
+template <int N> struct XCol {
+    size_t base;   // offset of row 0 in a field
+    size_t rs;     // offset between rows (consecutive ix)
+    int ky, kz;
+    __device__ __forceinline__ XCol(int c) {
+        constexpr int HC = N * (N / 2);
+        if (c < HC) {
+            base = (size_t)c;
+            rs = (size_t)HC;
+            ky = kfreq(c / (N / 2), N);
+            kz = c % (N / 2);
+        } else {
+            const int iy = c - HC;
+            base = main_size(N) + (size_t)iy;
+            rs = (size_t)N;
+            ky = kfreq(iy, N);
+            kz = N / 2;
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Pass 1: inverse x transform of u_hat (3 fields at U) and, when CURL, of
+// omega_hat = i k x u_hat (Sec. 3.1 Curl listing):
+//   omega_x = i (ky w - kz v), omega_y = i (kz u - kx w), omega_z = i (kx v - ky u)
+// Output fields at W: u, v, w, omega_x, omega_y, omega_z (CURL) or u, v, w.
+// ---------------------------------------------------------------------------
+template <typename R, int N, bool CURL>
+__global__ __launch_bounds__((Cfg<R, N>::XTHREADS))
+void k_xinv(const cx<R>* __restrict__ U, cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
+    using K = Cfg<R, N>;
+    constexpr int T = K::TX, G = K::G, E = K::E;
+    constexpr size_t FS = field_size(N);
+    __shared__ cx<R> lds[T * N];
+    const int t = threadIdx.x % T, g = threadIdx.x / T;
+    const XCol<N> col(blockIdx.x * T + t);
+
+    cx<R> u[3][E];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int m = 0; m < E; ++m) u[c][m] = U[c * FS + col.base + (size_t)(g + m * G) * col.rs];
+
+    constexpr int NF = CURL ? 6 : 3;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        cx<R> a[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const R kx = (R)kfreq(g + m * G, N), ky = (R)col.ky, kz = (R)col.kz;
+            if (f < 3) {
+                a[m] = u[f][m];
+            } else if (f == 3) {
+                a[m] = cmuli<R>(csub<R>(cscale<R>(u[2][m], ky), cscale<R>(u[1][m], kz)));
+            } else if (f == 4) {
+                a[m] = cmuli<R>(csub<R>(cscale<R>(u[0][m], kz), cscale<R>(u[2][m], kx)));
+            } else {
+                a[m] = cmuli<R>(csub<R>(cscale<R>(u[1][m], kx), cscale<R>(u[0][m], ky)));
+            }
+        }
+        fft_line<R, N, E, +1>(a, lds + t, T, tw, g);
+#pragma unroll
+        for (int m = 0; m < E; ++m) W[f * FS + col.base + (size_t)(g + m * G) * col.rs] = a[m];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2/4: y transform (direction DIR) of NF fields, in place, main block.
+// Workgroup = TY consecutive iz of one ix; rows iy have stride N/2.
+// ---------------------------------------------------------------------------
+template <typename R, int N, int DIR, int NF>
+__global__ __launch_bounds__((Cfg<R, N>::YTHREADS))
+void k_yline(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
+    using K = Cfg<R, N>;
+    constexpr int T = K::TY, G = K::G, E = K::E;
+    constexpr size_t FS = field_size(N);
+    constexpr int ZT = (N / 2) / T;          // tiles per ix
+    __shared__ cx<R> lds[T * N];
+    const int t = threadIdx.x % T, g = threadIdx.x / T;
+    const int ix = blockIdx.x / ZT;
+    const int iz = (blockIdx.x % ZT) * T + t;
+    const size_t base = (size_t)ix * (N * (N / 2)) + iz;
+    constexpr size_t rs = N / 2;
+#pragma unroll 1
+    for (int f = 0; f < NF; ++f) {
+        cx<R> a[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) a[m] = W[f * FS + base + (size_t)(g + m * G) * rs];
+        fft_line<R, N, E, DIR>(a, lds + t, T, tw, g);
+#pragma unroll
+        for (int m = 0; m < E; ++m) W[f * FS + base + (size_t)(g + m * G) * rs] = a[m];
+    }
+}
+
+// y transform of the Nyquist plane (kz = N/2): line ix is contiguous.
+template <typename R, int N, int DIR, int NF>
+__global__ __launch_bounds__((Cfg<R, N>::NYTHREADS))
+void k_yline_nyq(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
+    using K = Cfg<R, N>;
+    constexpr int L = K::LY, G = K::G, E = K::E;
+    constexpr size_t FS = field_size(N);
+    __shared__ cx<R> lds[L * N];
+    const int g = threadIdx.x % G, l = threadIdx.x / G;
+    const int ix = blockIdx.x * L + l;
+    const size_t base = main_size(N) + (size_t)ix * N;
+#pragma unroll 1
+    for (int f = 0; f < NF; ++f) {
+        cx<R> a[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) a[m] = W[f * FS + base + g + m * G];
+        fft_line<R, N, E, DIR>(a, lds + l * N, 1, tw, g);
+#pragma unroll
+        for (int m = 0; m < E; ++m) W[f * FS + base + g + m * G] = a[m];
+    }
+}
+
+// Load element k (0 <= k < N) of the Hermitian extension of a half-spectrum
+// z line: X_k for k <= N/2, conj(X_{N-k}) above; the imaginary parts of
+// X_0 and X_{N/2} are dropped (inverse real transform semantics).
+template <typename R, int N>
+__device__ __forceinline__ cx<R> zline_load(const cx<R>* __restrict__ F, size_t line, int k) {
+    if (k < N / 2) {
+        cx<R> a = F[line * (N / 2) + k];
+        if (k == 0) a.y = R(0);
+        return a;
+    } else if (k == N / 2) {
+        cx<R> a = F[main_size(N) + line];
+        a.y = R(0);
+        return a;
+    } else {
+        return cconj<R>(F[line * (N / 2) + (N - k)]);
+    }
+}
+
+// Two Hermitian half-spectrum lines X, Y packed as Z = X + i Y: the inverse
+// transform of Z is x + i y with x, y the two real inverse transforms.
+template <typename R, int N>
+__device__ __forceinline__ cx<R> zpair_load(const cx<R>* __restrict__ FX, const cx<R>* __restrict__ FY,
+                                             size_t line, int k) {
+    const cx<R> x = zline_load<R, N>(FX, line, k);
+    const cx<R> y = zline_load<R, N>(FY, line, k);
+    return {x.x - y.y, x.y + y.x};
+}
+
+// Unpack the forward transform P of p = a + i b (a, b real lines) into the
+// half spectra of a and b at wavenumber k (0 <= k <= N/2):
+//   A_k = (P_k + conj P_{N-k}) / 2,  B_k = (P_k - conj P_{N-k}) / (2 i).
+template <typename R>
+__device__ __forceinline__ void zsplit(cx<R> pk, cx<R> pnk, cx<R>& A, cx<R>& B) {
+    const R h = R(0.5);
+    A = {(pk.x + pnk.x) * h, (pk.y - pnk.y) * h};
+    B = {(pk.y + pnk.y) * h, (pnk.x - pk.x) * h};
+}
+
+// ---------------------------------------------------------------------------
+// Pass 3: per (x, y) line (eq. curl_convection, Sec. 3.4 cross product):
+// inverse real z transforms of the six fields (u, v, w, omega) paired into
+// three complex transforms, c = (u x omega) / N^6 in registers, forward real
+// z transforms of c paired as (c0 + i c1) and (c2 + 0 i).  Writes the half
+// spectra of c into fields 0..2 of W (in place: a workgroup owns its lines).
+// scale = N^-6 (exact power of two) restores the inverse transforms' 1/N^3.
+// ---------------------------------------------------------------------------
+template <typename R, int N>
+__global__ __launch_bounds__((Cfg<R, N>::ZTHREADS))
+void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale) {
+    using K = Cfg<R, N>;
+    constexpr int L = K::LZ, G = K::G, E = K::E;
+    constexpr size_t FS = field_size(N);
+    __shared__ cx<R> lds[L * N];
+    const int g = threadIdx.x % G, l = threadIdx.x / G;
+    const size_t line = (size_t)blockIdx.x * L + l;
+    cx<R>* my = lds + l * N;
+
+    cx<R> z[3][E];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            z[p][m] = zpair_load<R, N>(W + (2 * p) * FS, W + (2 * p + 1) * FS, line, g + m * G);
+        fft_line<R, N, E, +1>(z[p], my, 1, tw, g);
+    }
+    // z[0] = (u, v), z[1] = (w, omega_x), z[2] = (omega_y, omega_z)
+    cx<R> P[E], Q[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const R u = z[0][m].x, v = z[0][m].y, w = z[1][m].x;
+        const R ox = z[1][m].y, oy = z[2][m].x, oz = z[2][m].y;
+        P[m] = {(v * oz - w * oy) * scale, (w * ox - u * oz) * scale};
+        Q[m] = {(u * oy - v * ox) * scale, R(0)};
+    }
+    fft_line<R, N, E, -1>(Q, my, 1, tw, g);
+    fft_line<R, N, E, -1>(P, my, 1, tw, g);
+    // c2: Q_k is its half spectrum directly
+#pragma unroll
+    for (int m = 0; m < E / 2; ++m) W[2 * FS + line * (N / 2) + g + m * G] = Q[m];
+    if (g == 0) W[2 * FS + main_size(N) + line] = Q[E / 2];
+    // c0, c1: unpack P through LDS (needs P_{N-k})
+#pragma unroll
+    for (int m = 0; m < E; ++m) my[g + m * G] = P[m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E / 2; ++m) {
+        const int k = g + m * G;
+        cx<R> A, B;
+        zsplit<R>(my[k], my[(N - k) & (N - 1)], A, B);
+        W[0 * FS + line * (N / 2) + k] = A;
+        W[1 * FS + line * (N / 2) + k] = B;
+    }
+    if (g == 0) {
+        cx<R> A, B;
+        zsplit<R>(my[N / 2], my[N / 2], A, B);
+        W[0 * FS + main_size(N) + line] = A;
+        W[1 * FS + main_size(N) + line] = B;
+    }
+}
+
+// Forward real z transforms of three physical fields u (3, N, N, N) into the
+// half spectra of fields 0..2 of W (first step of the forward 3D transform).
+template <typename R, int N>
+__global__ __launch_bounds__((Cfg<R, N>::ZTHREADS))
+void k_zr2c(const R* __restrict__ u, cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
+    using K = Cfg<R, N>;
+    constexpr int L = K::LZ, G = K::G, E = K::E;
+    constexpr size_t FS = field_size(N);
+    constexpr size_t PS = (size_t)N * N * N;
+    __shared__ cx<R> lds[L * N];
+    const int g = threadIdx.x % G, l = threadIdx.x / G;
+    const size_t line = (size_t)blockIdx.x * L + l;
+    cx<R>* my = lds + l * N;
+    cx<R> P[E], Q[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const size_t o = line * N + g + m * G;
+        P[m] = {u[o], u[PS + o]};
+        Q[m] = {u[2 * PS + o], R(0)};
+    }
+    fft_line<R, N, E, -1>(Q, my, 1, tw, g);
+    fft_line<R, N, E, -1>(P, my, 1, tw, g);
+#pragma unroll
+    for (int m = 0; m < E / 2; ++m) W[2 * FS + line * (N / 2) + g + m * G] = Q[m];
+    if (g == 0) W[2 * FS + main_size(N) + line] = Q[E / 2];
+#pragma unroll
+    for (int m = 0; m < E; ++m) my[g + m * G] = P[m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E / 2; ++m) {
+        const int k = g + m * G;
+        cx<R> A, B;
+        zsplit<R>(my[k], my[(N - k) & (N - 1)], A, B);
+        W[0 * FS + line * (N / 2) + k] = A;
+        W[1 * FS + line * (N / 2) + k] = B;
+    }
+    if (g == 0) {
+        cx<R> A, B;
+        zsplit<R>(my[N / 2], my[N / 2], A, B);
+        W[0 * FS + main_size(N) + line] = A;
+        W[1 * FS + main_size(N) + line] = B;
+    }
+}
+
+// Inverse real z transforms of fields 0..2 of W into physical u (3, N, N, N),
+// scaled by `scale` (N^-3 for the normalised inverse).
+template <typename R, int N>
+__global__ __launch_bounds__((Cfg<R, N>::ZTHREADS))
+void k_zc2r(const cx<R>* __restrict__ W, R* __restrict__ u, const cx<R>* __restrict__ tw, R scale) {
+    using K = Cfg<R, N>;
+    constexpr int L = K::LZ, G = K::G, E = K::E;
+    constexpr size_t FS = field_size(N);
+    constexpr size_t PS = (size_t)N * N * N;
+    __shared__ cx<R> lds[L * N];
+    const int g = threadIdx.x % G, l = threadIdx.x / G;
+    const size_t line = (size_t)blockIdx.x * L + l;
+    cx<R>* my = lds + l * N;
+    cx<R> a[E], b[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        a[m] = zpair_load<R, N>(W, W + FS, line, g + m * G);
+        b[m] = zline_load<R, N>(W + 2 * FS, line, g + m * G);
+    }
+    fft_line<R, N, E, +1>(a, my, 1, tw, g);
+    fft_line<R, N, E, +1>(b, my, 1, tw, g);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const size_t o = line * N + g + m * G;
+        u[o] = a[m].x * scale;
+        u[PS + o] = a[m].y * scale;
+        u[2 * PS + o] = b[m].x * scale;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 5: forward x transform of N_hat = F(u x omega) (fields 0..2 of W),
+// then per mode (Sec. 3.1 computeRHS; eqs. mod_pressure, NSfinal):
+//   N_hat *= dealias;  P_hat = k . N_hat / |k|^2 (0 at k = 0);
+//   N_hat -= k P_hat;  R = N_hat - nu |k|^2 u_s
+// and the classic RK4 stage update (Appendix solver):
+//   stage 0: U1 = U0 + a0 dt R,  Us = U0 + b0 dt R     (u_s = U0)
+//   stage 1,2: U1 += a_s dt R,    Us = U0 + b_s dt R    (u_s = Us)
+//   stage 3: U0 = U1 + a3 dt R                          (u_s = Us)
+//   stage -1: U1 = R (right-hand side only; u_s = U0)
+// At stage 3 with diag != nullptr, each workgroup also writes partial sums
+// of w |u_hat|^2 and w |k x u_hat|^2 of the new state (w = 1 on the kz = 0
+// and kz = N/2 planes, 2 elsewhere) to diag[2 blockIdx], diag[2 blockIdx + 1].
+// ---------------------------------------------------------------------------
+template <typename R, int N>
+__global__ __launch_bounds__((Cfg<R, N>::XTHREADS))
+void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
+            cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa) {
+    using K = Cfg<R, N>;
+    constexpr int T = K::TX, G = K::G, E = K::E;
+    constexpr int NT = K::XTHREADS;
+    constexpr size_t FS = field_size(N);
+    __shared__ cx<R> lds[T * N];
+    __shared__ double red[2][NT];
+    const int t = threadIdx.x % T, g = threadIdx.x / T;
+    const XCol<N> col(blockIdx.x * T + t);
+
+    cx<R> nh[3][E];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) nh[f][m] = W[f * FS + col.base + (size_t)(g + m * G) * col.rs];
+        fft_line<R, N, E, -1>(nh[f], lds + t, T, tw, g);
+    }
+
+    const int ky = col.ky, kz = col.kz;
+    const int lim = sa.mask_lim;
+    const bool keep_yz = (3 * abs(ky) < lim) && (3 * abs(kz) < lim);
+    const R nu = (R)sa.nu, ca = (R)sa.ca, cb = (R)sa.cb;
+    double e_acc = 0.0, w_acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int kx = kfreq(g + m * G, N);
+        const size_t o = col.base + (size_t)(g + m * G) * col.rs;
+        const bool keep = keep_yz && (3 * abs(kx) < lim);
+        const int k2 = kx * kx + ky * ky + kz * kz;
+        cx<R> n0 = nh[0][m], n1 = nh[1][m], n2 = nh[2][m];
+        if (!keep) {
+            n0 = {R(0), R(0)}; n1 = n0; n2 = n0;
+        }
+        const R fx = (R)kx, fy = (R)ky, fz = (R)kz;
+        const R inv = k2 > 0 ? R(1) / (R)k2 : R(0);
+        // P_hat = sum_i N_i k_i / |k|^2
+        const cx<R> P = {(n0.x * fx + n1.x * fy + n2.x * fz) * inv, (n0.y * fx + n1.y * fy + n2.y * fz) * inv};
+        n0 = csub<R>(n0, cscale<R>(P, fx));
+        n1 = csub<R>(n1, cscale<R>(P, fy));
+        n2 = csub<R>(n2, cscale<R>(P, fz));
+        const R visc = nu * (R)k2;
+        cx<R> s0, s1, s2;
+        if (sa.stage <= 0) {
+            s0 = U0[o]; s1 = U0[FS + o]; s2 = U0[2 * FS + o];
+        } else {
+            s0 = Us[o]; s1 = Us[FS + o]; s2 = Us[2 * FS + o];
+        }
+        const cx<R> r0 = csub<R>(n0, cscale<R>(s0, visc));
+        const cx<R> r1 = csub<R>(n1, cscale<R>(s1, visc));
+        const cx<R> r2 = csub<R>(n2, cscale<R>(s2, visc));
+        if (sa.stage < 0) {
+            U1[o] = r0; U1[FS + o] = r1; U1[2 * FS + o] = r2;
+        } else if (sa.stage == 0) {
+            U1[o] = cadd<R>(s0, cscale<R>(r0, ca));
+            U1[FS + o] = cadd<R>(s1, cscale<R>(r1, ca));
+            U1[2 * FS + o] = cadd<R>(s2, cscale<R>(r2, ca));
+            Us[o] = cadd<R>(s0, cscale<R>(r0, cb));
+            Us[FS + o] = cadd<R>(s1, cscale<R>(r1, cb));
+            Us[2 * FS + o] = cadd<R>(s2, cscale<R>(r2, cb));
+        } else if (sa.stage < 3) {
+            const cx<R> a0 = U0[o], a1 = U0[FS + o], a2 = U0[2 * FS + o];
+            const cx<R> b0 = U1[o], b1 = U1[FS + o], b2 = U1[2 * FS + o];
+            U1[o] = cadd<R>(b0, cscale<R>(r0, ca));
+            U1[FS + o] = cadd<R>(b1, cscale<R>(r1, ca));
+            U1[2 * FS + o] = cadd<R>(b2, cscale<R>(r2, ca));
+            Us[o] = cadd<R>(a0, cscale<R>(r0, cb));
+            Us[FS + o] = cadd<R>(a1, cscale<R>(r1, cb));
+            Us[2 * FS + o] = cadd<R>(a2, cscale<R>(r2, cb));
+        } else {
+            const cx<R> b0 = U1[o], b1 = U1[FS + o], b2 = U1[2 * FS + o];
+            const cx<R> v0 = cadd<R>(b0, cscale<R>(r0, ca));
+            const cx<R> v1 = cadd<R>(b1, cscale<R>(r1, ca));
+            const cx<R> v2 = cadd<R>(b2, cscale<R>(r2, ca));
+            U0[o] = v0; U0[FS + o] = v1; U0[2 * FS + o] = v2;
+            if (sa.diag) {
+                const double wgt = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
+                const double x0 = v0.x, y0 = v0.y, x1 = v1.x, y1 = v1.y, x2 = v2.x, y2 = v2.y;
+                e_acc += wgt * (x0 * x0 + y0 * y0 + x1 * x1 + y1 * y1 + x2 * x2 + y2 * y2);
+                const double dx = kx, dy = ky, dz = kz;
+                const double cxr = dy * x2 - dz * x1, cxi = dy * y2 - dz * y1;
+                const double cyr = dz * x0 - dx * x2, cyi = dz * y0 - dx * y2;
+                const double czr = dx * x1 - dy * x0, czi = dx * y1 - dy * y0;
+                w_acc += wgt * (cxr * cxr + cxi * cxi + cyr * cyr + cyi * cyi + czr * czr + czi * czi);
+            }
+        }
+    }
+    if (sa.stage == 3 && sa.diag) {
+        // fixed-order tree reduction over the workgroup
+        red[0][threadIdx.x] = e_acc;
+        red[1][threadIdx.x] = w_acc;
+        __syncthreads();
+#pragma unroll 1
+        for (int s = NT / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) {
+                red[0][threadIdx.x] += red[0][threadIdx.x + s];
+                red[1][threadIdx.x] += red[1][threadIdx.x + s];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            sa.diag[2 * blockIdx.x] = red[0][0];
+            sa.diag[2 * blockIdx.x + 1] = red[1][0];
+        }
+    }
+}
+
+// Plain forward x transform: W fields 0..2 -> U fields 0..2 (last step of
+// the forward 3D transform).
+template <typename R, int N>
+__global__ __launch_bounds__((Cfg<R, N>::XTHREADS))
+void k_xfwd(const cx<R>* __restrict__ W, cx<R>* __restrict__ U, const cx<R>* __restrict__ tw) {
+    using K = Cfg<R, N>;
+    constexpr int T = K::TX, G = K::G, E = K::E;
+    constexpr size_t FS = field_size(N);
+    __shared__ cx<R> lds[T * N];
+    const int t = threadIdx.x % T, g = threadIdx.x / T;
+    const XCol<N> col(blockIdx.x * T + t);
+#pragma unroll 1
+    for (int f = 0; f < 3; ++f) {
+        cx<R> a[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) a[m] = W[f * FS + col.base + (size_t)(g + m * G) * col.rs];
+        fft_line<R, N, E, -1>(a, lds + t, T, tw, g);
+#pragma unroll
+        for (int m = 0; m < E; ++m) U[f * FS + col.base + (size_t)(g + m * G) * col.rs] = a[m];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Layout conversion between the external (3, N, N, N/2+1) array and the
+// internal split-Nyquist layout (one thread per complex value).
+// ---------------------------------------------------------------------------
+template <typename R, int N, bool TO_INTERNAL>
+__global__ __launch_bounds__(256)
+void k_layout(const cx<R>* __restrict__ src, cx<R>* __restrict__ dst, size_t total) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    constexpr size_t M = N / 2 + 1;
+    constexpr size_t FS = field_size(N);
+    const size_t c = i / ((size_t)N * N * M);
+    const size_t r = i - c * (size_t)N * N * M;
+    const size_t iz = r % M;
+    const size_t ixy = r / M;            // ix * N + iy
+    const size_t in = c * FS + (iz < N / 2 ? ixy * (N / 2) + iz : main_size(N) + ixy);
+    if (TO_INTERNAL) dst[in] = src[i];
+    else dst[i] = src[in];
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics of a state U: per-workgroup partial sums of w |u_hat|^2 and
+// w |k x u_hat|^2 over a fixed grid-stride assignment of modes, then one
+// workgroup sums the partials in fixed order: E = S_E / (2 N^6),
+// Omega = S_W / (2 N^6).  Deterministic for a given N and grid.
+// ---------------------------------------------------------------------------
+template <typename R, int N>
+__global__ __launch_bounds__(256)
+void k_diag_partial(const cx<R>* __restrict__ U, double* __restrict__ part) {
+    constexpr size_t FS = field_size(N);
+    __shared__ double red[2 * 4];
+    double e_acc = 0.0, w_acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < FS; i += (size_t)DIAG_BLOCKS * 256) {
+        int ix, iy, iz;
+        if (i < main_size(N)) {
+            iz = (int)(i % (N / 2));
+            iy = (int)((i / (N / 2)) % N);
+            ix = (int)(i / ((size_t)N * (N / 2)));
+        } else {
+            const size_t r = i - main_size(N);
+            iz = N / 2;
+            iy = (int)(r % N);
+            ix = (int)(r / N);
+        }
+        const double kx = kfreq(ix, N), ky = kfreq(iy, N), kz = iz;
+        const double wgt = (iz == 0 || iz == N / 2) ? 1.0 : 2.0;
+        const cx<R> a = U[i], b = U[FS + i], c = U[2 * FS + i];
+        const double x0 = a.x, y0 = a.y, x1 = b.x, y1 = b.y, x2 = c.x, y2 = c.y;
+        e_acc += wgt * (x0 * x0 + y0 * y0 + x1 * x1 + y1 * y1 + x2 * x2 + y2 * y2);
+        const double cxr = ky * x2 - kz * x1, cxi = ky * y2 - kz * y1;
+        const double cyr = kz * x0 - kx * x2, cyi = kz * y0 - kx * y2;
+        const double czr = kx * x1 - ky * x0, czi = kx * y1 - ky * y0;
+        w_acc += wgt * (cxr * cxr + cxi * cxi + cyr * cyr + cyi * cyi + czr * czr + czi * czi);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        e_acc += __shfl_down(e_acc, off, 64);
+        w_acc += __shfl_down(w_acc, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { red[2 * wave] = e_acc; red[2 * wave + 1] = w_acc; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double se = 0.0, sw = 0.0;
+        for (int i = 0; i < 4; ++i) { se += red[2 * i]; sw += red[2 * i + 1]; }
+        part[2 * blockIdx.x] = se;
+        part[2 * blockIdx.x + 1] = sw;
+    }
+}
+
+}  // namespace dns

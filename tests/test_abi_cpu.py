@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/dns.h declares, and rejects invalid arguments before
+touching the device."""
+import ctypes
+
+import pytest
+
+import paper_1602_03638_amd as dns
+from paper_1602_03638_amd import binding
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return dns.load_library()
+
+
+def test_exports_every_declared_function(lib):
+    names = dns.header_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_strerror_covers_status_codes(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.dns_strerror(code)
+    assert lib.dns_strerror(12345) == b"unknown status"
+
+
+def test_default_opts(lib):
+    o = dns.default_opts()
+    assert (o.dealias, o.diag_every, o.history_cap, o.use_graph) == (0, 0, 4096, 1)
+
+
+def test_state_bytes(lib):
+    # 15 half-spectrum fields of N*N*(N/2+1) complex values (+ a small table)
+    b = dns.state_bytes(512, dns.DNS_FP64)
+    field = 512 * 512 * 257 * 16
+    assert 15 * field <= b < 15 * field + 1 << 20
+    assert dns.state_bytes(512, dns.DNS_FP32) < b
+    assert dns.state_bytes(500, dns.DNS_FP64) == 0
+    assert dns.state_bytes(2048, dns.DNS_FP64) == 0
+    assert dns.state_bytes(64, 7) == 0
+
+
+@pytest.mark.parametrize("args", [
+    (6, 0.01, 0.01, 0),        # N not a power of two >= 8
+    (12, 0.01, 0.01, 0),
+    (2048, 0.01, 0.01, 0),     # N too large
+    (32, -1.0, 0.01, 0),       # negative viscosity
+    (32, float("nan"), 0.01, 0),
+    (32, 0.01, 0.0, 0),        # non-positive dt
+    (32, 0.01, float("inf"), 0),
+    (32, 0.01, 0.01, 2),       # bad dtype
+])
+def test_create_rejects_invalid_arguments(lib, args):
+    h = ctypes.c_void_p(123)
+    st = lib.dns_create(*args, ctypes.byref(h))
+    assert st == dns.DNS_E_INVAL
+    assert not h.value
+
+
+def test_create_rejects_bad_opts(lib):
+    o = dns.default_opts()
+    o.dealias = 5
+    h = ctypes.c_void_p()
+    assert lib.dns_create_ex(32, 0.01, 0.01, 0, ctypes.byref(o), None, ctypes.byref(h)) == dns.DNS_E_INVAL
+    o = dns.default_opts()
+    o.diag_every = -1
+    assert lib.dns_create_ex(32, 0.01, 0.01, 0, ctypes.byref(o), None, ctypes.byref(h)) == dns.DNS_E_INVAL
+
+
+def test_null_handles_are_rejected(lib):
+    assert lib.dns_create(32, 0.01, 0.01, 0, None) == dns.DNS_E_INVAL
+    assert lib.dns_destroy(None) == dns.DNS_OK
+    assert lib.dns_step(None, 1) == dns.DNS_E_INVAL
+    assert lib.dns_set_velocity(None, None) == dns.DNS_E_INVAL
+    assert lib.dns_energy(None, None) == dns.DNS_E_INVAL
+    assert lib.dns_synchronize(None) == dns.DNS_E_INVAL
+    assert lib.dns_last_error(None) == b""
+
+
+def test_binding_signatures_cover_header():
+    lib = dns.load_library()
+    for n in dns.header_functions():
+        assert getattr(lib, n).argtypes is not None or n == "dns_default_opts", n
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(RuntimeError, match="build"):
+        binding.load_library(str(tmp_path / "nope.so"))

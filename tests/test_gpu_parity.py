@@ -1,0 +1,204 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+FP64 transforms and right-hand sides agree with the oracle to rounding
+(relative L2 <= 1e-13); after 10 RK4 steps of the 32^3 Taylor-Green case
+the velocity agrees to relative L2 <= 1e-12 and the energy and enstrophy to
+1e-12 relative; FP32 runs agree in energy to 1e-5 relative.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import note, rel_l2, spectral_rel_l2, to_dev, to_host
+from oracle import ic, spectral
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL_F64 = 1e-13      # one transform or one RHS evaluation, relative L2
+TOL_F32 = 2e-6
+TOL_STEP10 = 1e-12   # velocity after 10 FP64 RK4 steps, relative L2
+
+
+def _solver(N, nu=0.01, dt=0.01, dtype="f64", **kw):
+    from paper_1602_03638_amd import Solver
+    return Solver(N, nu, dt, dtype=dtype, **kw)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("N", [8, 16, 32, 64, 128])
+def test_forward_transform(N, dtype):
+    note(f"forward N={N} {dtype}")
+    u = workloads.random_physical(N, seed=100 + N)
+    s = _solver(N, dtype=dtype)
+    got = to_host(s.forward(to_dev(u, dtype)))
+    ref = spectral.dft3(u)
+    assert rel_l2(got, ref) <= (TOL_F64 if dtype == "f64" else TOL_F32)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("N", [8, 16, 32, 64, 128])
+def test_inverse_transform_non_hermitian_input(N, dtype):
+    """The inverse real transform ignores Im of the kz = 0 and N/2 bins."""
+    note(f"inverse N={N} {dtype}")
+    h = workloads.random_half_spectrum(N, seed=200 + N)
+    s = _solver(N, dtype=dtype)
+    got = to_host(s.inverse(to_dev(h, dtype)))
+    ref = spectral.idft3(h)
+    assert rel_l2(got, ref) <= (TOL_F64 if dtype == "f64" else TOL_F32)
+
+
+@pytest.mark.parametrize("N", [16, 64])
+def test_set_velocity_equals_forward_and_spectral_roundtrip(N):
+    note(f"set/get N={N}")
+    u = workloads.random_physical(N, seed=7)
+    s = _solver(N)
+    du = to_dev(u, "f64")
+    a = to_host(s.set_velocity(du).get_spectral())
+    b = to_host(s.forward(du))
+    assert np.array_equal(a, b)
+    h = workloads.random_half_spectrum(N, seed=8)
+    back = to_host(s.set_spectral(to_dev(h, "f64")).get_spectral())
+    assert np.array_equal(back, h)
+    v = to_host(s.set_velocity(du).get_velocity())
+    assert rel_l2(v, u) <= TOL_F64
+
+
+def _rhs_input(N, seed):
+    """Random solenoidal field plus broadband noise (all modes, including
+    the Nyquist planes and modes outside the dealias mask)."""
+    uh = ic.random_isotropic(N, seed, k0=3.0)
+    return uh + 0.05 * np.abs(uh).max() * spectral.dft3(workloads.random_physical(N, seed + 1)) / N ** 1.5
+
+
+@pytest.mark.parametrize("dealias", ["text", "appendix"])
+@pytest.mark.parametrize("N", [8, 16, 32, 64])
+def test_rhs_matches_oracle(N, dealias):
+    note(f"rhs N={N} {dealias}")
+    nu = 0.0137
+    uh = _rhs_input(N, seed=30 + N)
+    s = _solver(N, nu=nu, dealias=dealias)
+    got = to_host(s.set_spectral(to_dev(uh, "f64")).rhs())
+    ref = spectral.rhs(uh, nu, spectral.wavenumber_mesh(N), spectral.dealias_mask(N, dealias))
+    assert spectral_rel_l2(got, ref) <= TOL_F64
+
+
+@pytest.mark.parametrize("N", [16, 32])
+def test_rhs_fp32(N):
+    note(f"rhs fp32 N={N}")
+    nu = 0.0137
+    uh = _rhs_input(N, seed=50 + N)
+    s = _solver(N, nu=nu, dtype="f32")
+    got = to_host(s.set_spectral(to_dev(uh, "f32")).rhs())
+    ref = spectral.rhs(uh.astype(np.complex64).astype(np.complex128), nu, spectral.wavenumber_mesh(N),
+                       spectral.dealias_mask(N))
+    assert spectral_rel_l2(got, ref) <= 2e-5
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_taylor_green_32_ten_steps(use_graph):
+    """Taylor-Green 32^3 FP64, nu = 0.01, dt = 0.01, 10 RK4 steps."""
+    note(f"tg32 10 steps graph={use_graph}")
+    N, nu, dt = 32, 0.01, 0.01
+    u0 = workloads.taylor_green(N)
+    orc = spectral.Solver(N, nu, dt).set_velocity(u0).step(10)
+    s = _solver(N, nu, dt, use_graph=use_graph)
+    s.set_velocity(to_dev(u0, "f64")).step(10)
+    u = to_host(s.get_velocity())
+    assert rel_l2(u, orc.get_velocity()) <= TOL_STEP10
+    uh = to_host(s.get_spectral())
+    assert spectral_rel_l2(uh, orc.uh) <= TOL_STEP10
+    E, W = s.diagnostics()
+    assert abs(E - orc.energy()) / orc.energy() <= 1e-12
+    assert abs(W - orc.enstrophy()) / orc.enstrophy() <= 1e-12
+
+
+def test_random_isotropic_steps_fp64():
+    """A broadband nonlinear flow (random solenoidal IC), 5 steps, 32^3."""
+    note("iso32 5 steps")
+    N, nu, dt = 32, 0.01, 0.005
+    uh0 = ic.random_isotropic(N, seed=1000)
+    orc = spectral.Solver(N, nu, dt).set_spectral(uh0).step(5)
+    s = _solver(N, nu, dt).set_spectral(to_dev(uh0, "f64")).step(5)
+    assert spectral_rel_l2(to_host(s.get_spectral()), orc.uh) <= TOL_STEP10
+
+
+def test_history_every_step():
+    note("history tg32")
+    N, nu, dt = 32, 0.01, 0.01
+    u0 = workloads.taylor_green(N)
+    E_ref, W_ref = [], []
+    spectral.Solver(N, nu, dt).set_velocity(u0).step(
+        10, callback=lambda o: (E_ref.append(o.energy()), W_ref.append(o.enstrophy())))
+    s = _solver(N, nu, dt, diag_every=1).set_velocity(to_dev(u0, "f64")).step(10)
+    E, W = s.history()
+    assert len(E) == 10
+    assert np.max(np.abs(np.array(E) - E_ref) / np.array(E_ref)) <= 1e-12
+    assert np.max(np.abs(np.array(W) - W_ref) / np.array(W_ref)) <= 1e-12
+
+
+def test_appendix_worked_example_on_gpu():
+    """The paper's Appendix run (N = 128, FP64, 10 steps): printed energy."""
+    note("appendix tg128")
+    with open(os.path.join(GOLDEN, "appendix_tg128.json")) as f:
+        g = json.load(f)
+    N = g["N"]
+    s = _solver(N, g["nu"], g["dt"], dealias=g["dealias"])
+    s.set_velocity(to_dev(workloads.taylor_green(N), "f64")).step(g["steps"])
+    u = to_host(s.get_velocity())
+    E_phys = 0.5 * np.sum(u * u) / N ** 3
+    assert abs(E_phys - g["energy_printed"]) <= 5e-13
+    assert abs(s.energy() - g["energy_printed"]) <= 5e-13
+
+
+@pytest.mark.parametrize("N", [32, 64])
+def test_fp32_energy_error(N):
+    note(f"fp32 tg N={N}")
+    nu, dt = 0.01, 0.01
+    u0 = workloads.taylor_green(N)
+    orc = spectral.Solver(N, nu, dt).set_velocity(u0).step(10)
+    s = _solver(N, nu, dt, dtype="f32").set_velocity(to_dev(u0, "f32")).step(10)
+    E, W = s.diagnostics()
+    assert abs(E - orc.energy()) / orc.energy() <= 1e-5
+    assert abs(W - orc.enstrophy()) / orc.enstrophy() <= 1e-5
+    assert rel_l2(to_host(s.get_velocity()), orc.get_velocity()) <= 1e-5
+
+
+def test_deterministic_and_resumable():
+    note("determinism/resume")
+    N, nu, dt = 32, 0.01, 0.005
+    uh0 = ic.random_isotropic(N, seed=1001)
+    a = to_host(_solver(N, nu, dt).set_spectral(to_dev(uh0, "f64")).step(6).get_spectral())
+    b = to_host(_solver(N, nu, dt).set_spectral(to_dev(uh0, "f64")).step(6).get_spectral())
+    assert np.array_equal(a, b)
+    s1 = _solver(N, nu, dt).set_spectral(to_dev(uh0, "f64")).step(3)
+    mid = s1.get_spectral()
+    c = to_host(_solver(N, nu, dt).set_spectral(mid).step(3).get_spectral())
+    assert np.array_equal(a, c)
+
+
+def test_state_errors():
+    from paper_1602_03638_amd import DNS_E_STATE, DnsError
+    note("state errors")
+    s = _solver(16)
+    with pytest.raises(DnsError) as e:
+        s.step(1)
+    assert e.value.status == DNS_E_STATE
+    with pytest.raises(DnsError):
+        s.energy()
+    with pytest.raises(ValueError):
+        s.set_velocity(to_dev(workloads.random_physical(8, 1), "f64"))
+
+
+def test_nonfinite_energy_reported():
+    from paper_1602_03638_amd import DNS_E_NONFINITE, DnsError
+    note("nonfinite")
+    h = workloads.random_half_spectrum(16, seed=3)
+    h[0, 1, 1, 1] = np.nan
+    s = _solver(16).set_spectral(to_dev(h, "f64"))
+    with pytest.raises(DnsError) as e:
+        s.energy()
+    assert e.value.status == DNS_E_NONFINITE
