@@ -96,6 +96,54 @@ def cpu_baseline(N):
                       "RHS elementwise work excluded"}
 
 
+def sweep(N, dtype, reps=2):
+    """Time every tile-shape variant of every pass (HIP events, mean of the
+    launches of `reps` steps) and the autotuner's choice."""
+    import torch
+    import workloads
+    from paper_1602_03638_amd import Solver
+
+    u0 = torch.from_numpy(workloads.taylor_green(N)).to(torch.float64 if dtype == "f64" else torch.float32)
+    s = Solver(N, NU, DT, dtype=dtype).set_velocity(u0.cuda().contiguous())
+    base = s.plan()
+    out = {"N": N, "dtype": dtype, "default_plan": base, "passes": {}}
+    for p, widths in s.plan_variants().items():
+        res = {}
+        for w in widths:
+            plan = dict(base)
+            plan[p] = w
+            if p in ("yinv6", "yfwd3"):
+                plan["yinv6"] = plan["yfwd3"] = w
+            s.set_plan(plan)
+            res[w] = round(s.profile_step(reps)[p], 4)
+        out["passes"][p] = res
+    s.set_plan(base)
+    out["autotuned_plan"] = s.autotune()
+    out["autotuned_ms"] = {k: round(v, 4) for k, v in s.profile_step(reps).items()}
+    s.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def calibrate_copy(gib, reps=5):
+    """Plain device-to-device copy of a known size: its HBM counters and
+    bandwidth calibrate the per-kernel counter readings."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "ms": ms,
+                      "GBps_read_plus_write": 2 * n * 8 / (ms * 1e-3) / 1e9}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,12 +153,26 @@ def main(argv=None):
     ap.add_argument("--prof-steps", type=int, default=2)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--sweep", action="store_true", help="only time every kernel variant at --N")
+    ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
+                    help="only time a plain device copy of this many GiB (counter calibration)")
     a = ap.parse_args(argv)
+    if a.calibrate_copy > 0:
+        return calibrate_copy(a.calibrate_copy)
+    if a.sweep:
+        for dt in ("f64", "f32"):
+            sweep(a.N, dt)
+        return 0
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(the slab decomposition over several GPUs is described, not built)", file=sys.stderr)
         return 2
 
+    if a.no_fp64:
+        f32 = run_gpu(a.N, "f32", a.steps, a.warmup, a.prof_steps)
+        print(json.dumps({"fp32": f32, "N": a.N, "steps": a.steps}), flush=True)
+        return 0
     f64 = run_gpu(a.N, "f64", a.steps, a.warmup, a.prof_steps)
     f32 = None if a.no_fp32 else run_gpu(a.N, "f32", a.steps, a.warmup, a.prof_steps)
 

@@ -72,6 +72,7 @@ typedef struct dns_opts {
     int history_cap;  /* capacity of the history buffer in steps; default 4096 */
     int use_graph;    /* 1 = replay each RK4 step as one captured HIP graph
                          (default), 0 = launch kernels one by one */
+    int autotune;     /* 1 = run dns_autotune at creation; default 0 */
 } dns_opts;
 
 typedef struct dns_ctx dns_t;
@@ -158,6 +159,24 @@ int dns_profile_step(dns_t* ctx, int nsteps, float* ms, const char** names, int 
  * (3, N, N, N) -> (3, N, N, N/2+1) and inverse complex-to-real. */
 int dns_forward(dns_t* ctx, const void* u_dev, void* uhat_dev);
 int dns_inverse(dns_t* ctx, const void* uhat_dev, void* u_dev);
+
+/* Execution plan.  Each of the five kernels of an RK4 stage (in launch
+ * order: inverse x pass with curl, inverse y pass, fused z pass, forward y
+ * pass, forward x pass with the RHS and RK4 update) has several variants
+ * that differ only in how many FFT lines share a workgroup (the "width");
+ * every variant performs the same arithmetic per line, so results are
+ * bitwise identical whichever is chosen.
+ *
+ * dns_autotune times every variant on the context's own buffers (reps
+ * launches each, 0 = 3) and keeps the fastest; the velocity state is
+ * preserved.  dns_get_plan writes the chosen widths (5 entries);
+ * dns_set_plan selects variants by width (DNS_E_INVAL if a width does not
+ * exist for this N and dtype); dns_plan_variants lists the widths available
+ * for one kernel (pass index 0..4). */
+int dns_autotune(dns_t* ctx, int reps);
+int dns_get_plan(const dns_t* ctx, int* widths, int max, int* count);
+int dns_set_plan(dns_t* ctx, const int* widths, int n);
+int dns_plan_variants(const dns_t* ctx, int pass, int* widths, int max, int* count);
 
 const char* dns_strerror(int status);
 const char* dns_last_error(const dns_t* ctx);

@@ -188,6 +188,23 @@ def idft3(uh):
     return _apply_z(Cz.T, np.ascontiguousarray(a.real)) + _apply_z(Sz.T, np.ascontiguousarray(a.imag))  # z (c2r)
 
 
+def dft3_mode(u, ix, iy, iz):
+    """One coefficient of dft3(u) by the definition, for spot checks of
+    transforms too large to evaluate whole: u_hat[ix, iy, iz] =
+    sum_{x,y,z} u[x,y,z] exp(-2 pi i ((ix x + iy y + iz z) mod N) / N),
+    summed over z, then y, then x with exact reduced twiddles."""
+    u = np.asarray(u, dtype=np.float64)
+    N = u.shape[-1]
+    roots = _unit_root_table(N)
+    n = np.arange(N, dtype=np.int64)
+    ez = roots[(iz * n) % N]
+    ey = roots[(iy * n) % N]
+    ex = roots[(ix * n) % N]
+    a = u @ ez           # (..., N, N)
+    b = a @ ey           # (..., N)
+    return b @ ex
+
+
 # ----------------------------------------------------------------------------
 # The right-hand side (Sec. 2 eqs. NSf, mod_pressure, NSfinal, curl_convection;
 # Sec. 3.1 Curl, Cross and computeRHS listings)

@@ -35,7 +35,7 @@ class DnsError(RuntimeError):
 
 class dns_opts(ctypes.Structure):
     _fields_ = [("dealias", ctypes.c_int), ("diag_every", ctypes.c_int),
-                ("history_cap", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("history_cap", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int)]
 
 
 _lib = None
@@ -79,6 +79,10 @@ def load_library(path=LIB_PATH):
                                  ctypes.POINTER(I)]),
         "dns_forward": (I, [P, P, P]),
         "dns_inverse": (I, [P, P, P]),
+        "dns_autotune": (I, [P, I]),
+        "dns_get_plan": (I, [P, ctypes.POINTER(I), I, ctypes.POINTER(I)]),
+        "dns_set_plan": (I, [P, ctypes.POINTER(I), I]),
+        "dns_plan_variants": (I, [P, I, ctypes.POINTER(I), I, ctypes.POINTER(I)]),
         "dns_strerror": (ctypes.c_char_p, [I]),
         "dns_last_error": (ctypes.c_char_p, [P]),
     }
@@ -129,7 +133,7 @@ class Solver:
     """
 
     def __init__(self, N, nu, dt, dtype="f64", dealias="text", diag_every=0, use_graph=True,
-                 history_cap=4096, stream=None):
+                 history_cap=4096, stream=None, autotune=False):
         import torch
         self._torch = torch
         lib = load_library()
@@ -143,6 +147,7 @@ class Solver:
         o.diag_every = int(diag_every)
         o.use_graph = 1 if use_graph else 0
         o.history_cap = int(history_cap)
+        o.autotune = 1 if autotune else 0
         self.history_cap = int(history_cap)
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -262,6 +267,35 @@ class Solver:
         _check(load_library().dns_profile_step(self.handle, int(nsteps), ms, names, 16, ctypes.byref(n)),
                self.handle, "dns_profile_step")
         return {names[i].decode(): float(ms[i]) for i in range(n.value)}
+
+    PASSES = ("xinv_curl", "yinv6", "zcross", "yfwd3", "xrhs_rk4")
+
+    def autotune(self, reps=3):
+        _check(load_library().dns_autotune(self.handle, int(reps)), self.handle, "dns_autotune")
+        return self.plan()
+
+    def plan(self):
+        w = (ctypes.c_int * 5)()
+        n = ctypes.c_int()
+        _check(load_library().dns_get_plan(self.handle, w, 5, ctypes.byref(n)), self.handle, "dns_get_plan")
+        return dict(zip(self.PASSES, list(w)))
+
+    def set_plan(self, widths):
+        if isinstance(widths, dict):
+            widths = [widths[p] for p in self.PASSES]
+        w = (ctypes.c_int * 5)(*[int(x) for x in widths])
+        _check(load_library().dns_set_plan(self.handle, w, 5), self.handle, "dns_set_plan")
+        return self
+
+    def plan_variants(self):
+        out = {}
+        for i, name in enumerate(self.PASSES):
+            w = (ctypes.c_int * 8)()
+            n = ctypes.c_int()
+            _check(load_library().dns_plan_variants(self.handle, i, w, 8, ctypes.byref(n)), self.handle,
+                   "dns_plan_variants")
+            out[name] = list(w[: n.value])
+        return out
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -103,6 +103,7 @@ struct dns_ctx {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipEvent_t ev_prof[2] = {nullptr, nullptr};
     const dns::Ops* ops = nullptr;
+    int sel[dns::P_COUNT] = {0, 0, 0, 0, 0};   // chosen variant of each pass
     size_t cbytes = 0;              // bytes of one complex value
     size_t fbytes = 0;              // bytes of one half-spectrum field
     char* state = nullptr;          // U0 | U1 | Us, three fields each
@@ -173,22 +174,30 @@ double inv_norm(int N) { return 1.0 / (2.0 * std::pow((double)N, 6)); }
 
 // Enqueue one RHS evaluation of stage `stage` on stream s (Sec. 3.1
 // computeRHS): the five passes of dns_kernels.hpp.
-void enqueue_stage(dns_t* c, int stage, bool with_diag, hipStream_t s) {
+void launch_pass(dns_t* c, int pass, int variant, int stage, double* diag, hipStream_t s) {
     const dns::Ops* o = c->ops;
-    const void* in = (stage <= 0) ? c->U0() : c->Us();
-    o->xinv(in, c->work, c->tw, true, s);
-    o->yinv6(c->work, c->tw, s);
-    o->zcross(c->work, c->tw, s);
-    o->yfwd3(c->work, c->tw, s);
-    const dns::StageArgs a = stage_args(c, stage, (stage == 3 && with_diag) ? c->part : nullptr);
-    o->xrhs(c->work, c->U0(), c->U1(), c->Us(), c->tw, a, s);
+    switch (pass) {
+        case dns::P_XINV: o->xinv[variant](stage <= 0 ? c->U0() : c->Us(), c->work, c->tw, s); break;
+        case dns::P_YINV6: o->yinv6[variant](c->work, c->tw, s); break;
+        case dns::P_ZCROSS: o->zcross[variant](c->work, c->tw, s); break;
+        case dns::P_YFWD3: o->yfwd3[variant](c->work, c->tw, s); break;
+        default: {
+            const dns::StageArgs a = stage_args(c, stage, diag);
+            o->xrhs[variant](c->work, c->U0(), c->U1(), c->Us(), c->tw, a, s);
+        }
+    }
+}
+
+void enqueue_stage(dns_t* c, int stage, bool with_diag, hipStream_t s) {
+    for (int p = 0; p < dns::P_COUNT; ++p)
+        launch_pass(c, p, c->sel[p], stage, (p == dns::P_XRHS && stage == 3 && with_diag) ? c->part : nullptr, s);
 }
 
 void enqueue_step(dns_t* c, bool with_diag, hipStream_t s) {
     for (int st = 0; st < 4; ++st) enqueue_stage(c, st, with_diag, s);
     if (with_diag)
-        dns::launch_diag_final(c->part, c->ops->x_tiles, inv_norm(c->N), c->dout, c->hist, c->hist_count,
-                               c->opts.history_cap, s);
+        dns::launch_diag_final(c->part, c->ops->xrhs_groups[c->sel[dns::P_XRHS]], inv_norm(c->N), c->dout,
+                               c->hist, c->hist_count, c->opts.history_cap, s);
 }
 
 int build_graph(dns_t* c, int which) {
@@ -254,6 +263,7 @@ void dns_default_opts(dns_opts* o) {
     o->diag_every = 0;
     o->history_cap = 4096;
     o->use_graph = 1;
+    o->autotune = 0;
 }
 
 size_t dns_state_bytes(int N, int dtype) {
@@ -308,7 +318,10 @@ int dns_create_ex(int N, double nu, double dt, int dtype, const dns_opts* opts, 
         return bail(DNS_E_HIP, "hipEventCreate", e);
     if ((e = hipMalloc((void**)&c->state, 9 * c->fbytes)) != hipSuccess) return bail(DNS_E_NOMEM, "hipMalloc(state)", e);
     if ((e = hipMalloc((void**)&c->work, 6 * c->fbytes)) != hipSuccess) return bail(DNS_E_NOMEM, "hipMalloc(work)", e);
-    c->npart_cap = c->ops->x_tiles > dns::DIAG_BLOCKS ? c->ops->x_tiles : dns::DIAG_BLOCKS;
+    c->npart_cap = dns::DIAG_BLOCKS;
+    for (int v = 0; v < c->ops->nvar[dns::P_XRHS]; ++v)
+        if (c->ops->xrhs_groups[v] > c->npart_cap) c->npart_cap = c->ops->xrhs_groups[v];
+    for (int p = 0; p < dns::P_COUNT; ++p) c->sel[p] = c->ops->def[p];
     if ((e = hipMalloc((void**)&c->part, 2 * sizeof(double) * c->npart_cap)) != hipSuccess ||
         (e = hipMalloc((void**)&c->dout, 2 * sizeof(double))) != hipSuccess ||
         (e = hipMalloc((void**)&c->hist, 2 * sizeof(double) * (o.history_cap > 0 ? o.history_cap : 1))) != hipSuccess ||
@@ -331,6 +344,14 @@ int dns_create_ex(int N, double nu, double dt, int dtype, const dns_opts* opts, 
     if ((e = hipMemset(c->state, 0, 9 * c->fbytes)) != hipSuccess ||
         (e = hipMemset(c->hist_count, 0, sizeof(int))) != hipSuccess)
         return bail(DNS_E_HIP, "hipMemset", e);
+    if (o.autotune) {
+        const int r = dns_autotune(c, 3);
+        if (r != DNS_OK) {
+            release(c);
+            delete c;
+            return r;
+        }
+    }
     *out = c;
     return DNS_OK;
 }
@@ -355,8 +376,8 @@ int dns_set_velocity(dns_t* c, const void* u) {
     int r = enter(c);
     if (r) return r;
     c->ops->zr2c(u, c->work, c->tw, c->s);
-    c->ops->yfwd3(c->work, c->tw, c->s);
-    c->ops->xfwd(c->work, c->U0(), c->tw, c->s);
+    c->ops->yfwd3[c->sel[dns::P_YFWD3]](c->work, c->tw, c->s);
+    c->ops->xfwd3(c->work, c->U0(), c->tw, c->s);
     if ((r = launched(c, "set_velocity"))) return r;
     if ((r = reset_counters(c))) return r;
     return leave(c);
@@ -387,7 +408,7 @@ int dns_get_velocity(dns_t* c, void* u) {
     if (!c->has_state) return fail(c, DNS_E_STATE, "no velocity set");
     int r = enter(c);
     if (r) return r;
-    c->ops->xinv(c->U0(), c->work, c->tw, false, c->s);
+    c->ops->xinv3(c->U0(), c->work, c->tw, c->s);
     c->ops->yinv3(c->work, c->tw, c->s);
     c->ops->zc2r(c->work, u, c->tw, c->s);
     if ((r = launched(c, "get_velocity"))) return r;
@@ -399,8 +420,8 @@ int dns_forward(dns_t* c, const void* u, void* uh) {
     int r = enter(c);
     if (r) return r;
     c->ops->zr2c(u, c->work, c->tw, c->s);
-    c->ops->yfwd3(c->work, c->tw, c->s);
-    c->ops->xfwd(c->work, c->Us(), c->tw, c->s);
+    c->ops->yfwd3[c->sel[dns::P_YFWD3]](c->work, c->tw, c->s);
+    c->ops->xfwd3(c->work, c->Us(), c->tw, c->s);
     c->ops->layout(c->Us(), uh, false, c->s);
     if ((r = launched(c, "forward"))) return r;
     return leave(c);
@@ -411,7 +432,7 @@ int dns_inverse(dns_t* c, const void* uh, void* u) {
     int r = enter(c);
     if (r) return r;
     c->ops->layout(uh, c->Us(), true, c->s);
-    c->ops->xinv(c->Us(), c->work, c->tw, false, c->s);
+    c->ops->xinv3(c->Us(), c->work, c->tw, c->s);
     c->ops->yinv3(c->work, c->tw, c->s);
     c->ops->zc2r(c->work, u, c->tw, c->s);
     if ((r = launched(c, "inverse"))) return r;
@@ -501,29 +522,20 @@ int dns_synchronize(dns_t* c) {
     return DNS_OK;
 }
 
+static const char* kPassNames[dns::P_COUNT] = {"xinv_curl", "yinv6", "zcross", "yfwd3", "xrhs_rk4"};
+
 int dns_profile_step(dns_t* c, int nsteps, float* ms, const char** names, int max, int* count) {
-    static const char* kNames[5] = {"xinv_curl", "yinv6", "zcross", "yfwd3", "xrhs_rk4"};
     if (!c || !ms || !count || nsteps <= 0 || max < 0) return fail(c, DNS_E_INVAL, "bad argument");
     if (!c->has_state) return fail(c, DNS_E_STATE, "no velocity set");
     int r = enter(c);
     if (r) return r;
-    double acc[5] = {0, 0, 0, 0, 0};
-    const dns::Ops* o = c->ops;
+    double acc[dns::P_COUNT] = {0, 0, 0, 0, 0};
     for (int n = 0; n < nsteps; ++n) {
         for (int st = 0; st < 4; ++st) {
-            for (int k = 0; k < 5; ++k) {
+            for (int k = 0; k < dns::P_COUNT; ++k) {
                 DNS_TRY(c, hipEventRecord(c->ev_prof[0], c->s));
-                switch (k) {
-                    case 0: o->xinv(st == 0 ? c->U0() : c->Us(), c->work, c->tw, true, c->s); break;
-                    case 1: o->yinv6(c->work, c->tw, c->s); break;
-                    case 2: o->zcross(c->work, c->tw, c->s); break;
-                    case 3: o->yfwd3(c->work, c->tw, c->s); break;
-                    default: {
-                        const dns::StageArgs a = stage_args(c, st, nullptr);
-                        o->xrhs(c->work, c->U0(), c->U1(), c->Us(), c->tw, a, c->s);
-                    }
-                }
-                if ((r = launched(c, kNames[k]))) return r;
+                launch_pass(c, k, c->sel[k], st, nullptr, c->s);
+                if ((r = launched(c, kPassNames[k]))) return r;
                 DNS_TRY(c, hipEventRecord(c->ev_prof[1], c->s));
                 DNS_TRY(c, hipEventSynchronize(c->ev_prof[1]));
                 float t = 0.f;
@@ -533,13 +545,74 @@ int dns_profile_step(dns_t* c, int nsteps, float* ms, const char** names, int ma
         }
         c->steps += 1;
     }
-    const int m = max < 5 ? max : 5;
+    const int m = max < dns::P_COUNT ? max : dns::P_COUNT;
     for (int k = 0; k < m; ++k) {
         ms[k] = (float)(acc[k] / (4.0 * nsteps));
-        if (names) names[k] = kNames[k];
+        if (names) names[k] = kPassNames[k];
     }
     *count = m;
     return leave(c);
+}
+
+// Time every tile-shape variant of every pass on the context's buffers and
+// keep the fastest.  The RHS pass is timed in its stage-1 form, which reads
+// U0 but writes only U1 and Us, so the current state is preserved.
+int dns_autotune(dns_t* c, int reps) {
+    if (!c || reps < 0) return fail(c, DNS_E_INVAL, "bad argument");
+    if (reps == 0) reps = 3;
+    int r = enter(c);
+    if (r) return r;
+    for (auto& g : c->gexec)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    for (int p = 0; p < dns::P_COUNT; ++p) {
+        float best = 1e30f;
+        int bestv = c->sel[p];
+        for (int v = 0; v < c->ops->nvar[p]; ++v) {
+            launch_pass(c, p, v, 1, nullptr, c->s);                  // warm-up
+            DNS_TRY(c, hipEventRecord(c->ev_prof[0], c->s));
+            for (int i = 0; i < reps; ++i) launch_pass(c, p, v, 1, nullptr, c->s);
+            if ((r = launched(c, kPassNames[p]))) return r;
+            DNS_TRY(c, hipEventRecord(c->ev_prof[1], c->s));
+            DNS_TRY(c, hipEventSynchronize(c->ev_prof[1]));
+            float t = 0.f;
+            DNS_TRY(c, hipEventElapsedTime(&t, c->ev_prof[0], c->ev_prof[1]));
+            if (t < best) { best = t; bestv = v; }
+        }
+        c->sel[p] = bestv;
+    }
+    return leave(c);
+}
+
+int dns_get_plan(const dns_t* c, int* widths, int max, int* count) {
+    if (!c || !count || max < 0 || (max > 0 && !widths)) return DNS_E_INVAL;
+    const int m = max < dns::P_COUNT ? max : dns::P_COUNT;
+    for (int p = 0; p < m; ++p) widths[p] = c->ops->width[p][c->sel[p]];
+    *count = dns::P_COUNT;
+    return DNS_OK;
+}
+
+int dns_set_plan(dns_t* c, const int* widths, int n) {
+    if (!c || !widths || n != dns::P_COUNT) return fail(c, DNS_E_INVAL, "bad argument");
+    int sel[dns::P_COUNT];
+    for (int p = 0; p < dns::P_COUNT; ++p) {
+        sel[p] = -1;
+        for (int v = 0; v < c->ops->nvar[p]; ++v)
+            if (c->ops->width[p][v] == widths[p]) sel[p] = v;
+        if (sel[p] < 0) return fail(c, DNS_E_INVAL, "no variant of that width for this N and dtype");
+    }
+    DNS_TRY(c, hipStreamSynchronize(c->s));
+    for (auto& g : c->gexec)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    for (int p = 0; p < dns::P_COUNT; ++p) c->sel[p] = sel[p];
+    return DNS_OK;
+}
+
+int dns_plan_variants(const dns_t* c, int pass, int* widths, int max, int* count) {
+    if (!c || !count || pass < 0 || pass >= dns::P_COUNT || max < 0 || (max > 0 && !widths)) return DNS_E_INVAL;
+    const int n = c->ops->nvar[pass];
+    for (int v = 0; v < n && v < max; ++v) widths[v] = c->ops->width[pass][v];
+    *count = n;
+    return DNS_OK;
 }
 
 const char* dns_strerror(int s) {

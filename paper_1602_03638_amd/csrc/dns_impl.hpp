@@ -9,49 +9,74 @@
 
 namespace dns {
 
-template <typename R, int N> struct Impl {
-    using K = Cfg<R, N>;
-    using C = cx<R>;
+constexpr size_t LDS_LIMIT = 160 * 1024;
 
-    static void xinv(const void* U, void* W, const void* tw, bool curl, hipStream_t s) {
-        if (curl)
-            hipLaunchKernelGGL((k_xinv<R, N, true>), dim3(K::X_TILES), dim3(K::XTHREADS), 0, s,
-                               (const C*)U, (C*)W, (const C*)tw);
-        else
-            hipLaunchKernelGGL((k_xinv<R, N, false>), dim3(K::X_TILES), dim3(K::XTHREADS), 0, s,
-                               (const C*)U, (C*)W, (const C*)tw);
+template <typename R, int N> struct Impl {
+    using C = cx<R>;
+    static constexpr int G = N / 8;
+    static constexpr size_t CB = sizeof(C);
+    static constexpr int XCOLS = N * (N / 2);
+
+    // Feasibility of a workgroup shape: at most 1024 threads and the LDS limit.
+    template <int T> static constexpr bool x_ok() {
+        return T <= N && G * T <= 1024 && (size_t)T * N * CB <= LDS_LIMIT;
     }
-    template <int DIR, int NF>
-    static void ypass(void* W, const void* tw, hipStream_t s) {
-        hipLaunchKernelGGL((k_yline<R, N, DIR, NF>), dim3(K::Y_TILES), dim3(K::YTHREADS), 0, s,
+    template <int T> static constexpr bool xr_ok() {
+        return x_ok<T>() && (size_t)T * N * CB + 2 * 8 * (size_t)G * T <= LDS_LIMIT;
+    }
+    template <int T> static constexpr bool y_ok() {
+        return T <= N / 2 && G * T <= 1024 && (size_t)T * N * CB <= LDS_LIMIT;
+    }
+    template <int L> static constexpr bool z_ok() {
+        return L <= N * N && G * L <= 1024 && (size_t)L * N * CB <= LDS_LIMIT;
+    }
+    template <int T> static constexpr int x_groups() { return XCOLS / T + N / T; }
+
+    // ---- pass launchers ----------------------------------------------------
+    template <int T> static void xinv(const void* U, void* W, const void* tw, hipStream_t s) {
+        hipLaunchKernelGGL((k_xinv_curl<R, N, T>), dim3(x_groups<T>()), dim3(G * T), 0, s,
+                           (const C*)U, (C*)W, (const C*)tw);
+    }
+    static constexpr int LY = (256 / G) < 1 ? 1 : ((256 / G) < N ? 256 / G : N);
+    template <int T, int DIR, int NF> static void ypass(void* W, const void* tw, hipStream_t s) {
+        hipLaunchKernelGGL((k_yline<R, N, T, DIR, NF>), dim3(N * ((N / 2) / T)), dim3(G * T), 0, s,
                            (C*)W, (const C*)tw);
-        hipLaunchKernelGGL((k_yline_nyq<R, N, DIR, NF>), dim3(N / K::LY), dim3(K::NYTHREADS), 0, s,
+        hipLaunchKernelGGL((k_yline_nyq<R, N, LY, DIR, NF>), dim3(N / LY), dim3(G * LY), 0, s,
                            (C*)W, (const C*)tw);
     }
-    static void yinv6(void* W, const void* tw, hipStream_t s) { ypass<+1, 6>(W, tw, s); }
-    static void yinv3(void* W, const void* tw, hipStream_t s) { ypass<+1, 3>(W, tw, s); }
-    static void yfwd3(void* W, const void* tw, hipStream_t s) { ypass<-1, 3>(W, tw, s); }
-    static void zcross(void* W, const void* tw, hipStream_t s) {
+    template <int T> static void yinv6(void* W, const void* tw, hipStream_t s) { ypass<T, +1, 6>(W, tw, s); }
+    template <int T> static void yfwd3(void* W, const void* tw, hipStream_t s) { ypass<T, -1, 3>(W, tw, s); }
+    template <int L> static void zcross(void* W, const void* tw, hipStream_t s) {
         const R scale = (R)std::ldexp(1.0, -6 * ilog2(N));
-        hipLaunchKernelGGL((k_zcross<R, N>), dim3((N * N) / K::LZ), dim3(K::ZTHREADS), 0, s,
-                           (C*)W, (const C*)tw, scale);
+        hipLaunchKernelGGL((k_zcross<R, N, L>), dim3((N * N) / L), dim3(G * L), 0, s, (C*)W, (const C*)tw, scale);
     }
+    template <int T>
     static void xrhs(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
                      hipStream_t s) {
-        hipLaunchKernelGGL((k_xrhs<R, N>), dim3(K::X_TILES), dim3(K::XTHREADS), 0, s,
+        hipLaunchKernelGGL((k_xrhs<R, N, T>), dim3(x_groups<T>()), dim3(G * T), 0, s,
                            (const C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a);
     }
-    static void xfwd(const void* W, void* U, const void* tw, hipStream_t s) {
-        hipLaunchKernelGGL((k_xfwd<R, N>), dim3(K::X_TILES), dim3(K::XTHREADS), 0, s,
+
+    // ---- standalone transforms (fixed shapes) -------------------------------
+    static constexpr int TS = x_ok<8>() ? 8 : (x_ok<4>() ? 4 : (x_ok<2>() ? 2 : 1));
+    static constexpr int YS = y_ok<8>() ? 8 : (y_ok<4>() ? 4 : (y_ok<2>() ? 2 : 1));
+    static constexpr int LS = z_ok<4>() ? 4 : (z_ok<2>() ? 2 : 1);
+    static void xinv3(const void* U, void* W, const void* tw, hipStream_t s) {
+        hipLaunchKernelGGL((k_xplain<R, N, TS, +1, 3>), dim3(x_groups<TS>()), dim3(G * TS), 0, s,
+                           (const C*)U, (C*)W, (const C*)tw);
+    }
+    static void xfwd3(const void* W, void* U, const void* tw, hipStream_t s) {
+        hipLaunchKernelGGL((k_xplain<R, N, TS, -1, 3>), dim3(x_groups<TS>()), dim3(G * TS), 0, s,
                            (const C*)W, (C*)U, (const C*)tw);
     }
+    static void yinv3(void* W, const void* tw, hipStream_t s) { ypass<YS, +1, 3>(W, tw, s); }
     static void zr2c(const void* u, void* W, const void* tw, hipStream_t s) {
-        hipLaunchKernelGGL((k_zr2c<R, N>), dim3((N * N) / K::LZ), dim3(K::ZTHREADS), 0, s,
+        hipLaunchKernelGGL((k_zr2c<R, N, LS>), dim3((N * N) / LS), dim3(G * LS), 0, s,
                            (const R*)u, (C*)W, (const C*)tw);
     }
     static void zc2r(const void* W, void* u, const void* tw, hipStream_t s) {
         const R scale = (R)std::ldexp(1.0, -3 * ilog2(N));
-        hipLaunchKernelGGL((k_zc2r<R, N>), dim3((N * N) / K::LZ), dim3(K::ZTHREADS), 0, s,
+        hipLaunchKernelGGL((k_zc2r<R, N, LS>), dim3((N * N) / LS), dim3(G * LS), 0, s,
                            (const C*)W, (R*)u, (const C*)tw, scale);
     }
     static void layout(const void* src, void* dst, bool to_internal, hipStream_t s) {
@@ -68,10 +93,72 @@ template <typename R, int N> struct Impl {
         hipLaunchKernelGGL((k_diag_partial<R, N>), dim3(DIAG_BLOCKS), dim3(256), 0, s, (const C*)U, part);
     }
 
+    // ---- variant tables ------------------------------------------------------
+    template <int T> static void add_x(Ops& o) {
+        if constexpr (x_ok<T>()) {
+            int& n = o.nvar[P_XINV];
+            o.xinv[n] = &xinv<T>;
+            o.width[P_XINV][n++] = T;
+        }
+        if constexpr (xr_ok<T>()) {
+            int& n = o.nvar[P_XRHS];
+            o.xrhs[n] = &xrhs<T>;
+            o.xrhs_groups[n] = x_groups<T>();
+            o.width[P_XRHS][n++] = T;
+        }
+    }
+    template <int T> static void add_y(Ops& o) {
+        if constexpr (y_ok<T>()) {
+            int& n = o.nvar[P_YINV6];
+            o.yinv6[n] = &yinv6<T>;
+            o.yfwd3[n] = &yfwd3<T>;
+            o.width[P_YINV6][n] = T;
+            o.width[P_YFWD3][n] = T;
+            ++n;
+            o.nvar[P_YFWD3] = n;
+        }
+    }
+    template <int L> static void add_z(Ops& o) {
+        if constexpr (z_ok<L>()) {
+            int& n = o.nvar[P_ZCROSS];
+            o.zcross[n] = &zcross<L>;
+            o.width[P_ZCROSS][n++] = L;
+        }
+    }
+    // index of the widest variant of pass p not wider than w
+    static int pick(const Ops& o, int p, int w) {
+        int best = 0;
+        for (int v = 0; v < o.nvar[p]; ++v)
+            if (o.width[p][v] <= w) best = v;
+        return best;
+    }
+    static Ops make() {
+        Ops o{};
+        o.N = N;
+        o.real_size = sizeof(R);
+        o.tw_count = tw_size(N) > 0 ? tw_size(N) : 1;
+        add_x<2>(o); add_x<4>(o); add_x<8>(o); add_x<16>(o);
+        add_y<4>(o); add_y<8>(o); add_y<16>(o); add_y<32>(o);
+        add_z<1>(o); add_z<2>(o); add_z<4>(o); add_z<8>(o);
+        // defaults: 128-byte row segments in the x passes, 256-byte in the
+        // y passes, four z lines per workgroup (measured on MI355X)
+        const int xw = (int)(128 / CB), yw = (int)(256 / CB);
+        o.def[P_XINV] = pick(o, P_XINV, xw);
+        o.def[P_XRHS] = pick(o, P_XRHS, xw);
+        o.def[P_YINV6] = pick(o, P_YINV6, yw);
+        o.def[P_YFWD3] = pick(o, P_YFWD3, yw);
+        o.def[P_ZCROSS] = pick(o, P_ZCROSS, 4);
+        o.xinv3 = &xinv3;
+        o.yinv3 = &yinv3;
+        o.xfwd3 = &xfwd3;
+        o.zr2c = &zr2c;
+        o.zc2r = &zc2r;
+        o.layout = &layout;
+        o.diag_partial = &diag_partial;
+        return o;
+    }
     static const Ops* table() {
-        static const Ops ops = {N, sizeof(R), K::X_TILES, tw_size(N) > 0 ? tw_size(N) : 1,
-                                &xinv, &yinv6, &zcross, &yfwd3, &xrhs,
-                                &yinv3, &xfwd, &zr2c, &zc2r, &layout, &diag_partial};
+        static const Ops ops = make();
         return &ops;
     }
 };

@@ -46,47 +46,88 @@ template <int N> struct XCol {
 };
 
 // ---------------------------------------------------------------------------
-// Pass 1: inverse x transform of u_hat (3 fields at U) and, when CURL, of
+// Pass 1: inverse x transform of u_hat (3 fields at U) and of the vorticity
 // omega_hat = i k x u_hat (Sec. 3.1 Curl listing):
-//   omega_x = i (ky w - kz v), omega_y = i (kz u - kx w), omega_z = i (kx v - ky u)
-// Output fields at W: u, v, w, omega_x, omega_y, omega_z (CURL) or u, v, w.
+//   omega_x = i (ky w - kz v), omega_y = i (kz u - kx w), omega_z = i (kx v - ky u).
+// ky and kz are constant along an x line, so by linearity only kx v_hat and
+// kx w_hat need transforms of their own:
+//   F(omega_x) = i (ky W - kz V),  F(omega_y) = i (kz U - F(kx w_hat)),
+//   F(omega_z) = i (F(kx v_hat) - ky U)          (F = inverse x transform)
+// Five transforms instead of six, and at most three lines per thread live at
+// once.  Output fields at W: u, v, w, omega_x, omega_y, omega_z.
+// T lines (consecutive columns) per workgroup.
 // ---------------------------------------------------------------------------
-template <typename R, int N, bool CURL>
-__global__ __launch_bounds__((Cfg<R, N>::XTHREADS))
-void k_xinv(const cx<R>* __restrict__ U, cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
-    using K = Cfg<R, N>;
-    constexpr int T = K::TX, G = K::G, E = K::E;
+template <typename R, int N, int T>
+__global__ __launch_bounds__(N / 8 * T)
+void k_xinv_curl(const cx<R>* __restrict__ U, cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
+    constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
     __shared__ cx<R> lds[T * N];
     const int t = threadIdx.x % T, g = threadIdx.x / T;
     const XCol<N> col(blockIdx.x * T + t);
+    const unsigned b0 = col.base, rs = col.rs;
+    const R ky = (R)col.ky, kz = (R)col.kz;
+    cx<R>* lt = lds + t;
+    auto at = [&](int m) { return b0 + (unsigned)(g + m * G) * rs; };
 
-    cx<R> u[3][E];
+    cx<R> a[E], b[E], c[E];
+    // v_hat: B = F(kx v_hat) in b, V = F(v_hat) in a
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int m = 0; m < E; ++m) {
+        a[m] = U[FS + at(m)];
+        b[m] = cscale<R>(a[m], (R)kfreq(g + m * G, N));
+    }
+    fft_line<R, N, E, +1>(b, lt, T, tw, g);
+    fft_line<R, N, E, +1>(a, lt, T, tw, g);
 #pragma unroll
-        for (int m = 0; m < E; ++m) u[c][m] = U[c * FS + col.base + (size_t)(g + m * G) * col.rs];
+    for (int m = 0; m < E; ++m) W[FS + at(m)] = a[m];
+    // u_hat: U in c; omega_z = i (B - ky U)
+#pragma unroll
+    for (int m = 0; m < E; ++m) c[m] = U[at(m)];
+    fft_line<R, N, E, +1>(c, lt, T, tw, g);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        W[at(m)] = c[m];
+        W[5 * FS + at(m)] = cmuli<R>(csub<R>(b[m], cscale<R>(c[m], ky)));
+    }
+    // w_hat: F(kx w_hat) in b; omega_y = i (kz U - F(kx w_hat))
+#pragma unroll
+    for (int m = 0; m < E; ++m) b[m] = cscale<R>(U[2 * FS + at(m)], (R)kfreq(g + m * G, N));
+    fft_line<R, N, E, +1>(b, lt, T, tw, g);
+#pragma unroll
+    for (int m = 0; m < E; ++m) W[4 * FS + at(m)] = cmuli<R>(csub<R>(cscale<R>(c[m], kz), b[m]));
+    // w_hat again (cache hit): W in b; omega_x = i (ky W - kz V)
+#pragma unroll
+    for (int m = 0; m < E; ++m) b[m] = U[2 * FS + at(m)];
+    fft_line<R, N, E, +1>(b, lt, T, tw, g);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        W[2 * FS + at(m)] = b[m];
+        W[3 * FS + at(m)] = cmuli<R>(csub<R>(cscale<R>(b[m], ky), cscale<R>(a[m], kz)));
+    }
+}
 
-    constexpr int NF = CURL ? 6 : 3;
-#pragma unroll
+// Plain inverse (DIR = +1) or forward (DIR = -1) x transform of NF fields
+// from S into D (used by the standalone 3D transforms).
+template <typename R, int N, int T, int DIR, int NF>
+__global__ __launch_bounds__(N / 8 * T)
+void k_xplain(const cx<R>* __restrict__ S, cx<R>* __restrict__ D, const cx<R>* __restrict__ tw) {
+    constexpr int E = 8, G = N / E;
+    constexpr size_t FS = field_size(N);
+    __shared__ cx<R> lds[T * N];
+    const int t = threadIdx.x % T, g = threadIdx.x / T;
+    const XCol<N> col(blockIdx.x * T + t);
+    const unsigned b0 = col.base, rs = col.rs;
+#pragma unroll 1
     for (int f = 0; f < NF; ++f) {
+        const cx<R>* src = S + f * FS;
+        cx<R>* dst = D + f * FS;
         cx<R> a[E];
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const R kx = (R)kfreq(g + m * G, N), ky = (R)col.ky, kz = (R)col.kz;
-            if (f < 3) {
-                a[m] = u[f][m];
-            } else if (f == 3) {
-                a[m] = cmuli<R>(csub<R>(cscale<R>(u[2][m], ky), cscale<R>(u[1][m], kz)));
-            } else if (f == 4) {
-                a[m] = cmuli<R>(csub<R>(cscale<R>(u[0][m], kz), cscale<R>(u[2][m], kx)));
-            } else {
-                a[m] = cmuli<R>(csub<R>(cscale<R>(u[1][m], kx), cscale<R>(u[0][m], ky)));
-            }
-        }
-        fft_line<R, N, E, +1>(a, lds + t, T, tw, g);
+        for (int m = 0; m < E; ++m) a[m] = src[b0 + (unsigned)(g + m * G) * rs];
+        fft_line<R, N, E, DIR>(a, lds + t, T, tw, g);
 #pragma unroll
-        for (int m = 0; m < E; ++m) W[f * FS + col.base + (size_t)(g + m * G) * col.rs] = a[m];
+        for (int m = 0; m < E; ++m) dst[b0 + (unsigned)(g + m * G) * rs] = a[m];
     }
 }
 
@@ -94,36 +135,35 @@ void k_xinv(const cx<R>* __restrict__ U, cx<R>* __restrict__ W, const cx<R>* __r
 // Pass 2/4: y transform (direction DIR) of NF fields, in place, main block.
 // Workgroup = TY consecutive iz of one ix; rows iy have stride N/2.
 // ---------------------------------------------------------------------------
-template <typename R, int N, int DIR, int NF>
-__global__ __launch_bounds__((Cfg<R, N>::YTHREADS))
+template <typename R, int N, int T, int DIR, int NF>
+__global__ __launch_bounds__(N / 8 * T)
 void k_yline(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
-    using K = Cfg<R, N>;
-    constexpr int T = K::TY, G = K::G, E = K::E;
+    constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
     constexpr int ZT = (N / 2) / T;          // tiles per ix
     __shared__ cx<R> lds[T * N];
     const int t = threadIdx.x % T, g = threadIdx.x / T;
     const int ix = blockIdx.x / ZT;
     const int iz = (blockIdx.x % ZT) * T + t;
-    const size_t base = (size_t)ix * (N * (N / 2)) + iz;
-    constexpr size_t rs = N / 2;
+    const unsigned base = (unsigned)ix * (N * (N / 2)) + iz;
+    constexpr unsigned rs = N / 2;
 #pragma unroll 1
     for (int f = 0; f < NF; ++f) {
+        cx<R>* F = W + f * FS;
         cx<R> a[E];
 #pragma unroll
-        for (int m = 0; m < E; ++m) a[m] = W[f * FS + base + (size_t)(g + m * G) * rs];
+        for (int m = 0; m < E; ++m) a[m] = F[base + (unsigned)(g + m * G) * rs];
         fft_line<R, N, E, DIR>(a, lds + t, T, tw, g);
 #pragma unroll
-        for (int m = 0; m < E; ++m) W[f * FS + base + (size_t)(g + m * G) * rs] = a[m];
+        for (int m = 0; m < E; ++m) F[base + (unsigned)(g + m * G) * rs] = a[m];
     }
 }
 
 // y transform of the Nyquist plane (kz = N/2): line ix is contiguous.
-template <typename R, int N, int DIR, int NF>
-__global__ __launch_bounds__((Cfg<R, N>::NYTHREADS))
+template <typename R, int N, int L, int DIR, int NF>
+__global__ __launch_bounds__(N / 8 * L)
 void k_yline_nyq(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
-    using K = Cfg<R, N>;
-    constexpr int L = K::LY, G = K::G, E = K::E;
+    constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
     __shared__ cx<R> lds[L * N];
     const int g = threadIdx.x % G, l = threadIdx.x / G;
@@ -186,11 +226,10 @@ __device__ __forceinline__ void zsplit(cx<R> pk, cx<R> pnk, cx<R>& A, cx<R>& B) 
 // spectra of c into fields 0..2 of W (in place: a workgroup owns its lines).
 // scale = N^-6 (exact power of two) restores the inverse transforms' 1/N^3.
 // ---------------------------------------------------------------------------
-template <typename R, int N>
-__global__ __launch_bounds__((Cfg<R, N>::ZTHREADS))
+template <typename R, int N, int L>
+__global__ __launch_bounds__(N / 8 * L)
 void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale) {
-    using K = Cfg<R, N>;
-    constexpr int L = K::LZ, G = K::G, E = K::E;
+    constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
     __shared__ cx<R> lds[L * N];
     const int g = threadIdx.x % G, l = threadIdx.x / G;
@@ -242,11 +281,10 @@ void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale) {
 
 // Forward real z transforms of three physical fields u (3, N, N, N) into the
 // half spectra of fields 0..2 of W (first step of the forward 3D transform).
-template <typename R, int N>
-__global__ __launch_bounds__((Cfg<R, N>::ZTHREADS))
+template <typename R, int N, int L>
+__global__ __launch_bounds__(N / 8 * L)
 void k_zr2c(const R* __restrict__ u, cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
-    using K = Cfg<R, N>;
-    constexpr int L = K::LZ, G = K::G, E = K::E;
+    constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
     constexpr size_t PS = (size_t)N * N * N;
     __shared__ cx<R> lds[L * N];
@@ -286,11 +324,10 @@ void k_zr2c(const R* __restrict__ u, cx<R>* __restrict__ W, const cx<R>* __restr
 
 // Inverse real z transforms of fields 0..2 of W into physical u (3, N, N, N),
 // scaled by `scale` (N^-3 for the normalised inverse).
-template <typename R, int N>
-__global__ __launch_bounds__((Cfg<R, N>::ZTHREADS))
+template <typename R, int N, int L>
+__global__ __launch_bounds__(N / 8 * L)
 void k_zc2r(const cx<R>* __restrict__ W, R* __restrict__ u, const cx<R>* __restrict__ tw, R scale) {
-    using K = Cfg<R, N>;
-    constexpr int L = K::LZ, G = K::G, E = K::E;
+    constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
     constexpr size_t PS = (size_t)N * N * N;
     __shared__ cx<R> lds[L * N];
@@ -328,13 +365,12 @@ void k_zc2r(const cx<R>* __restrict__ W, R* __restrict__ u, const cx<R>* __restr
 // of w |u_hat|^2 and w |k x u_hat|^2 of the new state (w = 1 on the kz = 0
 // and kz = N/2 planes, 2 elsewhere) to diag[2 blockIdx], diag[2 blockIdx + 1].
 // ---------------------------------------------------------------------------
-template <typename R, int N>
-__global__ __launch_bounds__((Cfg<R, N>::XTHREADS))
+template <typename R, int N, int T>
+__global__ __launch_bounds__(N / 8 * T)
 void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
             cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa) {
-    using K = Cfg<R, N>;
-    constexpr int T = K::TX, G = K::G, E = K::E;
-    constexpr int NT = K::XTHREADS;
+    constexpr int E = 8, G = N / E;
+    constexpr int NT = G * T;
     constexpr size_t FS = field_size(N);
     __shared__ cx<R> lds[T * N];
     __shared__ double red[2][NT];
@@ -434,28 +470,6 @@ void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restri
             sa.diag[2 * blockIdx.x] = red[0][0];
             sa.diag[2 * blockIdx.x + 1] = red[1][0];
         }
-    }
-}
-
-// Plain forward x transform: W fields 0..2 -> U fields 0..2 (last step of
-// the forward 3D transform).
-template <typename R, int N>
-__global__ __launch_bounds__((Cfg<R, N>::XTHREADS))
-void k_xfwd(const cx<R>* __restrict__ W, cx<R>* __restrict__ U, const cx<R>* __restrict__ tw) {
-    using K = Cfg<R, N>;
-    constexpr int T = K::TX, G = K::G, E = K::E;
-    constexpr size_t FS = field_size(N);
-    __shared__ cx<R> lds[T * N];
-    const int t = threadIdx.x % T, g = threadIdx.x / T;
-    const XCol<N> col(blockIdx.x * T + t);
-#pragma unroll 1
-    for (int f = 0; f < 3; ++f) {
-        cx<R> a[E];
-#pragma unroll
-        for (int m = 0; m < E; ++m) a[m] = W[f * FS + col.base + (size_t)(g + m * G) * col.rs];
-        fft_line<R, N, E, -1>(a, lds + t, T, tw, g);
-#pragma unroll
-        for (int m = 0; m < E; ++m) U[f * FS + col.base + (size_t)(g + m * G) * col.rs] = a[m];
     }
 }
 

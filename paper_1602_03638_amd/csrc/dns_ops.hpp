@@ -1,24 +1,42 @@
-// Host-side launch table of the kernels for one (real type, N) pair.
+// Host-side launch table of the kernels for one (real type, N) pair, with
+// the tile-shape variants the autotuner chooses between.  Every variant of a
+// pass runs the same per-line arithmetic, so all variants give bitwise
+// identical results; they differ only in how many lines share a workgroup.
 #pragma once
 
 #include "dns_common.hpp"
 
 namespace dns {
 
+constexpr int MAXV = 4;   // variants per pass
+
+enum Pass { P_XINV = 0, P_YINV6, P_ZCROSS, P_YFWD3, P_XRHS, P_COUNT };
+
+using XinvFn = void (*)(const void* U, void* W, const void* tw, hipStream_t s);
+using YFn = void (*)(void* W, const void* tw, hipStream_t s);
+using ZFn = void (*)(void* W, const void* tw, hipStream_t s);
+using XrhsFn = void (*)(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
+                        hipStream_t s);
+
 struct Ops {
     int N;
     size_t real_size;      // bytes of one real value
-    int x_tiles;           // workgroups of an x pass (= fused diagnostic partials)
     int tw_count;          // complex entries of the twiddle table
-    // one RK4 stage
-    void (*xinv)(const void* U, void* W, const void* tw, bool curl, hipStream_t s);
-    void (*yinv6)(void* W, const void* tw, hipStream_t s);
-    void (*zcross)(void* W, const void* tw, hipStream_t s);
-    void (*yfwd3)(void* W, const void* tw, hipStream_t s);
-    void (*xrhs)(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a, hipStream_t s);
-    // standalone transforms and utilities
+    // variants of the five passes of one RK4 stage; width[p][v] is the
+    // number of lines per workgroup of variant v of pass p
+    int nvar[P_COUNT];
+    int width[P_COUNT][MAXV];
+    int def[P_COUNT];      // default variant (before tuning)
+    XinvFn xinv[MAXV];
+    YFn yinv6[MAXV];
+    ZFn zcross[MAXV];
+    YFn yfwd3[MAXV];
+    XrhsFn xrhs[MAXV];
+    int xrhs_groups[MAXV]; // workgroups of each xrhs variant (= fused diagnostic partials)
+    // standalone transforms and utilities (default shapes)
+    void (*xinv3)(const void* U, void* W, const void* tw, hipStream_t s);
     void (*yinv3)(void* W, const void* tw, hipStream_t s);
-    void (*xfwd)(const void* W, void* U, const void* tw, hipStream_t s);
+    void (*xfwd3)(const void* W, void* U, const void* tw, hipStream_t s);
     void (*zr2c)(const void* u, void* W, const void* tw, hipStream_t s);
     void (*zc2r)(const void* W, void* u, const void* tw, hipStream_t s);
     void (*layout)(const void* src, void* dst, bool to_internal, hipStream_t s);

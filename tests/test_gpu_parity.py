@@ -202,3 +202,25 @@ def test_nonfinite_energy_reported():
     with pytest.raises(DnsError) as e:
         s.energy()
     assert e.value.status == DNS_E_NONFINITE
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("N", [16, 64])
+def test_every_plan_variant_is_bitwise_identical(N, dtype):
+    """Tile-shape variants change only how lines share a workgroup, never the
+    arithmetic: every variant of every pass gives identical bits."""
+    note(f"plan variants N={N} {dtype}")
+    uh0 = ic.random_isotropic(N, seed=77)
+    s = _solver(N, 0.01, 0.005, dtype=dtype)
+    base = s.plan()
+    ref = to_host(s.set_spectral(to_dev(uh0, dtype)).step(2).get_spectral())
+    for p, widths in s.plan_variants().items():
+        for w in widths:
+            plan = dict(base)
+            plan[p] = w
+            s.set_plan(plan)
+            got = to_host(s.set_spectral(to_dev(uh0, dtype)).step(2).get_spectral())
+            assert np.array_equal(got, ref), (p, w)
+    tuned = s.autotune()
+    got = to_host(s.set_spectral(to_dev(uh0, dtype)).step(2).get_spectral())
+    assert np.array_equal(got, ref), tuned

@@ -117,3 +117,14 @@ def test_random_isotropic_shell_spectrum():
     ks = np.arange(3, 13)
     ratio = np.bincount(shell.ravel(), e_mode.ravel())[ks] / np.bincount(shell.ravel(), model.ravel())[ks]
     assert np.std(ratio) / np.mean(ratio) < 0.1, ratio
+
+
+def test_single_mode_dft_matches_full_transform():
+    """dft3_mode (used for spot checks at full size) against dft3, which is
+    itself pinned by brute force."""
+    N = 16
+    u = np.random.default_rng(9).standard_normal((3, N, N, N))
+    full = spectral.dft3(u)
+    for ix, iy, iz in [(0, 0, 0), (1, 2, 3), (15, 8, 8), (7, 13, 0), (8, 8, 5)]:
+        got = spectral.dft3_mode(u, ix, iy, iz)
+        assert np.max(np.abs(got - full[:, ix, iy, iz])) < 1e-12
