@@ -63,47 +63,53 @@ void k_xinv_curl(const cx<R>* __restrict__ U, cx<R>* __restrict__ W, const cx<R>
     constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
     __shared__ cx<R> lds[T * N];
+    __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
     const int t = threadIdx.x % T, g = threadIdx.x / T;
     const XCol<N> col(blockIdx.x * T + t);
     const unsigned b0 = col.base, rs = col.rs;
     const R ky = (R)col.ky, kz = (R)col.kz;
     cx<R>* lt = lds + t;
     auto at = [&](int m) { return b0 + (unsigned)(g + m * G) * rs; };
+    load_twiddles<R, N>(twl, tw);
 
+    // Loads are issued as early as the register budget allows so that their
+    // latency overlaps the transforms (a barrier inside a transform keeps
+    // later loads from being hoisted by the compiler).
     cx<R> a[E], b[E], c[E];
-    // v_hat: B = F(kx v_hat) in b, V = F(v_hat) in a
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        a[m] = U[FS + at(m)];
-        b[m] = cscale<R>(a[m], (R)kfreq(g + m * G, N));
+        c[m] = U[at(m)];                 // u_hat
+        a[m] = U[FS + at(m)];            // v_hat
     }
-    fft_line<R, N, E, +1>(b, lt, T, tw, g);
-    fft_line<R, N, E, +1>(a, lt, T, tw, g);
-#pragma unroll
-    for (int m = 0; m < E; ++m) W[FS + at(m)] = a[m];
-    // u_hat: U in c; omega_z = i (B - ky U)
-#pragma unroll
-    for (int m = 0; m < E; ++m) c[m] = U[at(m)];
-    fft_line<R, N, E, +1>(c, lt, T, tw, g);
+    fft_line<R, N, E, +1, true>(c, lt, T, twl, g);          // c = U
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         W[at(m)] = c[m];
-        W[5 * FS + at(m)] = cmuli<R>(csub<R>(b[m], cscale<R>(c[m], ky)));
+        b[m] = cscale<R>(a[m], (R)kfreq(g + m * G, N));
     }
-    // w_hat: F(kx w_hat) in b; omega_y = i (kz U - F(kx w_hat))
-#pragma unroll
-    for (int m = 0; m < E; ++m) b[m] = cscale<R>(U[2 * FS + at(m)], (R)kfreq(g + m * G, N));
-    fft_line<R, N, E, +1>(b, lt, T, tw, g);
-#pragma unroll
-    for (int m = 0; m < E; ++m) W[4 * FS + at(m)] = cmuli<R>(csub<R>(cscale<R>(c[m], kz), b[m]));
-    // w_hat again (cache hit): W in b; omega_x = i (ky W - kz V)
-#pragma unroll
-    for (int m = 0; m < E; ++m) b[m] = U[2 * FS + at(m)];
-    fft_line<R, N, E, +1>(b, lt, T, tw, g);
+    fft_line<R, N, E, +1, true>(b, lt, T, twl, g);          // b = F(kx v_hat)
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        W[2 * FS + at(m)] = b[m];
-        W[3 * FS + at(m)] = cmuli<R>(csub<R>(cscale<R>(b[m], ky), cscale<R>(a[m], kz)));
+        W[5 * FS + at(m)] = cmuli<R>(csub<R>(b[m], cscale<R>(c[m], ky)));   // omega_z
+        b[m] = U[2 * FS + at(m)];        // w_hat, in flight during the next transform
+    }
+    fft_line<R, N, E, +1, true>(a, lt, T, twl, g);          // a = V
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        W[FS + at(m)] = a[m];
+        b[m] = cscale<R>(b[m], (R)kfreq(g + m * G, N));
+    }
+    fft_line<R, N, E, +1, true>(b, lt, T, twl, g);          // b = F(kx w_hat)
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        W[4 * FS + at(m)] = cmuli<R>(csub<R>(cscale<R>(c[m], kz), b[m]));   // omega_y
+        c[m] = U[2 * FS + at(m)];        // w_hat again (recently read: cache hit)
+    }
+    fft_line<R, N, E, +1, true>(c, lt, T, twl, g);          // c = W
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        W[2 * FS + at(m)] = c[m];
+        W[3 * FS + at(m)] = cmuli<R>(csub<R>(cscale<R>(c[m], ky), cscale<R>(a[m], kz)));   // omega_x
     }
 }
 
@@ -232,18 +238,52 @@ void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale) {
     constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
     __shared__ cx<R> lds[L * N];
+    __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
     const int g = threadIdx.x % G, l = threadIdx.x / G;
     const size_t line = (size_t)blockIdx.x * L + l;
     cx<R>* my = lds + l * N;
 
+    // Each stored coefficient is loaded once (lower half k < N/2 plus the
+    // Nyquist value), all six lines before the first transform so that the
+    // loads overlap; the upper half of the Hermitian extension,
+    // Z_{N-k} = conj X_k + i conj Y_k, is exchanged through shared memory.
+    cx<R> xl[3][E / 2], yl[3][E / 2], xn[3], yn[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const cx<R>* FX = W + (2 * p) * FS;
+        const cx<R>* FY = W + (2 * p + 1) * FS;
+#pragma unroll
+        for (int m = 0; m < E / 2; ++m) {
+            xl[p][m] = FX[line * (N / 2) + g + m * G];
+            yl[p][m] = FY[line * (N / 2) + g + m * G];
+        }
+        if (g == 0) {
+            xn[p] = FX[main_size(N) + line];
+            yn[p] = FY[main_size(N) + line];
+        }
+    }
+    load_twiddles<R, N>(twl, tw);
     cx<R> z[3][E];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
 #pragma unroll
-        for (int m = 0; m < E; ++m)
-            z[p][m] = zpair_load<R, N>(W + (2 * p) * FS, W + (2 * p + 1) * FS, line, g + m * G);
-        fft_line<R, N, E, +1>(z[p], my, 1, tw, g);
+        for (int m = 0; m < E / 2; ++m) {
+            const int k = g + m * G;
+            cx<R> X = xl[p][m], Y = yl[p][m];
+            if (k == 0) { X.y = R(0); Y.y = R(0); }
+            z[p][m] = {X.x - Y.y, X.y + Y.x};
+            if (k > 0) my[N - k] = {X.x + Y.y, Y.x - X.y};
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = E / 2; m < E; ++m) {
+            const int k = g + m * G;
+            z[p][m] = (k == N / 2) ? cx<R>{xn[p].x, yn[p].x} : my[k];
+        }
+        __syncthreads();
     }
+#pragma unroll
+    for (int p = 0; p < 3; ++p) fft_line<R, N, E, +1, true>(z[p], my, 1, twl, g);
     // z[0] = (u, v), z[1] = (w, omega_x), z[2] = (omega_y, omega_z)
     cx<R> P[E], Q[E];
 #pragma unroll
@@ -253,8 +293,8 @@ void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale) {
         P[m] = {(v * oz - w * oy) * scale, (w * ox - u * oz) * scale};
         Q[m] = {(u * oy - v * ox) * scale, R(0)};
     }
-    fft_line<R, N, E, -1>(Q, my, 1, tw, g);
-    fft_line<R, N, E, -1>(P, my, 1, tw, g);
+    fft_line<R, N, E, -1, true>(Q, my, 1, twl, g);
+    fft_line<R, N, E, -1, true>(P, my, 1, twl, g);
     // c2: Q_k is its half spectrum directly
 #pragma unroll
     for (int m = 0; m < E / 2; ++m) W[2 * FS + line * (N / 2) + g + m * G] = Q[m];
@@ -374,16 +414,18 @@ void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restri
     constexpr size_t FS = field_size(N);
     __shared__ cx<R> lds[T * N];
     __shared__ double red[2][NT];
+    __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
     const int t = threadIdx.x % T, g = threadIdx.x / T;
     const XCol<N> col(blockIdx.x * T + t);
 
     cx<R> nh[3][E];
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
+    for (int f = 0; f < 3; ++f)
 #pragma unroll
         for (int m = 0; m < E; ++m) nh[f][m] = W[f * FS + col.base + (size_t)(g + m * G) * col.rs];
-        fft_line<R, N, E, -1>(nh[f], lds + t, T, tw, g);
-    }
+    load_twiddles<R, N>(twl, tw);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true>(nh[f], lds + t, T, twl, g);
 
     const int ky = col.ky, kz = col.kz;
     const int lim = sa.mask_lim;

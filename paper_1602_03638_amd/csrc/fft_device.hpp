@@ -86,7 +86,11 @@ template <typename R, int RAD, int DIR> __device__ __forceinline__ void dft_smal
 
 // One Stockham stage S of the length-N line FFT (see the file comment).
 // lds + p * ps addresses element p of this thread's line in shared memory.
-template <typename R, int N, int E, int DIR, int S>
+// TWL: the twiddle table lives in shared memory and is re-read at every
+// stage (keeps it out of registers, which matters where a kernel holds
+// several lines per thread); otherwise it is read from global memory and
+// the compiler may keep it in registers across transforms.
+template <typename R, int N, int E, int DIR, int S, bool TWL = false>
 struct FftStage {
     static __device__ __forceinline__ void run(cx<R> (&v)[E], cx<R>* lds, int ps,
                                                const cx<R>* __restrict__ tw, int g) {
@@ -104,6 +108,7 @@ struct FftStage {
 #pragma unroll
             for (int r = 0; r < RAD; ++r) x[r] = v[q + r * Q];
             if constexpr (L > 1) {
+                if constexpr (TWL) asm volatile("" ::: "memory");
                 const cx<R>* w = tw + tw_offset(N, S) + j * (RAD - 1);
 #pragma unroll
                 for (int r = 1; r < RAD; ++r)
@@ -124,17 +129,25 @@ struct FftStage {
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = lds[(g + m * G) * ps];
             __syncthreads();
-            FftStage<R, N, E, DIR, S + 1>::run(v, lds, ps, tw, g);
+            FftStage<R, N, E, DIR, S + 1, TWL>::run(v, lds, ps, tw, g);
         }
     }
 };
 
 // Transform the line held in v (natural distribution in, natural out).
 // Every thread of the workgroup must call this (it contains barriers).
-template <typename R, int N, int E, int DIR>
+template <typename R, int N, int E, int DIR, bool TWL = false>
 __device__ __forceinline__ void fft_line(cx<R> (&v)[E], cx<R>* lds, int ps,
                                          const cx<R>* __restrict__ tw, int g) {
-    FftStage<R, N, E, DIR, 0>::run(v, lds, ps, tw, g);
+    FftStage<R, N, E, DIR, 0, TWL>::run(v, lds, ps, tw, g);
+}
+
+// Copy the twiddle table into shared memory (all threads of the workgroup
+// call this; ends with a barrier).
+template <typename R, int N>
+__device__ __forceinline__ void load_twiddles(cx<R>* twl, const cx<R>* __restrict__ tw) {
+    for (int i = threadIdx.x; i < tw_size(N); i += blockDim.x) twl[i] = tw[i];
+    __syncthreads();
 }
 
 }  // namespace dns
