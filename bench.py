@@ -21,12 +21,15 @@ METRIC = "ms per RK4 step at 512^3 (FP64 vs FP32) + HBM GB/s; ensemble steps/s"
 HBM_PEAK_GBPS = 8000.0
 N_DEFAULT, NU, DT = 512, 1.0 / 1600, 1e-3
 
-# Algorithmic HBM traffic of each kernel of one stage, in half-spectrum
-# fields C = N^2 (N/2+1) complex values (read + write); xrhs_rk4 averages
-# the four stages (N_hat reads 3C per stage plus RK4 state traffic 48C per
-# step).  One step moves 4 * 36 C + 60 C = 204 C.
-FIELDS_PER_LAUNCH = {"xinv_curl": 9.0, "yinv6": 12.0, "zcross": 9.0, "yfwd3": 6.0, "xrhs_rk4": 60.0 / 4}
-FIELDS_PER_STEP = 204.0
+# Algorithmic HBM traffic of each kernel, in half-spectrum fields
+# C = N^2 (N/2+1) complex values (read + write).  xrhs_rk4 averages the four
+# stages: N_hat reads 3C per stage plus RK4 state traffic of 48C per step.
+# xstage is xrhs_rk4 plus the 6C of inverse-x/curl fields it writes for the
+# next stage.  Unfused step: 4 * 36 C + 60 C = 204 C.  Fused step (the
+# default schedule): 4 * (12 + 9 + 6) C + 4 * 21 C = 192 C.
+FIELDS_PER_LAUNCH = {"xinv_curl": 9.0, "yinv6": 12.0, "zcross": 9.0, "yfwd3": 6.0, "xrhs_rk4": 60.0 / 4,
+                     "xstage": 60.0 / 4 + 6.0}
+FIELDS_PER_STEP = 192.0
 
 
 def field_bytes(N, dtype):
@@ -104,23 +107,32 @@ def sweep(N, dtype, reps=2):
     from paper_1602_03638_amd import Solver
 
     u0 = torch.from_numpy(workloads.taylor_green(N)).to(torch.float64 if dtype == "f64" else torch.float32)
-    s = Solver(N, NU, DT, dtype=dtype).set_velocity(u0.cuda().contiguous())
-    base = s.plan()
-    out = {"N": N, "dtype": dtype, "default_plan": base, "passes": {}}
-    for p, widths in s.plan_variants().items():
-        res = {}
-        for w in widths:
-            plan = dict(base)
-            plan[p] = w
-            if p in ("yinv6", "yfwd3"):
-                plan["yinv6"] = plan["yfwd3"] = w
-            s.set_plan(plan)
-            res[w] = round(s.profile_step(reps)[p], 4)
-        out["passes"][p] = res
-    s.set_plan(base)
-    out["autotuned_plan"] = s.autotune()
-    out["autotuned_ms"] = {k: round(v, 4) for k, v in s.profile_step(reps).items()}
-    s.close()
+    u0 = u0.cuda().contiguous()
+    out = {"N": N, "dtype": dtype, "passes": {}}
+    for fuse in (True, False):
+        s = Solver(N, NU, DT, dtype=dtype, fuse=fuse).set_velocity(u0)
+        base = s.plan()
+        out["default_plan"] = base
+        mine = ("yinv6", "zcross", "yfwd3", "xstage") if fuse else ("xinv_curl", "xrhs_rk4")
+        for p, widths in s.plan_variants().items():
+            if p not in mine:
+                continue
+            res = {}
+            for w in widths:
+                plan = dict(base)
+                plan[p] = w
+                if p in ("yinv6", "yfwd3"):
+                    plan["yinv6"] = plan["yfwd3"] = w
+                s.set_plan(plan)
+                s.profile_step(1)            # warm (rebuilds the fused work space)
+                res[w] = round(s.profile_step(reps)[p], 4)
+            out["passes"][p] = res
+        s.set_plan(base)
+        key = "fused" if fuse else "unfused"
+        out[f"autotuned_plan_{key}"] = s.autotune()
+        s.profile_step(1)
+        out[f"autotuned_ms_{key}"] = {k: round(v, 4) for k, v in s.profile_step(reps).items()}
+        s.close()
     print(json.dumps(out), flush=True)
     return 0
 

@@ -73,6 +73,10 @@ typedef struct dns_opts {
     int use_graph;    /* 1 = replay each RK4 step as one captured HIP graph
                          (default), 0 = launch kernels one by one */
     int autotune;     /* 1 = run dns_autotune at creation; default 0 */
+    int fuse;         /* 1 = fuse each stage's RHS/RK4 pass with the next
+                         stage's inverse x pass (16 kernels per step, default);
+                         0 = unfused schedule (20 kernels per step).  Both give
+                         bitwise identical results. */
 } dns_opts;
 
 typedef struct dns_ctx dns_t;
@@ -160,19 +164,20 @@ int dns_profile_step(dns_t* ctx, int nsteps, float* ms, const char** names, int 
 int dns_forward(dns_t* ctx, const void* u_dev, void* uhat_dev);
 int dns_inverse(dns_t* ctx, const void* uhat_dev, void* u_dev);
 
-/* Execution plan.  Each of the five kernels of an RK4 stage (in launch
- * order: inverse x pass with curl, inverse y pass, fused z pass, forward y
- * pass, forward x pass with the RHS and RK4 update) has several variants
+/* Execution plan.  Each of the six kernels (index order: inverse x pass
+ * with curl, inverse y pass, fused z pass, forward y pass, forward x pass
+ * with the RHS and RK4 update, and the latter fused with the next stage's
+ * inverse x pass) has several variants
  * that differ only in how many FFT lines share a workgroup (the "width");
  * every variant performs the same arithmetic per line, so results are
  * bitwise identical whichever is chosen.
  *
  * dns_autotune times every variant on the context's own buffers (reps
  * launches each, 0 = 3) and keeps the fastest; the velocity state is
- * preserved.  dns_get_plan writes the chosen widths (5 entries);
+ * preserved.  dns_get_plan writes the chosen widths (6 entries);
  * dns_set_plan selects variants by width (DNS_E_INVAL if a width does not
  * exist for this N and dtype); dns_plan_variants lists the widths available
- * for one kernel (pass index 0..4). */
+ * for one kernel (pass index 0..5). */
 int dns_autotune(dns_t* ctx, int reps);
 int dns_get_plan(const dns_t* ctx, int* widths, int max, int* count);
 int dns_set_plan(dns_t* ctx, const int* widths, int n);

@@ -35,7 +35,8 @@ class DnsError(RuntimeError):
 
 class dns_opts(ctypes.Structure):
     _fields_ = [("dealias", ctypes.c_int), ("diag_every", ctypes.c_int),
-                ("history_cap", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int)]
+                ("history_cap", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
+                ("fuse", ctypes.c_int)]
 
 
 _lib = None
@@ -133,7 +134,7 @@ class Solver:
     """
 
     def __init__(self, N, nu, dt, dtype="f64", dealias="text", diag_every=0, use_graph=True,
-                 history_cap=4096, stream=None, autotune=False):
+                 history_cap=4096, stream=None, autotune=False, fuse=True):
         import torch
         self._torch = torch
         lib = load_library()
@@ -148,6 +149,7 @@ class Solver:
         o.use_graph = 1 if use_graph else 0
         o.history_cap = int(history_cap)
         o.autotune = 1 if autotune else 0
+        o.fuse = 1 if fuse else 0
         self.history_cap = int(history_cap)
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -266,25 +268,26 @@ class Solver:
         n = ctypes.c_int()
         _check(load_library().dns_profile_step(self.handle, int(nsteps), ms, names, 16, ctypes.byref(n)),
                self.handle, "dns_profile_step")
-        return {names[i].decode(): float(ms[i]) for i in range(n.value)}
+        return {names[i].decode(): float(ms[i]) for i in range(n.value) if ms[i] > 0}
 
-    PASSES = ("xinv_curl", "yinv6", "zcross", "yfwd3", "xrhs_rk4")
+    PASSES = ("xinv_curl", "yinv6", "zcross", "yfwd3", "xrhs_rk4", "xstage")
 
     def autotune(self, reps=3):
         _check(load_library().dns_autotune(self.handle, int(reps)), self.handle, "dns_autotune")
         return self.plan()
 
     def plan(self):
-        w = (ctypes.c_int * 5)()
+        w = (ctypes.c_int * len(self.PASSES))()
         n = ctypes.c_int()
-        _check(load_library().dns_get_plan(self.handle, w, 5, ctypes.byref(n)), self.handle, "dns_get_plan")
+        _check(load_library().dns_get_plan(self.handle, w, len(self.PASSES), ctypes.byref(n)), self.handle,
+               "dns_get_plan")
         return dict(zip(self.PASSES, list(w)))
 
     def set_plan(self, widths):
         if isinstance(widths, dict):
             widths = [widths[p] for p in self.PASSES]
-        w = (ctypes.c_int * 5)(*[int(x) for x in widths])
-        _check(load_library().dns_set_plan(self.handle, w, 5), self.handle, "dns_set_plan")
+        w = (ctypes.c_int * len(self.PASSES))(*[int(x) for x in widths])
+        _check(load_library().dns_set_plan(self.handle, w, len(self.PASSES)), self.handle, "dns_set_plan")
         return self
 
     def plan_variants(self):

@@ -103,7 +103,8 @@ struct dns_ctx {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipEvent_t ev_prof[2] = {nullptr, nullptr};
     const dns::Ops* ops = nullptr;
-    int sel[dns::P_COUNT] = {0, 0, 0, 0, 0};   // chosen variant of each pass
+    int sel[dns::P_COUNT] = {0, 0, 0, 0, 0, 0};   // chosen variant of each pass
+    bool w_ready = false;           // W holds the inverse-x/curl fields of U0 (fused schedule)
     size_t cbytes = 0;              // bytes of one complex value
     size_t fbytes = 0;              // bytes of one half-spectrum field
     char* state = nullptr;          // U0 | U1 | Us, three fields each
@@ -181,23 +182,44 @@ void launch_pass(dns_t* c, int pass, int variant, int stage, double* diag, hipSt
         case dns::P_YINV6: o->yinv6[variant](c->work, c->tw, s); break;
         case dns::P_ZCROSS: o->zcross[variant](c->work, c->tw, s); break;
         case dns::P_YFWD3: o->yfwd3[variant](c->work, c->tw, s); break;
-        default: {
+        case dns::P_XRHS: {
             const dns::StageArgs a = stage_args(c, stage, diag);
             o->xrhs[variant](c->work, c->U0(), c->U1(), c->Us(), c->tw, a, s);
+            break;
+        }
+        default: {
+            const dns::StageArgs a = stage_args(c, stage, diag);
+            o->xstage[variant](c->work, c->U0(), c->U1(), c->Us(), c->tw, a, s);
         }
     }
 }
 
+// Unfused stage: inverse x (+curl), inverse y, z, forward y, RHS + RK4.
 void enqueue_stage(dns_t* c, int stage, bool with_diag, hipStream_t s) {
-    for (int p = 0; p < dns::P_COUNT; ++p)
+    for (int p = dns::P_XINV; p <= dns::P_XRHS; ++p)
         launch_pass(c, p, c->sel[p], stage, (p == dns::P_XRHS && stage == 3 && with_diag) ? c->part : nullptr, s);
 }
 
+int diag_groups(const dns_t* c) {
+    return c->opts.fuse ? c->ops->xstage_groups[c->sel[dns::P_XSTAGE]] : c->ops->xrhs_groups[c->sel[dns::P_XRHS]];
+}
+
+// One RK4 step.  Fused schedule: W already holds the inverse-x/curl fields
+// of U0 (prepared by the previous step's last kernel or by one k_xinv_curl
+// launch), and each stage ends with the RHS pass fused with the next
+// stage's inverse x pass, so a step is 16 kernels.  Unfused: 20 kernels.
 void enqueue_step(dns_t* c, bool with_diag, hipStream_t s) {
-    for (int st = 0; st < 4; ++st) enqueue_stage(c, st, with_diag, s);
+    if (c->opts.fuse) {
+        for (int st = 0; st < 4; ++st) {
+            for (int p = dns::P_YINV6; p <= dns::P_YFWD3; ++p) launch_pass(c, p, c->sel[p], st, nullptr, s);
+            launch_pass(c, dns::P_XSTAGE, c->sel[dns::P_XSTAGE], st, (st == 3 && with_diag) ? c->part : nullptr, s);
+        }
+    } else {
+        for (int st = 0; st < 4; ++st) enqueue_stage(c, st, with_diag, s);
+    }
     if (with_diag)
-        dns::launch_diag_final(c->part, c->ops->xrhs_groups[c->sel[dns::P_XRHS]], inv_norm(c->N), c->dout,
-                               c->hist, c->hist_count, c->opts.history_cap, s);
+        dns::launch_diag_final(c->part, diag_groups(c), inv_norm(c->N), c->dout, c->hist, c->hist_count,
+                               c->opts.history_cap, s);
 }
 
 int build_graph(dns_t* c, int which) {
@@ -264,6 +286,7 @@ void dns_default_opts(dns_opts* o) {
     o->history_cap = 4096;
     o->use_graph = 1;
     o->autotune = 0;
+    o->fuse = 1;
 }
 
 size_t dns_state_bytes(int N, int dtype) {
@@ -286,7 +309,7 @@ int dns_create_ex(int N, double nu, double dt, int dtype, const dns_opts* opts, 
     dns_default_opts(&o);
     if (opts) o = *opts;
     if ((o.dealias != DNS_DEALIAS_TEXT && o.dealias != DNS_DEALIAS_APPENDIX) || o.diag_every < 0 ||
-        o.history_cap < 0)
+        o.history_cap < 0 || (o.fuse != 0 && o.fuse != 1))
         return DNS_E_INVAL;
 
     dns_t* c = new (std::nothrow) dns_ctx();
@@ -375,6 +398,7 @@ int dns_set_velocity(dns_t* c, const void* u) {
     if (!c || !u) return fail(c, DNS_E_INVAL, "null argument");
     int r = enter(c);
     if (r) return r;
+    c->w_ready = false;
     c->ops->zr2c(u, c->work, c->tw, c->s);
     c->ops->yfwd3[c->sel[dns::P_YFWD3]](c->work, c->tw, c->s);
     c->ops->xfwd3(c->work, c->U0(), c->tw, c->s);
@@ -387,6 +411,7 @@ int dns_set_spectral(dns_t* c, const void* uh) {
     if (!c || !uh) return fail(c, DNS_E_INVAL, "null argument");
     int r = enter(c);
     if (r) return r;
+    c->w_ready = false;
     c->ops->layout(uh, c->U0(), true, c->s);
     if ((r = launched(c, "set_spectral"))) return r;
     if ((r = reset_counters(c))) return r;
@@ -408,6 +433,7 @@ int dns_get_velocity(dns_t* c, void* u) {
     if (!c->has_state) return fail(c, DNS_E_STATE, "no velocity set");
     int r = enter(c);
     if (r) return r;
+    c->w_ready = false;
     c->ops->xinv3(c->U0(), c->work, c->tw, c->s);
     c->ops->yinv3(c->work, c->tw, c->s);
     c->ops->zc2r(c->work, u, c->tw, c->s);
@@ -419,6 +445,7 @@ int dns_forward(dns_t* c, const void* u, void* uh) {
     if (!c || !u || !uh) return fail(c, DNS_E_INVAL, "null argument");
     int r = enter(c);
     if (r) return r;
+    c->w_ready = false;
     c->ops->zr2c(u, c->work, c->tw, c->s);
     c->ops->yfwd3[c->sel[dns::P_YFWD3]](c->work, c->tw, c->s);
     c->ops->xfwd3(c->work, c->Us(), c->tw, c->s);
@@ -431,6 +458,7 @@ int dns_inverse(dns_t* c, const void* uh, void* u) {
     if (!c || !u || !uh) return fail(c, DNS_E_INVAL, "null argument");
     int r = enter(c);
     if (r) return r;
+    c->w_ready = false;
     c->ops->layout(uh, c->Us(), true, c->s);
     c->ops->xinv3(c->Us(), c->work, c->tw, c->s);
     c->ops->yinv3(c->work, c->tw, c->s);
@@ -445,6 +473,10 @@ int dns_step(dns_t* c, int nsteps) {
     if (nsteps == 0) return DNS_OK;
     int r = enter(c);
     if (r) return r;
+    if (c->opts.fuse && !c->w_ready) {
+        launch_pass(c, dns::P_XINV, c->sel[dns::P_XINV], 0, nullptr, c->s);
+        if ((r = launched(c, "xinv_curl"))) return r;
+    }
     for (int i = 0; i < nsteps; ++i) {
         const long long n = c->steps + 1;
         const bool diag = c->opts.diag_every > 0 && (n % c->opts.diag_every) == 0;
@@ -457,6 +489,7 @@ int dns_step(dns_t* c, int nsteps) {
         }
         c->steps = n;
     }
+    c->w_ready = c->opts.fuse != 0;
     return leave(c);
 }
 
@@ -465,6 +498,7 @@ int dns_rhs(dns_t* c, void* out) {
     if (!c->has_state) return fail(c, DNS_E_STATE, "no velocity set");
     int r = enter(c);
     if (r) return r;
+    c->w_ready = false;
     enqueue_stage(c, -1, false, c->s);
     c->ops->layout(c->U1(), out, false, c->s);
     if ((r = launched(c, "rhs"))) return r;
@@ -522,32 +556,47 @@ int dns_synchronize(dns_t* c) {
     return DNS_OK;
 }
 
-static const char* kPassNames[dns::P_COUNT] = {"xinv_curl", "yinv6", "zcross", "yfwd3", "xrhs_rk4"};
+static const char* kPassNames[dns::P_COUNT] = {"xinv_curl", "yinv6", "zcross", "yfwd3", "xrhs_rk4", "xstage"};
 
 int dns_profile_step(dns_t* c, int nsteps, float* ms, const char** names, int max, int* count) {
     if (!c || !ms || !count || nsteps <= 0 || max < 0) return fail(c, DNS_E_INVAL, "bad argument");
     if (!c->has_state) return fail(c, DNS_E_STATE, "no velocity set");
     int r = enter(c);
     if (r) return r;
-    double acc[dns::P_COUNT] = {0, 0, 0, 0, 0};
+    double acc[dns::P_COUNT] = {0, 0, 0, 0, 0, 0};
+    int launches[dns::P_COUNT] = {0, 0, 0, 0, 0, 0};
+    auto timed = [&](int k, int st) -> int {
+        DNS_TRY(c, hipEventRecord(c->ev_prof[0], c->s));
+        launch_pass(c, k, c->sel[k], st, nullptr, c->s);
+        int rr = launched(c, kPassNames[k]);
+        if (rr) return rr;
+        DNS_TRY(c, hipEventRecord(c->ev_prof[1], c->s));
+        DNS_TRY(c, hipEventSynchronize(c->ev_prof[1]));
+        float t = 0.f;
+        DNS_TRY(c, hipEventElapsedTime(&t, c->ev_prof[0], c->ev_prof[1]));
+        acc[k] += t;
+        launches[k] += 1;
+        return DNS_OK;
+    };
     for (int n = 0; n < nsteps; ++n) {
-        for (int st = 0; st < 4; ++st) {
-            for (int k = 0; k < dns::P_COUNT; ++k) {
-                DNS_TRY(c, hipEventRecord(c->ev_prof[0], c->s));
-                launch_pass(c, k, c->sel[k], st, nullptr, c->s);
-                if ((r = launched(c, kPassNames[k]))) return r;
-                DNS_TRY(c, hipEventRecord(c->ev_prof[1], c->s));
-                DNS_TRY(c, hipEventSynchronize(c->ev_prof[1]));
-                float t = 0.f;
-                DNS_TRY(c, hipEventElapsedTime(&t, c->ev_prof[0], c->ev_prof[1]));
-                acc[k] += t;
+        if (c->opts.fuse) {
+            if (!c->w_ready && (r = timed(dns::P_XINV, 0))) return r;
+            for (int st = 0; st < 4; ++st) {
+                for (int k = dns::P_YINV6; k <= dns::P_YFWD3; ++k)
+                    if ((r = timed(k, st))) return r;
+                if ((r = timed(dns::P_XSTAGE, st))) return r;
             }
+            c->w_ready = true;
+        } else {
+            for (int st = 0; st < 4; ++st)
+                for (int k = dns::P_XINV; k <= dns::P_XRHS; ++k)
+                    if ((r = timed(k, st))) return r;
         }
         c->steps += 1;
     }
     const int m = max < dns::P_COUNT ? max : dns::P_COUNT;
     for (int k = 0; k < m; ++k) {
-        ms[k] = (float)(acc[k] / (4.0 * nsteps));
+        ms[k] = launches[k] ? (float)(acc[k] / launches[k]) : 0.f;
         if (names) names[k] = kPassNames[k];
     }
     *count = m;
@@ -580,6 +629,7 @@ int dns_autotune(dns_t* c, int reps) {
         }
         c->sel[p] = bestv;
     }
+    c->w_ready = false;
     return leave(c);
 }
 
@@ -604,6 +654,7 @@ int dns_set_plan(dns_t* c, const int* widths, int n) {
     for (auto& g : c->gexec)
         if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
     for (int p = 0; p < dns::P_COUNT; ++p) c->sel[p] = sel[p];
+    c->w_ready = false;
     return DNS_OK;
 }
 

@@ -21,14 +21,18 @@ template <typename R, int N> struct Impl {
     template <int T> static constexpr bool x_ok() {
         return T <= N && G * T <= 1024 && (size_t)T * N * CB <= LDS_LIMIT;
     }
+    // The RHS/RK4 passes hold three lines plus state per thread: in FP64
+    // their 1024-thread shapes (128 registers per thread) only spill.
     template <int T> static constexpr bool xr_ok() {
-        return x_ok<T>() && (size_t)T * N * CB + 2 * 8 * (size_t)G * T <= LDS_LIMIT;
+        return x_ok<T>() && (sizeof(R) == 4 || G * T <= 512) &&
+               (size_t)T * N * CB + 2 * 8 * (size_t)G * T <= LDS_LIMIT;
     }
     template <int T> static constexpr bool y_ok() {
         return T <= N / 2 && G * T <= 1024 && (size_t)T * N * CB <= LDS_LIMIT;
     }
     template <int L> static constexpr bool z_ok() {
-        return L <= N * N && G * L <= 1024 && (size_t)L * N * CB <= LDS_LIMIT;
+        return L <= N * N && G * L <= 1024 &&
+               (size_t)L * padded_line<N>(true) * CB + (size_t)tw_size(N) * CB <= LDS_LIMIT;
     }
     template <int T> static constexpr int x_groups() { return XCOLS / T + N / T; }
 
@@ -50,11 +54,39 @@ template <typename R, int N> struct Impl {
         const R scale = (R)std::ldexp(1.0, -6 * ilog2(N));
         hipLaunchKernelGGL((k_zcross<R, N, L>), dim3((N * N) / L), dim3(G * L), 0, s, (C*)W, (const C*)tw, scale);
     }
+    template <int T, int ST>
+    static void xrhs_st(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
+                        hipStream_t s) {
+        hipLaunchKernelGGL((k_xrhs<R, N, T, ST>), dim3(x_groups<T>()), dim3(G * T), 0, s,
+                           (const C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a);
+    }
     template <int T>
     static void xrhs(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
                      hipStream_t s) {
-        hipLaunchKernelGGL((k_xrhs<R, N, T>), dim3(x_groups<T>()), dim3(G * T), 0, s,
-                           (const C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a);
+        switch (a.stage) {
+            case 0: xrhs_st<T, 0>(W, U0, U1, Us, tw, a, s); break;
+            case 1: xrhs_st<T, 1>(W, U0, U1, Us, tw, a, s); break;
+            case 2: xrhs_st<T, 2>(W, U0, U1, Us, tw, a, s); break;
+            case 3: xrhs_st<T, 3>(W, U0, U1, Us, tw, a, s); break;
+            default: xrhs_st<T, -1>(W, U0, U1, Us, tw, a, s); break;
+        }
+    }
+
+    template <int T, int ST>
+    static void xstage_st(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
+                          hipStream_t s) {
+        hipLaunchKernelGGL((k_xstage<R, N, T, ST>), dim3(x_groups<T>()), dim3(G * T), 0, s,
+                           (C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a);
+    }
+    template <int T>
+    static void xstage(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
+                       hipStream_t s) {
+        switch (a.stage) {
+            case 0: xstage_st<T, 0>(W, U0, U1, Us, tw, a, s); break;
+            case 1: xstage_st<T, 1>(W, U0, U1, Us, tw, a, s); break;
+            case 2: xstage_st<T, 2>(W, U0, U1, Us, tw, a, s); break;
+            default: xstage_st<T, 3>(W, U0, U1, Us, tw, a, s); break;
+        }
     }
 
     // ---- standalone transforms (fixed shapes) -------------------------------
@@ -105,6 +137,10 @@ template <typename R, int N> struct Impl {
             o.xrhs[n] = &xrhs<T>;
             o.xrhs_groups[n] = x_groups<T>();
             o.width[P_XRHS][n++] = T;
+            int& k = o.nvar[P_XSTAGE];
+            o.xstage[k] = &xstage<T>;
+            o.xstage_groups[k] = x_groups<T>();
+            o.width[P_XSTAGE][k++] = T;
         }
     }
     template <int T> static void add_y(Ops& o) {
@@ -137,14 +173,15 @@ template <typename R, int N> struct Impl {
         o.N = N;
         o.real_size = sizeof(R);
         o.tw_count = tw_size(N) > 0 ? tw_size(N) : 1;
-        add_x<2>(o); add_x<4>(o); add_x<8>(o); add_x<16>(o);
+        add_x<4>(o); add_x<8>(o); add_x<16>(o);
         add_y<4>(o); add_y<8>(o); add_y<16>(o); add_y<32>(o);
         add_z<1>(o); add_z<2>(o); add_z<4>(o); add_z<8>(o);
-        // defaults: 128-byte row segments in the x passes, 256-byte in the
-        // y passes, four z lines per workgroup (measured on MI355X)
-        const int xw = (int)(128 / CB), yw = (int)(256 / CB);
+        // defaults: 128-byte row segments in the x and y passes, four z lines
+        // per workgroup (the fastest measured on MI355X at 256^3 and 512^3)
+        const int xw = (int)(128 / CB), yw = (int)(128 / CB);
         o.def[P_XINV] = pick(o, P_XINV, xw);
         o.def[P_XRHS] = pick(o, P_XRHS, xw);
+        o.def[P_XSTAGE] = pick(o, P_XSTAGE, xw);
         o.def[P_YINV6] = pick(o, P_YINV6, yw);
         o.def[P_YFWD3] = pick(o, P_YFWD3, yw);
         o.def[P_ZCROSS] = pick(o, P_ZCROSS, 4);

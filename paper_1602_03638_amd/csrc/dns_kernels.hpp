@@ -23,27 +23,50 @@ namespace dns {
 __device__ __forceinline__ int kfreq(int i, int n) { return i < n / 2 ? i : i - n; }
 
 // Column c of the x pass: c < N*N/2 is (iy, iz) = (c / (N/2), c % (N/2)) of
-// the main block; c >= N*N/2 is iy = c - N*N/2 of the Nyquist plane.
-template <int N> struct XCol {
-    size_t base;   // offset of row 0 in a field
-    size_t rs;     // offset between rows (consecutive ix)
+// the main block; c >= N*N/2 is iy = c - N*N/2 of the Nyquist plane.  A
+// workgroup's columns lie in one of the two blocks (tile widths divide
+// both), so the kernels branch once on the block and the row stride is a
+// compile-time constant, which lets the compiler see that different rows
+// never alias.
+template <int N, bool NYQ> struct XCol {
+    static constexpr unsigned RS = NYQ ? (unsigned)N : (unsigned)(N * (N / 2));   // offset between rows
+    unsigned base;   // offset of row 0 in a field
     int ky, kz;
-    __device__ __forceinline__ XCol(int c) {
+    __device__ __forceinline__ explicit XCol(int c) {
         constexpr int HC = N * (N / 2);
-        if (c < HC) {
-            base = (size_t)c;
-            rs = (size_t)HC;
+        if constexpr (!NYQ) {
+            base = (unsigned)c;
             ky = kfreq(c / (N / 2), N);
             kz = c % (N / 2);
         } else {
             const int iy = c - HC;
-            base = main_size(N) + (size_t)iy;
-            rs = (size_t)N;
+            base = (unsigned)main_size(N) + (unsigned)iy;
             ky = kfreq(iy, N);
             kz = N / 2;
         }
     }
+    __device__ __forceinline__ unsigned at(int row) const { return base + (unsigned)row * RS; }
 };
+
+// Element (row g + m G) of field f of the x tile, addressed as a uniform
+// base (field + m G rows, kept in scalar registers) plus one per-thread
+// 32-bit byte offset (column + g rows) shared by every field and row, so
+// that a thread holds one address register instead of one per element.
+template <typename C, int N, int G, bool NYQ>
+struct XAddr {
+    unsigned tb;                                  // byte offset of (column, row g)
+    __device__ __forceinline__ XAddr(const XCol<N, NYQ>& col, int g)
+        : tb((col.base + (unsigned)g * XCol<N, NYQ>::RS) * (unsigned)sizeof(C)) {}
+    __device__ __forceinline__ C& operator()(C* F, int m) const {
+        return *reinterpret_cast<C*>(reinterpret_cast<char*>(F + (size_t)m * G * XCol<N, NYQ>::RS) + tb);
+    }
+    __device__ __forceinline__ const C& operator()(const C* F, int m) const {
+        return *reinterpret_cast<const C*>(reinterpret_cast<const char*>(F + (size_t)m * G * XCol<N, NYQ>::RS) + tb);
+    }
+};
+
+// Number of x-pass workgroups of width T over the main block.
+template <int N, int T> constexpr int x_main_tiles() { return (N * (N / 2)) / T; }
 
 // ---------------------------------------------------------------------------
 // Pass 1: inverse x transform of u_hat (3 fields at U) and of the vorticity
@@ -57,20 +80,16 @@ template <int N> struct XCol {
 // once.  Output fields at W: u, v, w, omega_x, omega_y, omega_z.
 // T lines (consecutive columns) per workgroup.
 // ---------------------------------------------------------------------------
-template <typename R, int N, int T>
-__global__ __launch_bounds__(N / 8 * T)
-void k_xinv_curl(const cx<R>* __restrict__ U, cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
+template <typename R, int N, int T, bool NYQ>
+__device__ __forceinline__ void xinv_curl_tile(const cx<R>* __restrict__ U, cx<R>* __restrict__ W,
+                                               cx<R>* lds, const cx<R>* twl) {
     constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
-    __shared__ cx<R> lds[T * N];
-    __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
     const int t = threadIdx.x % T, g = threadIdx.x / T;
-    const XCol<N> col(blockIdx.x * T + t);
-    const unsigned b0 = col.base, rs = col.rs;
+    const XCol<N, NYQ> col(blockIdx.x * T + t);
     const R ky = (R)col.ky, kz = (R)col.kz;
     cx<R>* lt = lds + t;
-    auto at = [&](int m) { return b0 + (unsigned)(g + m * G) * rs; };
-    load_twiddles<R, N>(twl, tw);
+    const XAddr<cx<R>, N, G, NYQ> A(col, g);
 
     // Loads are issued as early as the register budget allows so that their
     // latency overlaps the transforms (a barrier inside a transform keeps
@@ -78,63 +97,79 @@ void k_xinv_curl(const cx<R>* __restrict__ U, cx<R>* __restrict__ W, const cx<R>
     cx<R> a[E], b[E], c[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        c[m] = U[at(m)];                 // u_hat
-        a[m] = U[FS + at(m)];            // v_hat
+        c[m] = A(U, m);                 // u_hat
+        a[m] = A(U + FS, m);            // v_hat
     }
     fft_line<R, N, E, +1, true>(c, lt, T, twl, g);          // c = U
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        W[at(m)] = c[m];
+        A(W, m) = c[m];
         b[m] = cscale<R>(a[m], (R)kfreq(g + m * G, N));
     }
     fft_line<R, N, E, +1, true>(b, lt, T, twl, g);          // b = F(kx v_hat)
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        W[5 * FS + at(m)] = cmuli<R>(csub<R>(b[m], cscale<R>(c[m], ky)));   // omega_z
-        b[m] = U[2 * FS + at(m)];        // w_hat, in flight during the next transform
+        A(W + 5 * FS, m) = cmuli<R>(csub<R>(b[m], cscale<R>(c[m], ky)));   // omega_z
+        b[m] = A(U + 2 * FS, m);        // w_hat, in flight during the next transform
     }
     fft_line<R, N, E, +1, true>(a, lt, T, twl, g);          // a = V
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        W[FS + at(m)] = a[m];
+        A(W + FS, m) = a[m];
         b[m] = cscale<R>(b[m], (R)kfreq(g + m * G, N));
     }
     fft_line<R, N, E, +1, true>(b, lt, T, twl, g);          // b = F(kx w_hat)
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        W[4 * FS + at(m)] = cmuli<R>(csub<R>(cscale<R>(c[m], kz), b[m]));   // omega_y
-        c[m] = U[2 * FS + at(m)];        // w_hat again (recently read: cache hit)
+        A(W + 4 * FS, m) = cmuli<R>(csub<R>(cscale<R>(c[m], kz), b[m]));   // omega_y
+        c[m] = A(U + 2 * FS, m);        // w_hat again (recently read: cache hit)
     }
     fft_line<R, N, E, +1, true>(c, lt, T, twl, g);          // c = W
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        W[2 * FS + at(m)] = c[m];
-        W[3 * FS + at(m)] = cmuli<R>(csub<R>(cscale<R>(c[m], ky), cscale<R>(a[m], kz)));   // omega_x
+        A(W + 2 * FS, m) = c[m];
+        A(W + 3 * FS, m) = cmuli<R>(csub<R>(cscale<R>(c[m], ky), cscale<R>(a[m], kz)));   // omega_x
     }
+}
+
+template <typename R, int N, int T>
+__global__ __launch_bounds__(N / 8 * T)
+void k_xinv_curl(const cx<R>* __restrict__ U, cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
+    __shared__ cx<R> lds[T * N];
+    __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
+    load_twiddles<R, N>(twl, tw);
+    if ((int)blockIdx.x < x_main_tiles<N, T>()) xinv_curl_tile<R, N, T, false>(U, W, lds, twl);
+    else xinv_curl_tile<R, N, T, true>(U, W, lds, twl);
 }
 
 // Plain inverse (DIR = +1) or forward (DIR = -1) x transform of NF fields
 // from S into D (used by the standalone 3D transforms).
-template <typename R, int N, int T, int DIR, int NF>
-__global__ __launch_bounds__(N / 8 * T)
-void k_xplain(const cx<R>* __restrict__ S, cx<R>* __restrict__ D, const cx<R>* __restrict__ tw) {
+template <typename R, int N, int T, int DIR, int NF, bool NYQ>
+__device__ __forceinline__ void xplain_tile(const cx<R>* __restrict__ S, cx<R>* __restrict__ D,
+                                            const cx<R>* __restrict__ tw, cx<R>* lds) {
     constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
-    __shared__ cx<R> lds[T * N];
     const int t = threadIdx.x % T, g = threadIdx.x / T;
-    const XCol<N> col(blockIdx.x * T + t);
-    const unsigned b0 = col.base, rs = col.rs;
+    const XCol<N, NYQ> col(blockIdx.x * T + t);
 #pragma unroll 1
     for (int f = 0; f < NF; ++f) {
         const cx<R>* src = S + f * FS;
         cx<R>* dst = D + f * FS;
         cx<R> a[E];
 #pragma unroll
-        for (int m = 0; m < E; ++m) a[m] = src[b0 + (unsigned)(g + m * G) * rs];
+        for (int m = 0; m < E; ++m) a[m] = src[col.at(g + m * G)];
         fft_line<R, N, E, DIR>(a, lds + t, T, tw, g);
 #pragma unroll
-        for (int m = 0; m < E; ++m) dst[b0 + (unsigned)(g + m * G) * rs] = a[m];
+        for (int m = 0; m < E; ++m) dst[col.at(g + m * G)] = a[m];
     }
+}
+
+template <typename R, int N, int T, int DIR, int NF>
+__global__ __launch_bounds__(N / 8 * T)
+void k_xplain(const cx<R>* __restrict__ S, cx<R>* __restrict__ D, const cx<R>* __restrict__ tw) {
+    __shared__ cx<R> lds[T * N];
+    if ((int)blockIdx.x < x_main_tiles<N, T>()) xplain_tile<R, N, T, DIR, NF, false>(S, D, tw, lds);
+    else xplain_tile<R, N, T, DIR, NF, true>(S, D, tw, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -171,7 +206,8 @@ __global__ __launch_bounds__(N / 8 * L)
 void k_yline_nyq(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
     constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
-    __shared__ cx<R> lds[L * N];
+    constexpr int LP = padded_line<N>(true);
+    __shared__ cx<R> lds[L * LP];
     const int g = threadIdx.x % G, l = threadIdx.x / G;
     const int ix = blockIdx.x * L + l;
     const size_t base = main_size(N) + (size_t)ix * N;
@@ -180,7 +216,7 @@ void k_yline_nyq(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
         cx<R> a[E];
 #pragma unroll
         for (int m = 0; m < E; ++m) a[m] = W[f * FS + base + g + m * G];
-        fft_line<R, N, E, DIR>(a, lds + l * N, 1, tw, g);
+        fft_line<R, N, E, DIR, false, true>(a, lds + l * LP, 1, tw, g);
 #pragma unroll
         for (int m = 0; m < E; ++m) W[f * FS + base + g + m * G] = a[m];
     }
@@ -237,11 +273,12 @@ __global__ __launch_bounds__(N / 8 * L)
 void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale) {
     constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
-    __shared__ cx<R> lds[L * N];
+    constexpr int LP = padded_line<N>(true);
+    __shared__ cx<R> lds[L * LP];
     __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
     const int g = threadIdx.x % G, l = threadIdx.x / G;
     const size_t line = (size_t)blockIdx.x * L + l;
-    cx<R>* my = lds + l * N;
+    cx<R>* my = lds + l * LP;
 
     // Each stored coefficient is loaded once (lower half k < N/2 plus the
     // Nyquist value), all six lines before the first transform so that the
@@ -283,7 +320,7 @@ void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale) {
         __syncthreads();
     }
 #pragma unroll
-    for (int p = 0; p < 3; ++p) fft_line<R, N, E, +1, true>(z[p], my, 1, twl, g);
+    for (int p = 0; p < 3; ++p) fft_line<R, N, E, +1, true, true>(z[p], my, 1, twl, g);
     // z[0] = (u, v), z[1] = (w, omega_x), z[2] = (omega_y, omega_z)
     cx<R> P[E], Q[E];
 #pragma unroll
@@ -293,8 +330,8 @@ void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale) {
         P[m] = {(v * oz - w * oy) * scale, (w * ox - u * oz) * scale};
         Q[m] = {(u * oy - v * ox) * scale, R(0)};
     }
-    fft_line<R, N, E, -1, true>(Q, my, 1, twl, g);
-    fft_line<R, N, E, -1, true>(P, my, 1, twl, g);
+    fft_line<R, N, E, -1, true, true>(Q, my, 1, twl, g);
+    fft_line<R, N, E, -1, true, true>(P, my, 1, twl, g);
     // c2: Q_k is its half spectrum directly
 #pragma unroll
     for (int m = 0; m < E / 2; ++m) W[2 * FS + line * (N / 2) + g + m * G] = Q[m];
@@ -327,10 +364,11 @@ void k_zr2c(const R* __restrict__ u, cx<R>* __restrict__ W, const cx<R>* __restr
     constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
     constexpr size_t PS = (size_t)N * N * N;
-    __shared__ cx<R> lds[L * N];
+    constexpr int LP = padded_line<N>(true);
+    __shared__ cx<R> lds[L * LP];
     const int g = threadIdx.x % G, l = threadIdx.x / G;
     const size_t line = (size_t)blockIdx.x * L + l;
-    cx<R>* my = lds + l * N;
+    cx<R>* my = lds + l * LP;
     cx<R> P[E], Q[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -338,8 +376,8 @@ void k_zr2c(const R* __restrict__ u, cx<R>* __restrict__ W, const cx<R>* __restr
         P[m] = {u[o], u[PS + o]};
         Q[m] = {u[2 * PS + o], R(0)};
     }
-    fft_line<R, N, E, -1>(Q, my, 1, tw, g);
-    fft_line<R, N, E, -1>(P, my, 1, tw, g);
+    fft_line<R, N, E, -1, false, true>(Q, my, 1, tw, g);
+    fft_line<R, N, E, -1, false, true>(P, my, 1, tw, g);
 #pragma unroll
     for (int m = 0; m < E / 2; ++m) W[2 * FS + line * (N / 2) + g + m * G] = Q[m];
     if (g == 0) W[2 * FS + main_size(N) + line] = Q[E / 2];
@@ -370,18 +408,19 @@ void k_zc2r(const cx<R>* __restrict__ W, R* __restrict__ u, const cx<R>* __restr
     constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
     constexpr size_t PS = (size_t)N * N * N;
-    __shared__ cx<R> lds[L * N];
+    constexpr int LP = padded_line<N>(true);
+    __shared__ cx<R> lds[L * LP];
     const int g = threadIdx.x % G, l = threadIdx.x / G;
     const size_t line = (size_t)blockIdx.x * L + l;
-    cx<R>* my = lds + l * N;
+    cx<R>* my = lds + l * LP;
     cx<R> a[E], b[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         a[m] = zpair_load<R, N>(W, W + FS, line, g + m * G);
         b[m] = zline_load<R, N>(W + 2 * FS, line, g + m * G);
     }
-    fft_line<R, N, E, +1>(a, my, 1, tw, g);
-    fft_line<R, N, E, +1>(b, my, 1, tw, g);
+    fft_line<R, N, E, +1, false, true>(a, my, 1, tw, g);
+    fft_line<R, N, E, +1, false, true>(b, my, 1, tw, g);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const size_t o = line * N + g + m * G;
@@ -405,37 +444,28 @@ void k_zc2r(const cx<R>* __restrict__ W, R* __restrict__ u, const cx<R>* __restr
 // of w |u_hat|^2 and w |k x u_hat|^2 of the new state (w = 1 on the kz = 0
 // and kz = N/2 planes, 2 elsewhere) to diag[2 blockIdx], diag[2 blockIdx + 1].
 // ---------------------------------------------------------------------------
-template <typename R, int N, int T>
-__global__ __launch_bounds__(N / 8 * T)
-void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
-            cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa) {
-    constexpr int E = 8, G = N / E;
-    constexpr int NT = G * T;
+// The mask / projection / viscous / RK4 update of one x tile, shared by the
+// RHS pass and the fused stage pass.  nh holds the x-transformed N_hat on
+// entry; on return it holds the input of the next stage (Us for stages 0..2,
+// the new U0 for stage 3, R for stage -1), which the fused pass transforms
+// on without reading it back.
+template <typename R, int N, int E, int STAGE, bool NYQ>
+__device__ __forceinline__ void rk_apply_stage(cx<R> (&nh)[3][E], const XCol<N, NYQ>& col, int g,
+                                               cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
+                                               cx<R>* __restrict__ Us, const StageArgs& sa, double& e_acc,
+                                               double& w_acc) {
+    constexpr int G = N / E;
     constexpr size_t FS = field_size(N);
-    __shared__ cx<R> lds[T * N];
-    __shared__ double red[2][NT];
-    __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
-    const int t = threadIdx.x % T, g = threadIdx.x / T;
-    const XCol<N> col(blockIdx.x * T + t);
-
-    cx<R> nh[3][E];
-#pragma unroll
-    for (int f = 0; f < 3; ++f)
-#pragma unroll
-        for (int m = 0; m < E; ++m) nh[f][m] = W[f * FS + col.base + (size_t)(g + m * G) * col.rs];
-    load_twiddles<R, N>(twl, tw);
-#pragma unroll
-    for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true>(nh[f], lds + t, T, twl, g);
-
     const int ky = col.ky, kz = col.kz;
     const int lim = sa.mask_lim;
     const bool keep_yz = (3 * abs(ky) < lim) && (3 * abs(kz) < lim);
     const R nu = (R)sa.nu, ca = (R)sa.ca, cb = (R)sa.cb;
-    double e_acc = 0.0, w_acc = 0.0;
+    const XAddr<cx<R>, N, G, NYQ> A(col, g);
+
+    // dealias and project: N_hat -= k (k . N_hat) / |k|^2
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int kx = kfreq(g + m * G, N);
-        const size_t o = col.base + (size_t)(g + m * G) * col.rs;
         const bool keep = keep_yz && (3 * abs(kx) < lim);
         const int k2 = kx * kx + ky * ky + kz * kz;
         cx<R> n0 = nh[0][m], n1 = nh[1][m], n2 = nh[2][m];
@@ -446,45 +476,85 @@ void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restri
         const R inv = k2 > 0 ? R(1) / (R)k2 : R(0);
         // P_hat = sum_i N_i k_i / |k|^2
         const cx<R> P = {(n0.x * fx + n1.x * fy + n2.x * fz) * inv, (n0.y * fx + n1.y * fy + n2.y * fz) * inv};
-        n0 = csub<R>(n0, cscale<R>(P, fx));
-        n1 = csub<R>(n1, cscale<R>(P, fy));
-        n2 = csub<R>(n2, cscale<R>(P, fz));
-        const R visc = nu * (R)k2;
-        cx<R> s0, s1, s2;
-        if (sa.stage <= 0) {
-            s0 = U0[o]; s1 = U0[FS + o]; s2 = U0[2 * FS + o];
-        } else {
-            s0 = Us[o]; s1 = Us[FS + o]; s2 = Us[2 * FS + o];
-        }
-        const cx<R> r0 = csub<R>(n0, cscale<R>(s0, visc));
-        const cx<R> r1 = csub<R>(n1, cscale<R>(s1, visc));
-        const cx<R> r2 = csub<R>(n2, cscale<R>(s2, visc));
-        if (sa.stage < 0) {
-            U1[o] = r0; U1[FS + o] = r1; U1[2 * FS + o] = r2;
-        } else if (sa.stage == 0) {
-            U1[o] = cadd<R>(s0, cscale<R>(r0, ca));
-            U1[FS + o] = cadd<R>(s1, cscale<R>(r1, ca));
-            U1[2 * FS + o] = cadd<R>(s2, cscale<R>(r2, ca));
-            Us[o] = cadd<R>(s0, cscale<R>(r0, cb));
-            Us[FS + o] = cadd<R>(s1, cscale<R>(r1, cb));
-            Us[2 * FS + o] = cadd<R>(s2, cscale<R>(r2, cb));
-        } else if (sa.stage < 3) {
-            const cx<R> a0 = U0[o], a1 = U0[FS + o], a2 = U0[2 * FS + o];
-            const cx<R> b0 = U1[o], b1 = U1[FS + o], b2 = U1[2 * FS + o];
-            U1[o] = cadd<R>(b0, cscale<R>(r0, ca));
-            U1[FS + o] = cadd<R>(b1, cscale<R>(r1, ca));
-            U1[2 * FS + o] = cadd<R>(b2, cscale<R>(r2, ca));
-            Us[o] = cadd<R>(a0, cscale<R>(r0, cb));
-            Us[FS + o] = cadd<R>(a1, cscale<R>(r1, cb));
-            Us[2 * FS + o] = cadd<R>(a2, cscale<R>(r2, cb));
-        } else {
-            const cx<R> b0 = U1[o], b1 = U1[FS + o], b2 = U1[2 * FS + o];
-            const cx<R> v0 = cadd<R>(b0, cscale<R>(r0, ca));
-            const cx<R> v1 = cadd<R>(b1, cscale<R>(r1, ca));
-            const cx<R> v2 = cadd<R>(b2, cscale<R>(r2, ca));
-            U0[o] = v0; U0[FS + o] = v1; U0[2 * FS + o] = v2;
-            if (sa.diag) {
+        nh[0][m] = csub<R>(n0, cscale<R>(P, fx));
+        nh[1][m] = csub<R>(n1, cscale<R>(P, fy));
+        nh[2][m] = csub<R>(n2, cscale<R>(P, fz));
+    }
+    // The state arrays are streamed one at a time, all elements of a thread
+    // at once, so that many loads are in flight together; a compiler memory
+    // barrier after each array keeps the next array's loads from being
+    // hoisted into the same batch (which would exhaust the registers).
+    // R = N_hat - nu |k|^2 u_s   (u_s = U0 at stage 0 and for the RHS alone)
+    cx<R> us[3][E];
+    const cx<R>* ps = (STAGE <= 0) ? U0 : Us;
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int m = 0; m < E; ++m) us[f][m] = A(ps + f * FS, m);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int kx = kfreq(g + m * G, N);
+        const R visc = nu * (R)(kx * kx + ky * ky + kz * kz);
+#pragma unroll
+        for (int f = 0; f < 3; ++f) nh[f][m] = csub<R>(nh[f][m], cscale<R>(us[f][m], visc));
+    }
+    if constexpr (STAGE != 0) asm volatile("" ::: "memory");
+    if constexpr (STAGE < 0) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int m = 0; m < E; ++m) A(U1 + f * FS, m) = nh[f][m];
+    } else if constexpr (STAGE == 0) {
+        // U1 = U0 + a0 dt R;  Us = U0 + b0 dt R
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                A(U1 + f * FS, m) = cadd<R>(us[f][m], cscale<R>(nh[f][m], ca));
+                nh[f][m] = cadd<R>(us[f][m], cscale<R>(nh[f][m], cb));
+                A(Us + f * FS, m) = nh[f][m];
+            }
+    } else if constexpr (STAGE < 3) {
+        // U1 += a_s dt R;  Us = U0 + b_s dt R
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int m = 0; m < E; ++m) us[f][m] = A(U1 + f * FS, m);
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int m = 0; m < E; ++m) A(U1 + f * FS, m) = cadd<R>(us[f][m], cscale<R>(nh[f][m], ca));
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int m = 0; m < E; ++m) us[f][m] = A(U0 + f * FS, m);
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                nh[f][m] = cadd<R>(us[f][m], cscale<R>(nh[f][m], cb));
+                A(Us + f * FS, m) = nh[f][m];
+            }
+    } else {
+        // U0 = U1 + a3 dt R  (the new state)
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int m = 0; m < E; ++m) us[f][m] = A(U1 + f * FS, m);
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                nh[f][m] = cadd<R>(us[f][m], cscale<R>(nh[f][m], ca));
+                A(U0 + f * FS, m) = nh[f][m];
+            }
+        if (sa.diag != nullptr) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int kx = kfreq(g + m * G, N);
                 const double wgt = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
+                const cx<R> v0 = nh[0][m], v1 = nh[1][m], v2 = nh[2][m];
                 const double x0 = v0.x, y0 = v0.y, x1 = v1.x, y1 = v1.y, x2 = v2.x, y2 = v2.y;
                 e_acc += wgt * (x0 * x0 + y0 * y0 + x1 * x1 + y1 * y1 + x2 * x2 + y2 * y2);
                 const double dx = kx, dy = ky, dz = kz;
@@ -495,24 +565,135 @@ void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restri
             }
         }
     }
-    if (sa.stage == 3 && sa.diag) {
-        // fixed-order tree reduction over the workgroup
-        red[0][threadIdx.x] = e_acc;
-        red[1][threadIdx.x] = w_acc;
-        __syncthreads();
+}
+
+// Fixed-order tree reduction of the two diagnostic partial sums over a
+// workgroup of NT threads; thread 0 writes them to diag[2 blockIdx + {0, 1}].
+template <int NT>
+__device__ __forceinline__ void diag_reduce(double (&red)[2][NT], double e_acc, double w_acc, double* diag) {
+    red[0][threadIdx.x] = e_acc;
+    red[1][threadIdx.x] = w_acc;
+    __syncthreads();
 #pragma unroll 1
-        for (int s = NT / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) {
-                red[0][threadIdx.x] += red[0][threadIdx.x + s];
-                red[1][threadIdx.x] += red[1][threadIdx.x + s];
-            }
-            __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
         }
-        if (threadIdx.x == 0) {
-            sa.diag[2 * blockIdx.x] = red[0][0];
-            sa.diag[2 * blockIdx.x + 1] = red[1][0];
-        }
+        __syncthreads();
     }
+    if (threadIdx.x == 0) {
+        diag[2 * blockIdx.x] = red[0][0];
+        diag[2 * blockIdx.x + 1] = red[1][0];
+    }
+}
+
+template <typename R, int N, int T, int STAGE, bool NYQ>
+__device__ __forceinline__ void xrhs_tile(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
+                                          cx<R>* __restrict__ Us, const StageArgs& sa, cx<R>* lds, const cx<R>* twl,
+                                          double (&red)[2][N / 8 * T]) {
+    constexpr int E = 8, G = N / E;
+    constexpr int NT = G * T;
+    constexpr size_t FS = field_size(N);
+    const int t = threadIdx.x % T, g = threadIdx.x / T;
+    const XCol<N, NYQ> col(blockIdx.x * T + t);
+    cx<R> nh[3][E];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int m = 0; m < E; ++m) nh[f][m] = XAddr<cx<R>, N, G, NYQ>(col, g)(W + f * FS, m);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true>(nh[f], lds + t, T, twl, g);
+    double e_acc = 0.0, w_acc = 0.0;
+    rk_apply_stage<R, N, E, STAGE, NYQ>(nh, col, g, U0, U1, Us, sa, e_acc, w_acc);
+    if (STAGE == 3 && sa.diag) diag_reduce<NT>(red, e_acc, w_acc, sa.diag);
+}
+
+// The RK stage is a template parameter: one kernel per stage gives each
+// its own straight-line code and register allocation.
+template <typename R, int N, int T, int STAGE>
+__global__ __launch_bounds__(N / 8 * T)
+void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
+            cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa) {
+    __shared__ cx<R> lds[T * N];
+    __shared__ double red[2][N / 8 * T];
+    __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
+    load_twiddles<R, N>(twl, tw);
+    if ((int)blockIdx.x < x_main_tiles<N, T>()) xrhs_tile<R, N, T, STAGE, false>(W, U0, U1, Us, sa, lds, twl, red);
+    else xrhs_tile<R, N, T, STAGE, true>(W, U0, U1, Us, sa, lds, twl, red);
+}
+
+// ---------------------------------------------------------------------------
+// Pass 5 fused with pass 1 of the next stage: after the RK4 update of stage
+// s the tile's next-stage velocity (Us for s < 3, the new U0 for s = 3) is
+// still in registers, so its curl and inverse x transforms are formed right
+// away (same five transforms and combinations as k_xinv_curl, hence the same
+// bits) and the next stage does not read it back from memory.  W fields 0..2
+// are read (N_hat) before fields 0..5 are written; a workgroup owns its
+// columns, so this is safe in place.
+// ---------------------------------------------------------------------------
+template <typename R, int N, int T, int STAGE, bool NYQ>
+__device__ __forceinline__ void xstage_tile(cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
+                                            cx<R>* __restrict__ Us, const StageArgs& sa, cx<R>* lds,
+                                            const cx<R>* twl, double (&red)[2][N / 8 * T]) {
+    constexpr int E = 8, G = N / E;
+    constexpr int NT = G * T;
+    constexpr size_t FS = field_size(N);
+    const int t = threadIdx.x % T, g = threadIdx.x / T;
+    const XCol<N, NYQ> col(blockIdx.x * T + t);
+    const XAddr<cx<R>, N, G, NYQ> A(col, g);
+
+    cx<R> u[3][E];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int m = 0; m < E; ++m) u[f][m] = A(W + f * FS, m);
+    cx<R>* lt = lds + t;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true>(u[f], lt, T, twl, g);
+    double e_acc = 0.0, w_acc = 0.0;
+    rk_apply_stage<R, N, E, STAGE, NYQ>(u, col, g, U0, U1, Us, sa, e_acc, w_acc);
+    if (STAGE == 3 && sa.diag) diag_reduce<NT>(red, e_acc, w_acc, sa.diag);
+
+    // curl and inverse x transforms of the next stage's velocity u
+    const R ky = (R)col.ky, kz = (R)col.kz;
+    cx<R> b[E];
+    fft_line<R, N, E, +1, true>(u[0], lt, T, twl, g);          // U
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        A(W, m) = u[0][m];
+        b[m] = cscale<R>(u[1][m], (R)kfreq(g + m * G, N));
+    }
+    fft_line<R, N, E, +1, true>(b, lt, T, twl, g);             // F(kx v_hat)
+#pragma unroll
+    for (int m = 0; m < E; ++m) A(W + 5 * FS, m) = cmuli<R>(csub<R>(b[m], cscale<R>(u[0][m], ky)));
+    fft_line<R, N, E, +1, true>(u[1], lt, T, twl, g);          // V
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        A(W + FS, m) = u[1][m];
+        b[m] = cscale<R>(u[2][m], (R)kfreq(g + m * G, N));
+    }
+    fft_line<R, N, E, +1, true>(b, lt, T, twl, g);             // F(kx w_hat)
+#pragma unroll
+    for (int m = 0; m < E; ++m) A(W + 4 * FS, m) = cmuli<R>(csub<R>(cscale<R>(u[0][m], kz), b[m]));
+    fft_line<R, N, E, +1, true>(u[2], lt, T, twl, g);          // W
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        A(W + 2 * FS, m) = u[2][m];
+        A(W + 3 * FS, m) = cmuli<R>(csub<R>(cscale<R>(u[2][m], ky), cscale<R>(u[1][m], kz)));
+    }
+}
+
+template <typename R, int N, int T, int STAGE>
+__global__ __launch_bounds__(N / 8 * T)
+void k_xstage(cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
+              cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa) {
+    __shared__ cx<R> lds[T * N];
+    __shared__ double red[2][N / 8 * T];
+    __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
+    load_twiddles<R, N>(twl, tw);
+    if ((int)blockIdx.x < x_main_tiles<N, T>()) xstage_tile<R, N, T, STAGE, false>(W, U0, U1, Us, sa, lds, twl, red);
+    else xstage_tile<R, N, T, STAGE, true>(W, U0, U1, Us, sa, lds, twl, red);
 }
 
 // ---------------------------------------------------------------------------

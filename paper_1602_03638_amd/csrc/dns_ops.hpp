@@ -10,7 +10,11 @@ namespace dns {
 
 constexpr int MAXV = 4;   // variants per pass
 
-enum Pass { P_XINV = 0, P_YINV6, P_ZCROSS, P_YFWD3, P_XRHS, P_COUNT };
+// The kernels of a stage: the inverse x pass with the curl (first stage
+// only when fused), the inverse y pass, the fused z pass, the forward y
+// pass, and either the RHS pass (unfused schedule) or the RHS pass fused
+// with the next stage's inverse x pass.
+enum Pass { P_XINV = 0, P_YINV6, P_ZCROSS, P_YFWD3, P_XRHS, P_XSTAGE, P_COUNT };
 
 using XinvFn = void (*)(const void* U, void* W, const void* tw, hipStream_t s);
 using YFn = void (*)(void* W, const void* tw, hipStream_t s);
@@ -32,7 +36,9 @@ struct Ops {
     ZFn zcross[MAXV];
     YFn yfwd3[MAXV];
     XrhsFn xrhs[MAXV];
+    XrhsFn xstage[MAXV];
     int xrhs_groups[MAXV]; // workgroups of each xrhs variant (= fused diagnostic partials)
+    int xstage_groups[MAXV];
     // standalone transforms and utilities (default shapes)
     void (*xinv3)(const void* U, void* W, const void* tw, hipStream_t s);
     void (*yinv3)(void* W, const void* tw, hipStream_t s);

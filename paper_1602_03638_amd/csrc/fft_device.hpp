@@ -90,7 +90,12 @@ template <typename R, int RAD, int DIR> __device__ __forceinline__ void dft_smal
 // stage (keeps it out of registers, which matters where a kernel holds
 // several lines per thread); otherwise it is read from global memory and
 // the compiler may keep it in registers across transforms.
-template <typename R, int N, int E, int DIR, int S, bool TWL = false>
+// PAD: element p of a contiguous line (ps = 1) is stored at p + p/8, so that
+// the stride-8 Stockham writes of 16-byte elements spread over all banks.
+template <int N> constexpr int padded_line(bool pad) { return pad ? N + N / 8 : N; }
+template <bool PAD> __device__ __forceinline__ int lds_index(int p) { return PAD ? p + (p >> 3) : p; }
+
+template <typename R, int N, int E, int DIR, int S, bool TWL = false, bool PAD = false>
 struct FftStage {
     static __device__ __forceinline__ void run(cx<R> (&v)[E], cx<R>* lds, int ps,
                                                const cx<R>* __restrict__ tw, int g) {
@@ -121,25 +126,25 @@ struct FftStage {
             } else {
                 const int p0 = (b - j) * RAD + j;
 #pragma unroll
-                for (int r = 0; r < RAD; ++r) lds[(p0 + r * L) * ps] = x[r];
+                for (int r = 0; r < RAD; ++r) lds[lds_index<PAD>(p0 + r * L) * ps] = x[r];
             }
         }
         if constexpr (!LAST) {
             __syncthreads();
 #pragma unroll
-            for (int m = 0; m < E; ++m) v[m] = lds[(g + m * G) * ps];
+            for (int m = 0; m < E; ++m) v[m] = lds[lds_index<PAD>(g + m * G) * ps];
             __syncthreads();
-            FftStage<R, N, E, DIR, S + 1, TWL>::run(v, lds, ps, tw, g);
+            FftStage<R, N, E, DIR, S + 1, TWL, PAD>::run(v, lds, ps, tw, g);
         }
     }
 };
 
 // Transform the line held in v (natural distribution in, natural out).
 // Every thread of the workgroup must call this (it contains barriers).
-template <typename R, int N, int E, int DIR, bool TWL = false>
+template <typename R, int N, int E, int DIR, bool TWL = false, bool PAD = false>
 __device__ __forceinline__ void fft_line(cx<R> (&v)[E], cx<R>* lds, int ps,
                                          const cx<R>* __restrict__ tw, int g) {
-    FftStage<R, N, E, DIR, 0, TWL>::run(v, lds, ps, tw, g);
+    FftStage<R, N, E, DIR, 0, TWL, PAD>::run(v, lds, ps, tw, g);
 }
 
 // Copy the twiddle table into shared memory (all threads of the workgroup
