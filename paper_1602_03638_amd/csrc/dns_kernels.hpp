@@ -449,8 +449,88 @@ void k_zc2r(const cx<R>* __restrict__ W, R* __restrict__ u, const cx<R>* __restr
 // entry; on return it holds the input of the next stage (Us for stages 0..2,
 // the new U0 for stage 3, R for stage -1), which the fused pass transforms
 // on without reading it back.
+// Per-element variant of the same update (identical arithmetic): each
+// element's state values are loaded, combined and stored before the next
+// element's; a compiler memory barrier between elements keeps the loads from
+// being batched.  Fewer registers than the batched form, for 1024-thread
+// shapes whose register budget is 128 per thread.
 template <typename R, int N, int E, int STAGE, bool NYQ>
-__device__ __forceinline__ void rk_apply_stage(cx<R> (&nh)[3][E], const XCol<N, NYQ>& col, int g,
+__device__ __forceinline__ void rk_apply_elementwise(cx<R> (&nh)[3][E], const XCol<N, NYQ>& col, int g,
+                                                     cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
+                                                     cx<R>* __restrict__ Us, const StageArgs& sa,
+                                                     double& e_acc, double& w_acc) {
+    constexpr int G = N / E;
+    constexpr size_t FS = field_size(N);
+    const int ky = col.ky, kz = col.kz;
+    const int lim = sa.mask_lim;
+    const bool keep_yz = (3 * abs(ky) < lim) && (3 * abs(kz) < lim);
+    const R nu = (R)sa.nu, ca = (R)sa.ca, cb = (R)sa.cb;
+    const XAddr<cx<R>, N, G, NYQ> A(col, g);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int kx = kfreq(g + m * G, N);
+        const bool keep = keep_yz && (3 * abs(kx) < lim);
+        const int k2 = kx * kx + ky * ky + kz * kz;
+        cx<R> n[3] = {nh[0][m], nh[1][m], nh[2][m]};
+        if (!keep) {
+            n[0] = {R(0), R(0)}; n[1] = n[0]; n[2] = n[0];
+        }
+        const R fx = (R)kx, fy = (R)ky, fz = (R)kz;
+        const R inv = k2 > 0 ? R(1) / (R)k2 : R(0);
+        const cx<R> P = {(n[0].x * fx + n[1].x * fy + n[2].x * fz) * inv,
+                         (n[0].y * fx + n[1].y * fy + n[2].y * fz) * inv};
+        n[0] = csub<R>(n[0], cscale<R>(P, fx));
+        n[1] = csub<R>(n[1], cscale<R>(P, fy));
+        n[2] = csub<R>(n[2], cscale<R>(P, fz));
+        const R visc = nu * (R)(kx * kx + ky * ky + kz * kz);
+        const cx<R>* ps = (STAGE <= 0) ? U0 : Us;
+        cx<R> us[3], a0[3], a1[3];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            us[f] = A(ps + f * FS, m);
+            if constexpr (STAGE > 0) a1[f] = A(U1 + f * FS, m);
+            if constexpr (STAGE == 1 || STAGE == 2) a0[f] = A(U0 + f * FS, m);
+        }
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const cx<R> r = csub<R>(n[f], cscale<R>(us[f], visc));
+            cx<R> v;
+            if constexpr (STAGE < 0) {
+                v = r;
+                A(U1 + f * FS, m) = v;
+            } else if constexpr (STAGE == 0) {
+                A(U1 + f * FS, m) = cadd<R>(us[f], cscale<R>(r, ca));
+                v = cadd<R>(us[f], cscale<R>(r, cb));
+                A(Us + f * FS, m) = v;
+            } else if constexpr (STAGE < 3) {
+                A(U1 + f * FS, m) = cadd<R>(a1[f], cscale<R>(r, ca));
+                v = cadd<R>(a0[f], cscale<R>(r, cb));
+                A(Us + f * FS, m) = v;
+            } else {
+                v = cadd<R>(a1[f], cscale<R>(r, ca));
+                A(U0 + f * FS, m) = v;
+            }
+            nh[f][m] = v;
+        }
+        if constexpr (STAGE == 3) {
+            if (sa.diag != nullptr) {
+                const double wgt = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
+                const cx<R> v0 = nh[0][m], v1 = nh[1][m], v2 = nh[2][m];
+                const double x0 = v0.x, y0 = v0.y, x1 = v1.x, y1 = v1.y, x2 = v2.x, y2 = v2.y;
+                e_acc += wgt * (x0 * x0 + y0 * y0 + x1 * x1 + y1 * y1 + x2 * x2 + y2 * y2);
+                const double dx = kx, dy = ky, dz = kz;
+                const double cxr = dy * x2 - dz * x1, cxi = dy * y2 - dz * y1;
+                const double cyr = dz * x0 - dx * x2, cyi = dz * y0 - dx * y2;
+                const double czr = dx * x1 - dy * x0, czi = dx * y1 - dy * y0;
+                w_acc += wgt * (cxr * cxr + cxi * cxi + cyr * cyr + cyi * cyi + czr * czr + czi * czi);
+            }
+        }
+        asm volatile("" ::: "memory");
+    }
+}
+
+template <typename R, int N, int E, int STAGE, bool NYQ>
+__device__ __forceinline__ void rk_apply_batched(cx<R> (&nh)[3][E], const XCol<N, NYQ>& col, int g,
                                                cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
                                                cx<R>* __restrict__ Us, const StageArgs& sa, double& e_acc,
                                                double& w_acc) {
@@ -567,6 +647,18 @@ __device__ __forceinline__ void rk_apply_stage(cx<R> (&nh)[3][E], const XCol<N, 
     }
 }
 
+// Register budget decides between the two forms of the update: the
+// batched one keeps more loads in flight, the per-element one fits the
+// 128-register budget of 1024-thread workgroups.
+template <typename R, int N, int E, int STAGE, bool NYQ, int NT>
+__device__ __forceinline__ void rk_apply_stage(cx<R> (&nh)[3][E], const XCol<N, NYQ>& col, int g,
+                                               cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
+                                               cx<R>* __restrict__ Us, const StageArgs& sa, double& e_acc,
+                                               double& w_acc) {
+    if constexpr (NT > 512) rk_apply_elementwise<R, N, E, STAGE, NYQ>(nh, col, g, U0, U1, Us, sa, e_acc, w_acc);
+    else rk_apply_batched<R, N, E, STAGE, NYQ>(nh, col, g, U0, U1, Us, sa, e_acc, w_acc);
+}
+
 // Fixed-order tree reduction of the two diagnostic partial sums over a
 // workgroup of NT threads; thread 0 writes them to diag[2 blockIdx + {0, 1}].
 template <int NT>
@@ -605,7 +697,7 @@ __device__ __forceinline__ void xrhs_tile(const cx<R>* __restrict__ W, cx<R>* __
 #pragma unroll
     for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true>(nh[f], lds + t, T, twl, g);
     double e_acc = 0.0, w_acc = 0.0;
-    rk_apply_stage<R, N, E, STAGE, NYQ>(nh, col, g, U0, U1, Us, sa, e_acc, w_acc);
+    rk_apply_stage<R, N, E, STAGE, NYQ, NT>(nh, col, g, U0, U1, Us, sa, e_acc, w_acc);
     if (STAGE == 3 && sa.diag) diag_reduce<NT>(red, e_acc, w_acc, sa.diag);
 }
 
@@ -652,7 +744,7 @@ __device__ __forceinline__ void xstage_tile(cx<R>* __restrict__ W, cx<R>* __rest
 #pragma unroll
     for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true>(u[f], lt, T, twl, g);
     double e_acc = 0.0, w_acc = 0.0;
-    rk_apply_stage<R, N, E, STAGE, NYQ>(u, col, g, U0, U1, Us, sa, e_acc, w_acc);
+    rk_apply_stage<R, N, E, STAGE, NYQ, NT>(u, col, g, U0, U1, Us, sa, e_acc, w_acc);
     if (STAGE == 3 && sa.diag) diag_reduce<NT>(red, e_acc, w_acc, sa.diag);
 
     // curl and inverse x transforms of the next stage's velocity u
