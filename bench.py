@@ -32,6 +32,37 @@ FIELDS_PER_LAUNCH = {"xinv_curl": 9.0, "yinv6": 12.0, "zcross": 9.0, "yfwd3": 6.
 FIELDS_PER_STEP = 192.0
 
 
+def kernel_source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, "paper_1602_03638_amd", "csrc", "*"))):
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(N, dtype, kernel):
+    """HBM bytes per launch of `kernel` (averaged over its RK stages) from the
+    committed rocprofv3 counter summary, calibrated against a plain copy;
+    None when no summary exists for this size or the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_tg{N}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    real = "double" if dtype == "f64" else "float"
+    name = {"xstage": "k_xstage", "xrhs_rk4": "k_xrhs", "xinv_curl": "k_xinv_curl", "zcross": "k_zcross",
+            "yinv6": "k_yline", "yfwd3": "k_yline"}[kernel]
+    vals = [v["traffic_bytes_calibrated"] for k, v in rec["kernels"].items()
+            if k.startswith(f"{name}<{real}, {N},") and (kernel != "yinv6" or k.endswith(", 1, 6>"))
+            and (kernel != "yfwd3" or k.endswith(", -1, 3>"))]
+    return sum(vals) / len(vals) if vals else None
+
+
 def field_bytes(N, dtype):
     return N * N * (N // 2 + 1) * (16 if dtype == "f64" else 8)
 
@@ -193,8 +224,10 @@ def main(argv=None):
         dom = max(f64["kernels_ms"], key=f64["kernels_ms"].get)
         C = field_bytes(a.N, "f64")
         ach = f64["kernels_GBps"][dom]
+        tr = measured_traffic(a.N, "f64", dom)
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
+                "traffic": None if tr is None else round(tr / 1e9, 3), "traffic_unit": "GB per launch",
                 "bytes_per_launch": FIELDS_PER_LAUNCH[dom] * C,
                 "mean_launch_ms": f64["kernels_ms"][dom]}
     cpu = None if a.no_cpu_baseline else cpu_baseline(a.N)
