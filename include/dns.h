@@ -108,6 +108,31 @@ size_t dns_state_bytes(int N, int dtype);
  * the history. */
 int dns_set_velocity(dns_t* ctx, const void* u_dev);
 
+/* Analytic initial velocity generated on the device and transformed as by
+ * dns_set_velocity (kinds below; params may be NULL for the defaults):
+ *   DNS_IC_TAYLOR_GREEN     (sin x cos y cos z, -cos x sin y cos z, 0)
+ *                           (Sec. 4.2 and the Appendix solver)
+ *   DNS_IC_TAYLOR_GREEN_2D  (sin x cos y, -cos x sin y, 0)
+ *   DNS_IC_ABC              (A sin z + C cos y, B sin x + A cos z, C sin y + B cos x),
+ *                           params {A, B, C}, default 1, 1, 1
+ *   DNS_IC_SHEAR            (amp sin(k z), 0, 0), params {k, amp}, default 1, 1
+ * Angles are 2 pi i / N evaluated as sinpi/cospi of 2 i / N.  Uses the work
+ * space; resets the step counter and the history. */
+enum { DNS_IC_TAYLOR_GREEN = 0, DNS_IC_TAYLOR_GREEN_2D = 1, DNS_IC_ABC = 2, DNS_IC_SHEAR = 3 };
+int dns_init_velocity(dns_t* ctx, int kind, const double* params, int nparams);
+
+/* Seeded random solenoidal initial spectrum (not from the paper: a synthetic
+ * workload).  Per stored mode and component, two uniforms in (0, 1] come
+ * from SplitMix64 (Steele, Lea & Flood 2014) of counters 2 key and 2 key + 1,
+ * key = (seed << 40) xor ((c N + ix) N + iy)(N/2 + 1) + iz; Box-Muller gives
+ * a complex Gaussian g with E|g|^2 = 1; g is projected to k . g = 0 and
+ * scaled by sqrt(E(|k|) / (4 pi |k|^2)) N^3, E(k) = k^4 exp(-2 (k/k0)^2); k = 0
+ * and modes outside the dealias mask are zero; the kz = 0 and kz = N/2 planes
+ * are made Hermitian (a mode whose mirror comes first in (iy, ix) order takes
+ * the conjugate of the mirror's value; self-mirrored modes are real); the
+ * field is then scaled to mean kinetic energy `energy`.  Synchronous. */
+int dns_init_random(dns_t* ctx, unsigned long long seed, double k0, double energy);
+
 /* Load u_hat from a (3, N, N, N/2+1) complex array. */
 int dns_set_spectral(dns_t* ctx, const void* uhat_dev);
 
@@ -185,6 +210,37 @@ int dns_plan_variants(const dns_t* ctx, int pass, int* widths, int max, int* cou
 
 const char* dns_strerror(int status);
 const char* dns_last_error(const dns_t* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Ensembles of independent simulations (possibly of different N).
+ *
+ * Members with equal (N, nu, dt) form a class whose state lives in one
+ * allocation; every stage kernel advances all members of a class in one
+ * launch (one workgroup row per member).  Member i is addressed by its index
+ * in the arrays given at creation.  Same conventions, ownership and
+ * ordering rules as the single-simulation calls; opts applies to all
+ * members.
+ * ------------------------------------------------------------------------- */
+typedef struct dns_ens dns_ens_t;
+enum {
+    DNS_ENS_BATCHED = 0,   /* one captured graph per step covering every class */
+    DNS_ENS_PER_SIM = 1    /* every member's kernels launched separately (baseline) */
+};
+int dns_ens_create(int count, const int* N, const double* nu, const double* dt, int dtype,
+                   const dns_opts* opts, void* stream, dns_ens_t** out);
+int dns_ens_destroy(dns_ens_t* ens);
+int dns_ens_size(const dns_ens_t* ens, int* count, int* classes);
+int dns_ens_set_velocity(dns_ens_t* ens, int i, const void* u_dev);
+int dns_ens_set_spectral(dns_ens_t* ens, int i, const void* uhat_dev);
+int dns_ens_init_random(dns_ens_t* ens, int i, unsigned long long seed, double k0, double energy);
+int dns_ens_get_spectral(dns_ens_t* ens, int i, void* uhat_dev);
+/* Advance every member nsteps RK4 steps; mode DNS_ENS_BATCHED or
+ * DNS_ENS_PER_SIM (bitwise identical results). */
+int dns_ens_step(dns_ens_t* ens, int nsteps, int mode);
+/* E[i], Omega[i] for every member (either pointer may be NULL). Synchronous. */
+int dns_ens_diagnostics(dns_ens_t* ens, double* E, double* Omega);
+int dns_ens_synchronize(dns_ens_t* ens);
+const char* dns_ens_last_error(const dns_ens_t* ens);
 
 #ifdef __cplusplus
 }

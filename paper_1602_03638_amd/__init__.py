@@ -5,7 +5,7 @@ this package holds its sources (csrc/), its build script (build.py) and a
 ctypes binding (binding.py).
 """
 from .binding import (  # noqa: F401
-    DnsError, Solver, load_library, header_functions, default_opts, state_bytes, LIB_PATH,
+    DnsError, Solver, Ensemble, load_library, header_functions, default_opts, state_bytes, LIB_PATH,
     DNS_OK, DNS_E_INVAL, DNS_E_NOMEM, DNS_E_HIP, DNS_E_STATE, DNS_E_NONFINITE, DNS_E_UNSUPPORTED,
     DNS_FP64, DNS_FP32,
 )

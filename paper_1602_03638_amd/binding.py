@@ -80,10 +80,24 @@ def load_library(path=LIB_PATH):
                                  ctypes.POINTER(I)]),
         "dns_forward": (I, [P, P, P]),
         "dns_inverse": (I, [P, P, P]),
+        "dns_init_velocity": (I, [P, I, ctypes.POINTER(D), I]),
+        "dns_init_random": (I, [P, ctypes.c_ulonglong, D, D]),
         "dns_autotune": (I, [P, I]),
         "dns_get_plan": (I, [P, ctypes.POINTER(I), I, ctypes.POINTER(I)]),
         "dns_set_plan": (I, [P, ctypes.POINTER(I), I]),
         "dns_plan_variants": (I, [P, I, ctypes.POINTER(I), I, ctypes.POINTER(I)]),
+        "dns_ens_create": (I, [I, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D), I,
+                               ctypes.POINTER(dns_opts), P, PP]),
+        "dns_ens_destroy": (I, [P]),
+        "dns_ens_size": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "dns_ens_set_velocity": (I, [P, I, P]),
+        "dns_ens_set_spectral": (I, [P, I, P]),
+        "dns_ens_init_random": (I, [P, I, ctypes.c_ulonglong, D, D]),
+        "dns_ens_get_spectral": (I, [P, I, P]),
+        "dns_ens_step": (I, [P, I, I]),
+        "dns_ens_diagnostics": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D)]),
+        "dns_ens_synchronize": (I, [P]),
+        "dns_ens_last_error": (ctypes.c_char_p, [P]),
         "dns_strerror": (ctypes.c_char_p, [I]),
         "dns_last_error": (ctypes.c_char_p, [P]),
     }
@@ -196,6 +210,19 @@ class Solver:
 
     def set_spectral(self, uh):
         _check(load_library().dns_set_spectral(self.handle, self._spec(uh)), self.handle, "dns_set_spectral")
+        return self
+
+    IC_KINDS = {"taylor_green": 0, "taylor_green_2d": 1, "abc": 2, "shear": 3}
+
+    def init_velocity(self, kind="taylor_green", params=()):
+        arr = (ctypes.c_double * max(len(params), 1))(*[float(p) for p in params])
+        _check(load_library().dns_init_velocity(self.handle, self.IC_KINDS[kind], arr, len(params)), self.handle,
+               "dns_init_velocity")
+        return self
+
+    def init_random(self, seed, k0=4.0, energy=0.5):
+        _check(load_library().dns_init_random(self.handle, int(seed), float(k0), float(energy)), self.handle,
+               "dns_init_random")
         return self
 
     def get_spectral(self, out=None):
@@ -316,3 +343,122 @@ class Solver:
 
     def __exit__(self, *exc):
         self.close()
+
+
+DNS_ENS_BATCHED = 0
+DNS_ENS_PER_SIM = 1
+
+
+def _check_ens(status, ens, what):
+    if status != DNS_OK:
+        lib = load_library()
+        msg = lib.dns_strerror(status).decode()
+        if ens:
+            detail = lib.dns_ens_last_error(ens).decode()
+            if detail:
+                msg += ": " + detail
+        raise DnsError(status, f"{what}: {msg}")
+
+
+class Ensemble:
+    """Independent simulations advanced together (see include/dns.h).
+
+    Ns, nus, dts: per-member grid size, viscosity and time step.  Members with
+    equal (N, nu, dt) are batched into one launch per kernel.
+    """
+
+    def __init__(self, Ns, nus, dts, dtype="f64", dealias="text", use_graph=True, fuse=True, stream=None):
+        import torch
+        self._torch = torch
+        lib = load_library()
+        n = len(Ns)
+        self.Ns = [int(v) for v in Ns]
+        self.dtype = dtype
+        self.real = torch.float64 if dtype == "f64" else torch.float32
+        self.complex = torch.complex128 if dtype == "f64" else torch.complex64
+        o = default_opts()
+        o.dealias = {"text": DNS_DEALIAS_TEXT, "appendix": DNS_DEALIAS_APPENDIX}[dealias]
+        o.use_graph = 1 if use_graph else 0
+        o.fuse = 1 if fuse else 0
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check_ens(lib.dns_ens_create(n, (ctypes.c_int * n)(*self.Ns), (ctypes.c_double * n)(*map(float, nus)),
+                                      (ctypes.c_double * n)(*map(float, dts)), {"f64": DNS_FP64, "f32": DNS_FP32}[dtype],
+                                      ctypes.byref(o), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)),
+                   None, "dns_ens_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise RuntimeError("ensemble is closed")
+        return self._h
+
+    def __len__(self):
+        return len(self.Ns)
+
+    def classes(self):
+        n, k = ctypes.c_int(), ctypes.c_int()
+        _check_ens(load_library().dns_ens_size(self.handle, ctypes.byref(n), ctypes.byref(k)), self.handle,
+                   "dns_ens_size")
+        return k.value
+
+    def _spec(self, i, t):
+        N = self.Ns[i]
+        if (not t.is_cuda or t.dtype != self.complex or tuple(t.shape) != (3, N, N, N // 2 + 1)
+                or not t.is_contiguous()):
+            raise ValueError(f"expected a contiguous CUDA {self.complex} tensor of shape (3, {N}, {N}, {N // 2 + 1})")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def set_velocity(self, i, u):
+        N = self.Ns[i]
+        if (not u.is_cuda or u.dtype != self.real or tuple(u.shape) != (3, N, N, N) or not u.is_contiguous()):
+            raise ValueError(f"expected a contiguous CUDA {self.real} tensor of shape (3, {N}, {N}, {N})")
+        _check_ens(load_library().dns_ens_set_velocity(self.handle, int(i), ctypes.c_void_p(u.data_ptr())),
+                   self.handle, "dns_ens_set_velocity")
+        return self
+
+    def set_spectral(self, i, uh):
+        _check_ens(load_library().dns_ens_set_spectral(self.handle, int(i), self._spec(i, uh)), self.handle,
+                   "dns_ens_set_spectral")
+        return self
+
+    def init_random(self, i, seed, k0=4.0, energy=0.5):
+        _check_ens(load_library().dns_ens_init_random(self.handle, int(i), int(seed), float(k0), float(energy)),
+                   self.handle, "dns_ens_init_random")
+        return self
+
+    def get_spectral(self, i, out=None):
+        N = self.Ns[i]
+        if out is None:
+            out = self._torch.empty((3, N, N, N // 2 + 1), dtype=self.complex, device="cuda")
+        _check_ens(load_library().dns_ens_get_spectral(self.handle, int(i), self._spec(i, out)), self.handle,
+                   "dns_ens_get_spectral")
+        return out
+
+    def step(self, n=1, batched=True):
+        _check_ens(load_library().dns_ens_step(self.handle, int(n), DNS_ENS_BATCHED if batched else DNS_ENS_PER_SIM),
+                   self.handle, "dns_ens_step")
+        return self
+
+    def diagnostics(self):
+        n = len(self.Ns)
+        E = (ctypes.c_double * n)()
+        W = (ctypes.c_double * n)()
+        _check_ens(load_library().dns_ens_diagnostics(self.handle, E, W), self.handle, "dns_ens_diagnostics")
+        return list(E), list(W)
+
+    def synchronize(self):
+        _check_ens(load_library().dns_ens_synchronize(self.handle), self.handle, "dns_ens_synchronize")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().dns_ens_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -91,38 +91,46 @@ void launch_diag_final(const double* part, int nparts, double inv_norm, double* 
 }  // namespace dns
 
 // ---------------------------------------------------------------------------
-// Context
+// Context.  A context holds `members` independent simulations of one size,
+// precision, viscosity and time step (1 for dns_create); the stage kernels
+// advance all members in one launch (grid y = member).
 // ---------------------------------------------------------------------------
 struct dns_ctx {
     int N = 0, dtype = 0;
     double nu = 0, dt = 0;
     dns_opts opts{};
     int mask_lim = 0;
+    int members = 1;
     hipStream_t user = nullptr;     // caller's stream (ordering reference)
     hipStream_t s = nullptr;        // library stream (graph capture needs a non-null stream)
+    bool own_stream = true;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipEvent_t ev_prof[2] = {nullptr, nullptr};
     const dns::Ops* ops = nullptr;
     int sel[dns::P_COUNT] = {0, 0, 0, 0, 0, 0};   // chosen variant of each pass
     bool w_ready = false;           // W holds the inverse-x/curl fields of U0 (fused schedule)
+    size_t fs = 0;                  // complex values per half-spectrum field
     size_t cbytes = 0;              // bytes of one complex value
     size_t fbytes = 0;              // bytes of one half-spectrum field
-    char* state = nullptr;          // U0 | U1 | Us, three fields each
-    char* work = nullptr;           // W: six fields
+    char* state = nullptr;          // per member: U0 | U1 | Us, three fields each
+    char* work = nullptr;           // per member: W, six fields
     void* tw = nullptr;
-    double* part = nullptr;         // diagnostic partials
+    double* part = nullptr;         // diagnostic partials, npart_cap pairs per member
     int npart_cap = 0;
-    double* dout = nullptr;         // [E, Omega] of the last reduction
-    double* hist = nullptr;         // [cap][2]
-    int* hist_count = nullptr;
+    double* dout = nullptr;         // [member][E, Omega] of the last reduction
+    double* hist = nullptr;         // [member][cap][2]
+    int* hist_count = nullptr;      // [member]
     hipGraphExec_t gexec[2] = {nullptr, nullptr};   // step without / with diagnostics
     bool has_state = false;
     long long steps = 0;
     std::string err;
 
-    char* U0() const { return state; }
-    char* U1() const { return state + 3 * fbytes; }
-    char* Us() const { return state + 6 * fbytes; }
+    char* U0(int m = 0) const { return state + (size_t)m * 9 * fbytes; }
+    char* U1(int m = 0) const { return U0(m) + 3 * fbytes; }
+    char* Us(int m = 0) const { return U0(m) + 6 * fbytes; }
+    char* W(int m = 0) const { return work + (size_t)m * 6 * fbytes; }
+    dns::Batch batch() const { return dns::Batch{members, 9 * fs, 6 * fs}; }
+    int hist_cap() const { return opts.history_cap > 0 ? opts.history_cap : 1; }
 };
 
 namespace {
@@ -147,11 +155,13 @@ bool valid_n(int N) { return N >= 8 && N <= 1024 && (N & (N - 1)) == 0; }
 // Make the library stream wait for work already enqueued on the caller's
 // stream, and the caller's stream wait for what the library enqueues.
 int enter(dns_t* c) {
+    if (c->user == c->s) return DNS_OK;
     DNS_TRY(c, hipEventRecord(c->ev_in, c->user));
     DNS_TRY(c, hipStreamWaitEvent(c->s, c->ev_in, 0));
     return DNS_OK;
 }
 int leave(dns_t* c) {
+    if (c->user == c->s) return DNS_OK;
     DNS_TRY(c, hipEventRecord(c->ev_out, c->s));
     DNS_TRY(c, hipStreamWaitEvent(c->user, c->ev_out, 0));
     return DNS_OK;
@@ -173,53 +183,70 @@ dns::StageArgs stage_args(const dns_t* c, int stage, double* diag) {
 
 double inv_norm(int N) { return 1.0 / (2.0 * std::pow((double)N, 6)); }
 
-// Enqueue one RHS evaluation of stage `stage` on stream s (Sec. 3.1
-// computeRHS): the five passes of dns_kernels.hpp.
-void launch_pass(dns_t* c, int pass, int variant, int stage, double* diag, hipStream_t s) {
+int diag_groups(const dns_t* c) {
+    return c->opts.fuse ? c->ops->xstage_groups[c->sel[dns::P_XSTAGE]] : c->ops->xrhs_groups[c->sel[dns::P_XRHS]];
+}
+
+// Launch one pass of stage `stage` for all members (member < 0, one batched
+// launch) or for one member only.  diag: fused diagnostic partials of
+// member 0; member m's sit 2 * groups * m doubles further.
+void launch_pass(dns_t* c, int pass, int variant, int stage, double* diag, hipStream_t s, int member = -1) {
     const dns::Ops* o = c->ops;
+    const int m = member < 0 ? 0 : member;
+    const dns::Batch b = member < 0 ? c->batch() : dns::Batch{1, 0, 0};
+    double* dg = diag ? diag + (size_t)2 * diag_groups(c) * m : nullptr;
     switch (pass) {
-        case dns::P_XINV: o->xinv[variant](stage <= 0 ? c->U0() : c->Us(), c->work, c->tw, s); break;
-        case dns::P_YINV6: o->yinv6[variant](c->work, c->tw, s); break;
-        case dns::P_ZCROSS: o->zcross[variant](c->work, c->tw, s); break;
-        case dns::P_YFWD3: o->yfwd3[variant](c->work, c->tw, s); break;
+        case dns::P_XINV: o->xinv[variant](stage <= 0 ? c->U0(m) : c->Us(m), c->W(m), c->tw, b, s); break;
+        case dns::P_YINV6: o->yinv6[variant](c->W(m), c->tw, b, s); break;
+        case dns::P_ZCROSS: o->zcross[variant](c->W(m), c->tw, b, s); break;
+        case dns::P_YFWD3: o->yfwd3[variant](c->W(m), c->tw, b, s); break;
         case dns::P_XRHS: {
-            const dns::StageArgs a = stage_args(c, stage, diag);
-            o->xrhs[variant](c->work, c->U0(), c->U1(), c->Us(), c->tw, a, s);
+            const dns::StageArgs a = stage_args(c, stage, dg);
+            o->xrhs[variant](c->W(m), c->U0(m), c->U1(m), c->Us(m), c->tw, a, b, s);
             break;
         }
         default: {
-            const dns::StageArgs a = stage_args(c, stage, diag);
-            o->xstage[variant](c->work, c->U0(), c->U1(), c->Us(), c->tw, a, s);
+            const dns::StageArgs a = stage_args(c, stage, dg);
+            o->xstage[variant](c->W(m), c->U0(m), c->U1(m), c->Us(m), c->tw, a, b, s);
         }
     }
 }
 
 // Unfused stage: inverse x (+curl), inverse y, z, forward y, RHS + RK4.
-void enqueue_stage(dns_t* c, int stage, bool with_diag, hipStream_t s) {
+void enqueue_stage(dns_t* c, int stage, bool with_diag, hipStream_t s, int member = -1) {
     for (int p = dns::P_XINV; p <= dns::P_XRHS; ++p)
-        launch_pass(c, p, c->sel[p], stage, (p == dns::P_XRHS && stage == 3 && with_diag) ? c->part : nullptr, s);
+        launch_pass(c, p, c->sel[p], stage, (p == dns::P_XRHS && stage == 3 && with_diag) ? c->part : nullptr, s,
+                    member);
 }
 
-int diag_groups(const dns_t* c) {
-    return c->opts.fuse ? c->ops->xstage_groups[c->sel[dns::P_XSTAGE]] : c->ops->xrhs_groups[c->sel[dns::P_XRHS]];
+void enqueue_diag_final(dns_t* c, hipStream_t s, int member) {
+    const int groups = diag_groups(c);
+    const int m0 = member < 0 ? 0 : member, m1 = member < 0 ? c->members : member + 1;
+    for (int m = m0; m < m1; ++m)
+        dns::launch_diag_final(c->part + (size_t)2 * groups * m, groups, inv_norm(c->N), c->dout + 2 * m,
+                               c->hist + (size_t)2 * c->hist_cap() * m, c->hist_count + m, c->opts.history_cap, s);
 }
 
 // One RK4 step.  Fused schedule: W already holds the inverse-x/curl fields
 // of U0 (prepared by the previous step's last kernel or by one k_xinv_curl
 // launch), and each stage ends with the RHS pass fused with the next
 // stage's inverse x pass, so a step is 16 kernels.  Unfused: 20 kernels.
-void enqueue_step(dns_t* c, bool with_diag, hipStream_t s) {
+void enqueue_step(dns_t* c, bool with_diag, hipStream_t s, int member = -1) {
     if (c->opts.fuse) {
         for (int st = 0; st < 4; ++st) {
-            for (int p = dns::P_YINV6; p <= dns::P_YFWD3; ++p) launch_pass(c, p, c->sel[p], st, nullptr, s);
-            launch_pass(c, dns::P_XSTAGE, c->sel[dns::P_XSTAGE], st, (st == 3 && with_diag) ? c->part : nullptr, s);
+            for (int p = dns::P_YINV6; p <= dns::P_YFWD3; ++p) launch_pass(c, p, c->sel[p], st, nullptr, s, member);
+            launch_pass(c, dns::P_XSTAGE, c->sel[dns::P_XSTAGE], st, (st == 3 && with_diag) ? c->part : nullptr, s,
+                        member);
         }
     } else {
-        for (int st = 0; st < 4; ++st) enqueue_stage(c, st, with_diag, s);
+        for (int st = 0; st < 4; ++st) enqueue_stage(c, st, with_diag, s, member);
     }
-    if (with_diag)
-        dns::launch_diag_final(c->part, diag_groups(c), inv_norm(c->N), c->dout, c->hist, c->hist_count,
-                               c->opts.history_cap, s);
+    if (with_diag) enqueue_diag_final(c, s, member);
+}
+
+void drop_graphs(dns_t* c) {
+    for (auto& g : c->gexec)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
 }
 
 int build_graph(dns_t* c, int which) {
@@ -239,6 +266,14 @@ int build_graph(dns_t* c, int which) {
     return hip_check(c, ie, "hipGraphInstantiate");
 }
 
+// The curl/inverse-x fields of U0 that the fused schedule starts from.
+int prepare_w(dns_t* c) {
+    if (!c->opts.fuse || c->w_ready) return DNS_OK;
+    launch_pass(c, dns::P_XINV, c->sel[dns::P_XINV], 0, nullptr, c->s);
+    return launched(c, "xinv_curl");
+}
+
+// Energy and enstrophy of member m's U0 (synchronous, fixed order).
 int reduce_state(dns_t* c, const void* U, double* E, double* W) {
     c->ops->diag_partial(U, c->part, c->s);
     int r = launched(c, "diag_partial");
@@ -256,8 +291,7 @@ int reduce_state(dns_t* c, const void* U, double* E, double* W) {
 }
 
 void release(dns_t* c) {
-    for (auto& g : c->gexec)
-        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    drop_graphs(c);
     if (c->state) (void)hipFree(c->state);
     if (c->work) (void)hipFree(c->work);
     if (c->tw) (void)hipFree(c->tw);
@@ -269,13 +303,207 @@ void release(dns_t* c) {
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     for (auto& e : c->ev_prof)
         if (e) (void)hipEventDestroy(e);
-    if (c->s) (void)hipStreamDestroy(c->s);
+    if (c->s && c->own_stream) (void)hipStreamDestroy(c->s);
+}
+
+int check_args(int N, double nu, double dt, int dtype, const dns_opts& o) {
+    if (!valid_n(N) || !(nu >= 0.0) || !std::isfinite(nu) || !(dt > 0.0) || !std::isfinite(dt) ||
+        (dtype != DNS_FP64 && dtype != DNS_FP32))
+        return DNS_E_INVAL;
+    if ((o.dealias != DNS_DEALIAS_TEXT && o.dealias != DNS_DEALIAS_APPENDIX) || o.diag_every < 0 ||
+        o.history_cap < 0 || (o.fuse != 0 && o.fuse != 1))
+        return DNS_E_INVAL;
+    return DNS_OK;
+}
+
+// Create a context of `members` simulations.  lib_stream: when non-null the
+// context enqueues on that stream (owned by an ensemble) instead of its own.
+int create_ctx(int N, double nu, double dt, int dtype, const dns_opts& o, hipStream_t user, int members,
+               hipStream_t lib_stream, dns_t** out) {
+    *out = nullptr;
+    dns_t* c = new (std::nothrow) dns_ctx();
+    if (!c) return DNS_E_NOMEM;
+    c->N = N;
+    c->nu = nu;
+    c->dt = dt;
+    c->dtype = dtype;
+    c->opts = o;
+    c->members = members;
+    c->mask_lim = (o.dealias == DNS_DEALIAS_TEXT) ? N : N + 2;
+    c->user = user;
+    c->ops = dtype == DNS_FP64 ? dns::ops_f64(N) : dns::ops_f32(N);
+    const size_t rs = c->ops->real_size;
+    c->fs = dns::field_size(N);
+    c->cbytes = 2 * rs;
+    c->fbytes = c->fs * c->cbytes;
+
+    auto bail = [&](int code, const char* what, hipError_t e) {
+        std::fprintf(stderr, "dns_create: %s: %s\n", what, hipGetErrorString(e));
+        release(c);
+        delete c;
+        return code;
+    };
+    hipError_t e;
+    if (lib_stream) {
+        c->s = lib_stream;
+        c->own_stream = false;
+    } else if ((e = hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking)) != hipSuccess) {
+        return bail(DNS_E_HIP, "hipStreamCreate", e);
+    }
+    if ((e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreate(&c->ev_prof[0])) != hipSuccess || (e = hipEventCreate(&c->ev_prof[1])) != hipSuccess)
+        return bail(DNS_E_HIP, "hipEventCreate", e);
+    if ((e = hipMalloc((void**)&c->state, (size_t)members * 9 * c->fbytes)) != hipSuccess)
+        return bail(DNS_E_NOMEM, "hipMalloc(state)", e);
+    if ((e = hipMalloc((void**)&c->work, (size_t)members * 6 * c->fbytes)) != hipSuccess)
+        return bail(DNS_E_NOMEM, "hipMalloc(work)", e);
+    c->npart_cap = dns::DIAG_BLOCKS;
+    for (int v = 0; v < c->ops->nvar[dns::P_XRHS]; ++v)
+        if (c->ops->xrhs_groups[v] > c->npart_cap) c->npart_cap = c->ops->xrhs_groups[v];
+    for (int v = 0; v < c->ops->nvar[dns::P_XSTAGE]; ++v)
+        if (c->ops->xstage_groups[v] > c->npart_cap) c->npart_cap = c->ops->xstage_groups[v];
+    for (int p = 0; p < dns::P_COUNT; ++p) c->sel[p] = c->ops->def[p];
+    if ((e = hipMalloc((void**)&c->part, 2 * sizeof(double) * (size_t)c->npart_cap * members)) != hipSuccess ||
+        (e = hipMalloc((void**)&c->dout, 2 * sizeof(double) * (size_t)members)) != hipSuccess ||
+        (e = hipMalloc((void**)&c->hist, 2 * sizeof(double) * (size_t)c->hist_cap() * members)) != hipSuccess ||
+        (e = hipMalloc((void**)&c->hist_count, sizeof(int) * (size_t)members)) != hipSuccess)
+        return bail(DNS_E_NOMEM, "hipMalloc(diagnostics)", e);
+
+    // twiddles: long-double accurate, rounded to the context's precision
+    const int ntw = c->ops->tw_count;
+    std::vector<double> twd(2 * (size_t)ntw, 0.0);
+    dns::make_twiddles(N, twd.data());
+    if ((e = hipMalloc(&c->tw, (size_t)ntw * c->cbytes)) != hipSuccess) return bail(DNS_E_NOMEM, "hipMalloc(tw)", e);
+    if (dtype == DNS_FP64) {
+        e = hipMemcpy(c->tw, twd.data(), (size_t)ntw * c->cbytes, hipMemcpyHostToDevice);
+    } else {
+        std::vector<float> twf(twd.size());
+        for (size_t i = 0; i < twd.size(); ++i) twf[i] = (float)twd[i];
+        e = hipMemcpy(c->tw, twf.data(), (size_t)ntw * c->cbytes, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return bail(DNS_E_HIP, "hipMemcpy(tw)", e);
+    if ((e = hipMemset(c->state, 0, (size_t)members * 9 * c->fbytes)) != hipSuccess ||
+        (e = hipMemset(c->hist_count, 0, sizeof(int) * (size_t)members)) != hipSuccess)
+        return bail(DNS_E_HIP, "hipMemset", e);
+    *out = c;
+    return DNS_OK;
+}
+
+int reset_counters(dns_t* c) {
+    c->steps = 0;
+    c->has_state = true;
+    DNS_TRY(c, hipMemsetAsync(c->hist_count, 0, sizeof(int) * (size_t)c->members, c->s));
+    return DNS_OK;
+}
+
+// ---- per-member operations (shared by the single-simulation API and the
+// ensemble API); the caller brackets them with enter/leave -----------------
+int set_velocity_m(dns_t* c, int m, const void* u) {
+    c->w_ready = false;
+    c->ops->zr2c(u, c->W(m), c->tw, c->s);
+    c->ops->yfwd3[c->sel[dns::P_YFWD3]](c->W(m), c->tw, dns::Batch{1, 0, 0}, c->s);
+    c->ops->xfwd3(c->W(m), c->U0(m), c->tw, c->s);
+    return launched(c, "set_velocity");
+}
+
+int init_velocity_m(dns_t* c, int m, int kind, const double* p) {
+    c->w_ready = false;
+    // the physical field is written into work fields 3..5 (3 N^3 reals fit in
+    // three half-spectrum fields), then transformed as dns_set_velocity does
+    void* phys = c->W(m) + 3 * c->fbytes;
+    c->ops->ic_physical(phys, kind, p[0], p[1], p[2], c->s);
+    int r = launched(c, "ic_physical");
+    if (r) return r;
+    return set_velocity_m(c, m, phys);
+}
+
+int init_random_m(dns_t* c, int m, unsigned long long seed, double k0, double energy) {
+    c->w_ready = false;
+    c->ops->ic_random(c->U0(m), seed, k0, c->mask_lim, c->s);
+    int r = launched(c, "init_random");
+    if (r) return r;
+    double E = 0.0;
+    if ((r = reduce_state(c, c->U0(m), &E, nullptr))) return r;
+    if (!(E > 0.0)) return fail(c, DNS_E_NONFINITE, "random field has no energy (mask empty?)");
+    c->ops->scale(c->U0(m), std::sqrt(energy / E), c->s);
+    return launched(c, "scale");
+}
+
+int set_spectral_m(dns_t* c, int m, const void* uh) {
+    c->w_ready = false;
+    c->ops->layout(uh, c->U0(m), true, c->s);
+    return launched(c, "set_spectral");
+}
+
+int get_spectral_m(dns_t* c, int m, void* uh) {
+    c->ops->layout(c->U0(m), uh, false, c->s);
+    return launched(c, "get_spectral");
+}
+
+int get_velocity_m(dns_t* c, int m, void* u) {
+    c->w_ready = false;
+    c->ops->xinv3(c->U0(m), c->W(m), c->tw, c->s);
+    c->ops->yinv3(c->W(m), c->tw, c->s);
+    c->ops->zc2r(c->W(m), u, c->tw, c->s);
+    return launched(c, "get_velocity");
+}
+
+// Advance all members nsteps steps as replayed graphs (use_graph) or
+// launch by launch; per_member launches every member's kernels separately.
+int step_all(dns_t* c, int nsteps, bool per_member) {
+    int r = DNS_OK;
+    if (c->opts.fuse && !c->w_ready) {
+        if (per_member) {
+            for (int m = 0; m < c->members; ++m)
+                launch_pass(c, dns::P_XINV, c->sel[dns::P_XINV], 0, nullptr, c->s, m);
+            if ((r = launched(c, "xinv_curl"))) return r;
+        } else if ((r = prepare_w(c))) {
+            return r;
+        }
+    }
+    for (int i = 0; i < nsteps; ++i) {
+        const long long n = c->steps + 1;
+        const bool diag = c->opts.diag_every > 0 && (n % c->opts.diag_every) == 0;
+        if (per_member) {
+            for (int m = 0; m < c->members; ++m) enqueue_step(c, diag, c->s, m);
+            if ((r = launched(c, "step"))) return r;
+        } else if (c->opts.use_graph) {
+            if ((r = build_graph(c, diag ? 1 : 0))) return r;
+            DNS_TRY(c, hipGraphLaunch(c->gexec[diag ? 1 : 0], c->s));
+        } else {
+            enqueue_step(c, diag, c->s);
+            if ((r = launched(c, "step"))) return r;
+        }
+        c->steps = n;
+    }
+    c->w_ready = c->opts.fuse != 0;
+    return DNS_OK;
+}
+
+int history_m(dns_t* c, int m, double* E, double* W, int max, int* count) {
+    DNS_TRY(c, hipStreamSynchronize(c->s));
+    int n = 0;
+    DNS_TRY(c, hipMemcpy(&n, c->hist_count + m, sizeof(int), hipMemcpyDeviceToHost));
+    *count = n;
+    const int avail = n < c->opts.history_cap ? n : c->opts.history_cap;
+    const int k = avail < max ? avail : max;
+    if (k > 0) {
+        std::vector<double> h(2 * (size_t)k);
+        DNS_TRY(c, hipMemcpy(h.data(), c->hist + (size_t)2 * c->hist_cap() * m, h.size() * sizeof(double),
+                             hipMemcpyDeviceToHost));
+        for (int i = 0; i < k; ++i) {
+            E[i] = h[2 * i];
+            W[i] = h[2 * i + 1];
+        }
+    }
+    return DNS_OK;
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// C ABI
+// C ABI: single simulation
 // ---------------------------------------------------------------------------
 extern "C" {
 
@@ -302,78 +530,17 @@ int dns_create(int N, double nu, double dt, int dtype, dns_t** out) {
 int dns_create_ex(int N, double nu, double dt, int dtype, const dns_opts* opts, void* stream, dns_t** out) {
     if (!out) return DNS_E_INVAL;
     *out = nullptr;
-    if (!valid_n(N) || !(nu >= 0.0) || !std::isfinite(nu) || !(dt > 0.0) || !std::isfinite(dt) ||
-        (dtype != DNS_FP64 && dtype != DNS_FP32))
-        return DNS_E_INVAL;
     dns_opts o;
     dns_default_opts(&o);
     if (opts) o = *opts;
-    if ((o.dealias != DNS_DEALIAS_TEXT && o.dealias != DNS_DEALIAS_APPENDIX) || o.diag_every < 0 ||
-        o.history_cap < 0 || (o.fuse != 0 && o.fuse != 1))
-        return DNS_E_INVAL;
-
-    dns_t* c = new (std::nothrow) dns_ctx();
-    if (!c) return DNS_E_NOMEM;
-    c->N = N;
-    c->nu = nu;
-    c->dt = dt;
-    c->dtype = dtype;
-    c->opts = o;
-    c->mask_lim = (o.dealias == DNS_DEALIAS_TEXT) ? N : N + 2;
-    c->user = (hipStream_t)stream;
-    c->ops = dtype == DNS_FP64 ? dns::ops_f64(N) : dns::ops_f32(N);
-    const size_t rs = c->ops->real_size;
-    c->cbytes = 2 * rs;
-    c->fbytes = dns::field_size(N) * c->cbytes;
-
-    auto bail = [&](int code, const char* what, hipError_t e) {
-        std::fprintf(stderr, "dns_create: %s: %s\n", what, hipGetErrorString(e));
+    int r = check_args(N, nu, dt, dtype, o);
+    if (r) return r;
+    dns_t* c = nullptr;
+    if ((r = create_ctx(N, nu, dt, dtype, o, (hipStream_t)stream, 1, nullptr, &c))) return r;
+    if (o.autotune && (r = dns_autotune(c, 3)) != DNS_OK) {
         release(c);
         delete c;
-        return code;
-    };
-    hipError_t e;
-    if ((e = hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking)) != hipSuccess)
-        return bail(DNS_E_HIP, "hipStreamCreate", e);
-    if ((e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreate(&c->ev_prof[0])) != hipSuccess || (e = hipEventCreate(&c->ev_prof[1])) != hipSuccess)
-        return bail(DNS_E_HIP, "hipEventCreate", e);
-    if ((e = hipMalloc((void**)&c->state, 9 * c->fbytes)) != hipSuccess) return bail(DNS_E_NOMEM, "hipMalloc(state)", e);
-    if ((e = hipMalloc((void**)&c->work, 6 * c->fbytes)) != hipSuccess) return bail(DNS_E_NOMEM, "hipMalloc(work)", e);
-    c->npart_cap = dns::DIAG_BLOCKS;
-    for (int v = 0; v < c->ops->nvar[dns::P_XRHS]; ++v)
-        if (c->ops->xrhs_groups[v] > c->npart_cap) c->npart_cap = c->ops->xrhs_groups[v];
-    for (int p = 0; p < dns::P_COUNT; ++p) c->sel[p] = c->ops->def[p];
-    if ((e = hipMalloc((void**)&c->part, 2 * sizeof(double) * c->npart_cap)) != hipSuccess ||
-        (e = hipMalloc((void**)&c->dout, 2 * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc((void**)&c->hist, 2 * sizeof(double) * (o.history_cap > 0 ? o.history_cap : 1))) != hipSuccess ||
-        (e = hipMalloc((void**)&c->hist_count, sizeof(int))) != hipSuccess)
-        return bail(DNS_E_NOMEM, "hipMalloc(diagnostics)", e);
-
-    // twiddles: long-double accurate, rounded to the context's precision
-    const int ntw = c->ops->tw_count;
-    std::vector<double> twd(2 * (size_t)ntw, 0.0);
-    dns::make_twiddles(N, twd.data());
-    if ((e = hipMalloc(&c->tw, (size_t)ntw * c->cbytes)) != hipSuccess) return bail(DNS_E_NOMEM, "hipMalloc(tw)", e);
-    if (dtype == DNS_FP64) {
-        e = hipMemcpy(c->tw, twd.data(), (size_t)ntw * c->cbytes, hipMemcpyHostToDevice);
-    } else {
-        std::vector<float> twf(twd.size());
-        for (size_t i = 0; i < twd.size(); ++i) twf[i] = (float)twd[i];
-        e = hipMemcpy(c->tw, twf.data(), (size_t)ntw * c->cbytes, hipMemcpyHostToDevice);
-    }
-    if (e != hipSuccess) return bail(DNS_E_HIP, "hipMemcpy(tw)", e);
-    if ((e = hipMemset(c->state, 0, 9 * c->fbytes)) != hipSuccess ||
-        (e = hipMemset(c->hist_count, 0, sizeof(int))) != hipSuccess)
-        return bail(DNS_E_HIP, "hipMemset", e);
-    if (o.autotune) {
-        const int r = dns_autotune(c, 3);
-        if (r != DNS_OK) {
-            release(c);
-            delete c;
-            return r;
-        }
+        return r;
     }
     *out = c;
     return DNS_OK;
@@ -387,34 +554,35 @@ int dns_destroy(dns_t* c) {
     return DNS_OK;
 }
 
-static int reset_counters(dns_t* c) {
-    c->steps = 0;
-    c->has_state = true;
-    DNS_TRY(c, hipMemsetAsync(c->hist_count, 0, sizeof(int), c->s));
-    return DNS_OK;
-}
-
 int dns_set_velocity(dns_t* c, const void* u) {
     if (!c || !u) return fail(c, DNS_E_INVAL, "null argument");
     int r = enter(c);
-    if (r) return r;
-    c->w_ready = false;
-    c->ops->zr2c(u, c->work, c->tw, c->s);
-    c->ops->yfwd3[c->sel[dns::P_YFWD3]](c->work, c->tw, c->s);
-    c->ops->xfwd3(c->work, c->U0(), c->tw, c->s);
-    if ((r = launched(c, "set_velocity"))) return r;
-    if ((r = reset_counters(c))) return r;
+    if (r || (r = set_velocity_m(c, 0, u)) || (r = reset_counters(c))) return r;
+    return leave(c);
+}
+
+int dns_init_velocity(dns_t* c, int kind, const double* params, int nparams) {
+    if (!c || kind < DNS_IC_TAYLOR_GREEN || kind > DNS_IC_SHEAR || nparams < 0 || (nparams > 0 && !params))
+        return fail(c, DNS_E_INVAL, "bad argument");
+    double p[3] = {1.0, 1.0, 1.0};
+    for (int i = 0; i < nparams && i < 3; ++i) p[i] = params[i];
+    int r = enter(c);
+    if (r || (r = init_velocity_m(c, 0, kind, p)) || (r = reset_counters(c))) return r;
+    return leave(c);
+}
+
+int dns_init_random(dns_t* c, unsigned long long seed, double k0, double energy) {
+    if (!c || !(k0 > 0.0) || !(energy > 0.0) || !std::isfinite(k0) || !std::isfinite(energy))
+        return fail(c, DNS_E_INVAL, "bad argument");
+    int r = enter(c);
+    if (r || (r = init_random_m(c, 0, seed, k0, energy)) || (r = reset_counters(c))) return r;
     return leave(c);
 }
 
 int dns_set_spectral(dns_t* c, const void* uh) {
     if (!c || !uh) return fail(c, DNS_E_INVAL, "null argument");
     int r = enter(c);
-    if (r) return r;
-    c->w_ready = false;
-    c->ops->layout(uh, c->U0(), true, c->s);
-    if ((r = launched(c, "set_spectral"))) return r;
-    if ((r = reset_counters(c))) return r;
+    if (r || (r = set_spectral_m(c, 0, uh)) || (r = reset_counters(c))) return r;
     return leave(c);
 }
 
@@ -422,9 +590,7 @@ int dns_get_spectral(dns_t* c, void* uh) {
     if (!c || !uh) return fail(c, DNS_E_INVAL, "null argument");
     if (!c->has_state) return fail(c, DNS_E_STATE, "no velocity set");
     int r = enter(c);
-    if (r) return r;
-    c->ops->layout(c->U0(), uh, false, c->s);
-    if ((r = launched(c, "get_spectral"))) return r;
+    if (r || (r = get_spectral_m(c, 0, uh))) return r;
     return leave(c);
 }
 
@@ -432,12 +598,7 @@ int dns_get_velocity(dns_t* c, void* u) {
     if (!c || !u) return fail(c, DNS_E_INVAL, "null argument");
     if (!c->has_state) return fail(c, DNS_E_STATE, "no velocity set");
     int r = enter(c);
-    if (r) return r;
-    c->w_ready = false;
-    c->ops->xinv3(c->U0(), c->work, c->tw, c->s);
-    c->ops->yinv3(c->work, c->tw, c->s);
-    c->ops->zc2r(c->work, u, c->tw, c->s);
-    if ((r = launched(c, "get_velocity"))) return r;
+    if (r || (r = get_velocity_m(c, 0, u))) return r;
     return leave(c);
 }
 
@@ -446,9 +607,9 @@ int dns_forward(dns_t* c, const void* u, void* uh) {
     int r = enter(c);
     if (r) return r;
     c->w_ready = false;
-    c->ops->zr2c(u, c->work, c->tw, c->s);
-    c->ops->yfwd3[c->sel[dns::P_YFWD3]](c->work, c->tw, c->s);
-    c->ops->xfwd3(c->work, c->Us(), c->tw, c->s);
+    c->ops->zr2c(u, c->W(), c->tw, c->s);
+    c->ops->yfwd3[c->sel[dns::P_YFWD3]](c->W(), c->tw, dns::Batch{1, 0, 0}, c->s);
+    c->ops->xfwd3(c->W(), c->Us(), c->tw, c->s);
     c->ops->layout(c->Us(), uh, false, c->s);
     if ((r = launched(c, "forward"))) return r;
     return leave(c);
@@ -460,9 +621,9 @@ int dns_inverse(dns_t* c, const void* uh, void* u) {
     if (r) return r;
     c->w_ready = false;
     c->ops->layout(uh, c->Us(), true, c->s);
-    c->ops->xinv3(c->Us(), c->work, c->tw, c->s);
-    c->ops->yinv3(c->work, c->tw, c->s);
-    c->ops->zc2r(c->work, u, c->tw, c->s);
+    c->ops->xinv3(c->Us(), c->W(), c->tw, c->s);
+    c->ops->yinv3(c->W(), c->tw, c->s);
+    c->ops->zc2r(c->W(), u, c->tw, c->s);
     if ((r = launched(c, "inverse"))) return r;
     return leave(c);
 }
@@ -472,24 +633,7 @@ int dns_step(dns_t* c, int nsteps) {
     if (!c->has_state) return fail(c, DNS_E_STATE, "no velocity set");
     if (nsteps == 0) return DNS_OK;
     int r = enter(c);
-    if (r) return r;
-    if (c->opts.fuse && !c->w_ready) {
-        launch_pass(c, dns::P_XINV, c->sel[dns::P_XINV], 0, nullptr, c->s);
-        if ((r = launched(c, "xinv_curl"))) return r;
-    }
-    for (int i = 0; i < nsteps; ++i) {
-        const long long n = c->steps + 1;
-        const bool diag = c->opts.diag_every > 0 && (n % c->opts.diag_every) == 0;
-        if (c->opts.use_graph) {
-            if ((r = build_graph(c, diag ? 1 : 0))) return r;
-            DNS_TRY(c, hipGraphLaunch(c->gexec[diag ? 1 : 0], c->s));
-        } else {
-            enqueue_step(c, diag, c->s);
-            if ((r = launched(c, "step"))) return r;
-        }
-        c->steps = n;
-    }
-    c->w_ready = c->opts.fuse != 0;
+    if (r || (r = step_all(c, nsteps, false))) return r;
     return leave(c);
 }
 
@@ -527,21 +671,7 @@ int dns_enstrophy(dns_t* c, double* W) {
 
 int dns_history(dns_t* c, double* E, double* W, int max, int* count) {
     if (!c || !count || max < 0 || (max > 0 && (!E || !W))) return fail(c, DNS_E_INVAL, "bad argument");
-    DNS_TRY(c, hipStreamSynchronize(c->s));
-    int n = 0;
-    DNS_TRY(c, hipMemcpy(&n, c->hist_count, sizeof(int), hipMemcpyDeviceToHost));
-    *count = n;
-    const int avail = n < c->opts.history_cap ? n : c->opts.history_cap;
-    const int m = avail < max ? avail : max;
-    if (m > 0) {
-        std::vector<double> h(2 * (size_t)m);
-        DNS_TRY(c, hipMemcpy(h.data(), c->hist, h.size() * sizeof(double), hipMemcpyDeviceToHost));
-        for (int i = 0; i < m; ++i) {
-            E[i] = h[2 * i];
-            W[i] = h[2 * i + 1];
-        }
-    }
-    return DNS_OK;
+    return history_m(c, 0, E, W, max, count);
 }
 
 int dns_steps_taken(const dns_t* c, long long* steps) {
@@ -604,15 +734,14 @@ int dns_profile_step(dns_t* c, int nsteps, float* ms, const char** names, int ma
 }
 
 // Time every tile-shape variant of every pass on the context's buffers and
-// keep the fastest.  The RHS pass is timed in its stage-1 form, which reads
-// U0 but writes only U1 and Us, so the current state is preserved.
+// keep the fastest.  The RHS passes are timed in their stage-1 form, which
+// reads U0 but writes only U1, Us and W, so the current state is preserved.
 int dns_autotune(dns_t* c, int reps) {
     if (!c || reps < 0) return fail(c, DNS_E_INVAL, "bad argument");
     if (reps == 0) reps = 3;
     int r = enter(c);
     if (r) return r;
-    for (auto& g : c->gexec)
-        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    drop_graphs(c);
     for (int p = 0; p < dns::P_COUNT; ++p) {
         float best = 1e30f;
         int bestv = c->sel[p];
@@ -651,8 +780,7 @@ int dns_set_plan(dns_t* c, const int* widths, int n) {
         if (sel[p] < 0) return fail(c, DNS_E_INVAL, "no variant of that width for this N and dtype");
     }
     DNS_TRY(c, hipStreamSynchronize(c->s));
-    for (auto& g : c->gexec)
-        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    drop_graphs(c);
     for (int p = 0; p < dns::P_COUNT; ++p) c->sel[p] = sel[p];
     c->w_ready = false;
     return DNS_OK;
@@ -680,5 +808,242 @@ const char* dns_strerror(int s) {
 }
 
 const char* dns_last_error(const dns_t* c) { return c ? c->err.c_str() : ""; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// C ABI: ensembles of independent simulations
+// ---------------------------------------------------------------------------
+struct dns_ens {
+    hipStream_t user = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<dns_t*> cls;              // one context per (N, nu, dt) class
+    std::vector<int> cls_of, idx_of;      // member i -> (class, index in class)
+    std::vector<char> ready;              // member i has a velocity field
+    hipGraphExec_t gexec = nullptr;       // one step of every class
+    std::string err;
+};
+
+namespace {
+
+int ens_fail(dns_ens_t* e, int code, const std::string& msg) {
+    if (e) e->err = msg;
+    return code;
+}
+
+int ens_enter(dns_ens_t* e) {
+    if (hipEventRecord(e->ev_in, e->user) != hipSuccess || hipStreamWaitEvent(e->s, e->ev_in, 0) != hipSuccess)
+        return ens_fail(e, DNS_E_HIP, "stream ordering");
+    return DNS_OK;
+}
+
+int ens_leave(dns_ens_t* e) {
+    if (hipEventRecord(e->ev_out, e->s) != hipSuccess || hipStreamWaitEvent(e->user, e->ev_out, 0) != hipSuccess)
+        return ens_fail(e, DNS_E_HIP, "stream ordering");
+    return DNS_OK;
+}
+
+int ens_cls_error(dns_ens_t* e, dns_t* c, int r) {
+    if (r != DNS_OK && c) e->err = c->err;
+    return r;
+}
+
+void ens_release(dns_ens_t* e) {
+    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+    for (dns_t* c : e->cls) {
+        release(c);
+        delete c;
+    }
+    e->cls.clear();
+    if (e->ev_in) (void)hipEventDestroy(e->ev_in);
+    if (e->ev_out) (void)hipEventDestroy(e->ev_out);
+    if (e->s) (void)hipStreamDestroy(e->s);
+}
+
+bool ens_member(const dns_ens_t* e, int i) { return e && i >= 0 && i < (int)e->cls_of.size(); }
+
+}  // namespace
+
+extern "C" {
+
+int dns_ens_create(int count, const int* N, const double* nu, const double* dt, int dtype, const dns_opts* opts,
+                   void* stream, dns_ens_t** out) {
+    if (!out) return DNS_E_INVAL;
+    *out = nullptr;
+    if (count <= 0 || !N || !nu || !dt) return DNS_E_INVAL;
+    dns_opts o;
+    dns_default_opts(&o);
+    if (opts) o = *opts;
+    for (int i = 0; i < count; ++i)
+        if (check_args(N[i], nu[i], dt[i], dtype, o)) return DNS_E_INVAL;
+    dns_ens_t* e = new (std::nothrow) dns_ens();
+    if (!e) return DNS_E_NOMEM;
+    e->user = (hipStream_t)stream;
+    if (hipStreamCreateWithFlags(&e->s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&e->ev_out, hipEventDisableTiming) != hipSuccess) {
+        ens_release(e);
+        delete e;
+        return DNS_E_HIP;
+    }
+    // group members by (N, nu, dt), in order of first appearance
+    std::vector<int> key_n;
+    std::vector<double> key_nu, key_dt;
+    std::vector<int> cnt;
+    e->cls_of.resize(count);
+    e->idx_of.resize(count);
+    e->ready.assign(count, 0);
+    for (int i = 0; i < count; ++i) {
+        int k = -1;
+        for (size_t j = 0; j < key_n.size(); ++j)
+            if (key_n[j] == N[i] && key_nu[j] == nu[i] && key_dt[j] == dt[i]) k = (int)j;
+        if (k < 0) {
+            k = (int)key_n.size();
+            key_n.push_back(N[i]);
+            key_nu.push_back(nu[i]);
+            key_dt.push_back(dt[i]);
+            cnt.push_back(0);
+        }
+        e->cls_of[i] = k;
+        e->idx_of[i] = cnt[k]++;
+    }
+    for (size_t k = 0; k < key_n.size(); ++k) {
+        dns_t* c = nullptr;
+        int r = create_ctx(key_n[k], key_nu[k], key_dt[k], dtype, o, e->s, cnt[k], e->s, &c);
+        if (r) {
+            ens_release(e);
+            delete e;
+            return r;
+        }
+        e->cls.push_back(c);
+    }
+    *out = e;
+    return DNS_OK;
+}
+
+int dns_ens_destroy(dns_ens_t* e) {
+    if (!e) return DNS_OK;
+    if (e->s) (void)hipStreamSynchronize(e->s);
+    ens_release(e);
+    delete e;
+    return DNS_OK;
+}
+
+int dns_ens_size(const dns_ens_t* e, int* count, int* classes) {
+    if (!e || !count) return DNS_E_INVAL;
+    *count = (int)e->cls_of.size();
+    if (classes) *classes = (int)e->cls.size();
+    return DNS_OK;
+}
+
+int dns_ens_set_spectral(dns_ens_t* e, int i, const void* uh) {
+    if (!ens_member(e, i) || !uh) return ens_fail(e, DNS_E_INVAL, "bad argument");
+    dns_t* c = e->cls[e->cls_of[i]];
+    int r = ens_enter(e);
+    if (r || (r = ens_cls_error(e, c, set_spectral_m(c, e->idx_of[i], uh))) || (r = reset_counters(c))) return r;
+    e->ready[i] = 1;
+    return ens_leave(e);
+}
+
+int dns_ens_set_velocity(dns_ens_t* e, int i, const void* u) {
+    if (!ens_member(e, i) || !u) return ens_fail(e, DNS_E_INVAL, "bad argument");
+    dns_t* c = e->cls[e->cls_of[i]];
+    int r = ens_enter(e);
+    if (r || (r = ens_cls_error(e, c, set_velocity_m(c, e->idx_of[i], u))) || (r = reset_counters(c))) return r;
+    e->ready[i] = 1;
+    return ens_leave(e);
+}
+
+int dns_ens_init_random(dns_ens_t* e, int i, unsigned long long seed, double k0, double energy) {
+    if (!ens_member(e, i) || !(k0 > 0.0) || !(energy > 0.0)) return ens_fail(e, DNS_E_INVAL, "bad argument");
+    dns_t* c = e->cls[e->cls_of[i]];
+    int r = ens_enter(e);
+    if (r || (r = ens_cls_error(e, c, init_random_m(c, e->idx_of[i], seed, k0, energy))) ||
+        (r = reset_counters(c)))
+        return r;
+    e->ready[i] = 1;
+    return ens_leave(e);
+}
+
+int dns_ens_get_spectral(dns_ens_t* e, int i, void* uh) {
+    if (!ens_member(e, i) || !uh) return ens_fail(e, DNS_E_INVAL, "bad argument");
+    dns_t* c = e->cls[e->cls_of[i]];
+    if (!e->ready[i]) return ens_fail(e, DNS_E_STATE, "no velocity set");
+    int r = ens_enter(e);
+    if (r || (r = ens_cls_error(e, c, get_spectral_m(c, e->idx_of[i], uh)))) return r;
+    return ens_leave(e);
+}
+
+int dns_ens_step(dns_ens_t* e, int nsteps, int mode) {
+    if (!e || nsteps < 0 || (mode != DNS_ENS_BATCHED && mode != DNS_ENS_PER_SIM))
+        return ens_fail(e, DNS_E_INVAL, "bad argument");
+    for (char ok : e->ready)
+        if (!ok) return ens_fail(e, DNS_E_STATE, "a member has no velocity set");
+    if (nsteps == 0) return DNS_OK;
+    int r = ens_enter(e);
+    if (r) return r;
+    bool diag = false;
+    for (dns_t* c : e->cls) diag = diag || c->opts.diag_every > 0;
+    if (mode == DNS_ENS_PER_SIM || diag || !e->cls[0]->opts.use_graph) {
+        // every class advanced by its own batched launches, or every member
+        // by its own launches (the unbatched baseline)
+        for (dns_t* c : e->cls)
+            if ((r = ens_cls_error(e, c, step_all(c, nsteps, mode == DNS_ENS_PER_SIM)))) return r;
+        return ens_leave(e);
+    }
+    // batched: one captured graph advances every class by one step
+    for (dns_t* c : e->cls)
+        if ((r = ens_cls_error(e, c, prepare_w(c)))) return r;
+    if (!e->gexec) {
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(e->s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return ens_fail(e, DNS_E_HIP, "hipStreamBeginCapture");
+        for (dns_t* c : e->cls) enqueue_step(c, false, e->s);
+        hipError_t le = hipGetLastError();
+        hipError_t ee = hipStreamEndCapture(e->s, &g);
+        if (le != hipSuccess || ee != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return ens_fail(e, DNS_E_HIP, "ensemble graph capture");
+        }
+        hipError_t ie = hipGraphInstantiate(&e->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return ens_fail(e, DNS_E_HIP, "hipGraphInstantiate");
+    }
+    for (int i = 0; i < nsteps; ++i)
+        if (hipGraphLaunch(e->gexec, e->s) != hipSuccess) return ens_fail(e, DNS_E_HIP, "hipGraphLaunch");
+    for (dns_t* c : e->cls) {
+        c->steps += nsteps;
+        c->w_ready = c->opts.fuse != 0;
+    }
+    return ens_leave(e);
+}
+
+int dns_ens_diagnostics(dns_ens_t* e, double* E, double* W) {
+    if (!e || (!E && !W)) return ens_fail(e, DNS_E_INVAL, "bad argument");
+    int r = ens_enter(e);
+    if (r) return r;
+    int status = DNS_OK;
+    for (size_t i = 0; i < e->cls_of.size(); ++i) {
+        dns_t* c = e->cls[e->cls_of[i]];
+        if (!e->ready[i]) return ens_fail(e, DNS_E_STATE, "a member has no velocity set");
+        double a = 0.0, b = 0.0;
+        r = reduce_state(c, c->U0(e->idx_of[i]), &a, &b);
+        if (r == DNS_E_NONFINITE) status = r;
+        else if (r) return ens_cls_error(e, c, r);
+        if (E) E[i] = a;
+        if (W) W[i] = b;
+    }
+    r = ens_leave(e);
+    return status ? status : r;
+}
+
+int dns_ens_synchronize(dns_ens_t* e) {
+    if (!e) return DNS_E_INVAL;
+    if (hipStreamSynchronize(e->s) != hipSuccess) return ens_fail(e, DNS_E_HIP, "hipStreamSynchronize");
+    return DNS_OK;
+}
+
+const char* dns_ens_last_error(const dns_ens_t* e) { return e ? e->err.c_str() : ""; }
 
 }  // extern "C"

@@ -81,6 +81,16 @@ template <typename R, int N> struct Cfg {
 // order and hence the result are reproducible).
 constexpr int DIAG_BLOCKS = 1024;
 
+// Independent simulations of one size batched into one launch: member m of a
+// launch is blockIdx.y = m, its state fields start sst complex values after
+// member m-1's and its work fields wst after.  A single simulation is
+// {1, 0, 0}.
+struct Batch {
+    int members;
+    size_t sst;
+    size_t wst;
+};
+
 // Per-stage coefficients of one RK4 stage of the fused x-forward kernel.
 struct StageArgs {
     double nu;       // viscosity

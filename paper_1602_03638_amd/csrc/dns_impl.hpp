@@ -37,55 +37,60 @@ template <typename R, int N> struct Impl {
     template <int T> static constexpr int x_groups() { return XCOLS / T + N / T; }
 
     // ---- pass launchers ----------------------------------------------------
-    template <int T> static void xinv(const void* U, void* W, const void* tw, hipStream_t s) {
-        hipLaunchKernelGGL((k_xinv_curl<R, N, T>), dim3(x_groups<T>()), dim3(G * T), 0, s,
-                           (const C*)U, (C*)W, (const C*)tw);
+    template <int T> static void xinv(const void* U, void* W, const void* tw, const Batch& b, hipStream_t s) {
+        hipLaunchKernelGGL((k_xinv_curl<R, N, T>), dim3(x_groups<T>(), b.members), dim3(G * T), 0, s,
+                           (const C*)U, (C*)W, (const C*)tw, b.sst, b.wst);
     }
     static constexpr int LY = (256 / G) < 1 ? 1 : ((256 / G) < N ? 256 / G : N);
-    template <int T, int DIR, int NF> static void ypass(void* W, const void* tw, hipStream_t s) {
-        hipLaunchKernelGGL((k_yline<R, N, T, DIR, NF>), dim3(N * ((N / 2) / T)), dim3(G * T), 0, s,
-                           (C*)W, (const C*)tw);
-        hipLaunchKernelGGL((k_yline_nyq<R, N, LY, DIR, NF>), dim3(N / LY), dim3(G * LY), 0, s,
-                           (C*)W, (const C*)tw);
+    template <int T, int DIR, int NF> static void ypass(void* W, const void* tw, const Batch& b, hipStream_t s) {
+        hipLaunchKernelGGL((k_yline<R, N, T, DIR, NF>), dim3(N * ((N / 2) / T), b.members), dim3(G * T), 0, s,
+                           (C*)W, (const C*)tw, b.wst);
+        hipLaunchKernelGGL((k_yline_nyq<R, N, LY, DIR, NF>), dim3(N / LY, b.members), dim3(G * LY), 0, s,
+                           (C*)W, (const C*)tw, b.wst);
     }
-    template <int T> static void yinv6(void* W, const void* tw, hipStream_t s) { ypass<T, +1, 6>(W, tw, s); }
-    template <int T> static void yfwd3(void* W, const void* tw, hipStream_t s) { ypass<T, -1, 3>(W, tw, s); }
-    template <int L> static void zcross(void* W, const void* tw, hipStream_t s) {
+    template <int T> static void yinv6(void* W, const void* tw, const Batch& b, hipStream_t s) {
+        ypass<T, +1, 6>(W, tw, b, s);
+    }
+    template <int T> static void yfwd3(void* W, const void* tw, const Batch& b, hipStream_t s) {
+        ypass<T, -1, 3>(W, tw, b, s);
+    }
+    template <int L> static void zcross(void* W, const void* tw, const Batch& b, hipStream_t s) {
         const R scale = (R)std::ldexp(1.0, -6 * ilog2(N));
-        hipLaunchKernelGGL((k_zcross<R, N, L>), dim3((N * N) / L), dim3(G * L), 0, s, (C*)W, (const C*)tw, scale);
+        hipLaunchKernelGGL((k_zcross<R, N, L>), dim3((N * N) / L, b.members), dim3(G * L), 0, s, (C*)W,
+                           (const C*)tw, scale, b.wst);
     }
     template <int T, int ST>
     static void xrhs_st(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
-                        hipStream_t s) {
-        hipLaunchKernelGGL((k_xrhs<R, N, T, ST>), dim3(x_groups<T>()), dim3(G * T), 0, s,
-                           (const C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a);
+                        const Batch& b, hipStream_t s) {
+        hipLaunchKernelGGL((k_xrhs<R, N, T, ST>), dim3(x_groups<T>(), b.members), dim3(G * T), 0, s,
+                           (const C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a, b.sst, b.wst);
     }
     template <int T>
     static void xrhs(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
-                     hipStream_t s) {
+                     const Batch& b, hipStream_t s) {
         switch (a.stage) {
-            case 0: xrhs_st<T, 0>(W, U0, U1, Us, tw, a, s); break;
-            case 1: xrhs_st<T, 1>(W, U0, U1, Us, tw, a, s); break;
-            case 2: xrhs_st<T, 2>(W, U0, U1, Us, tw, a, s); break;
-            case 3: xrhs_st<T, 3>(W, U0, U1, Us, tw, a, s); break;
-            default: xrhs_st<T, -1>(W, U0, U1, Us, tw, a, s); break;
+            case 0: xrhs_st<T, 0>(W, U0, U1, Us, tw, a, b, s); break;
+            case 1: xrhs_st<T, 1>(W, U0, U1, Us, tw, a, b, s); break;
+            case 2: xrhs_st<T, 2>(W, U0, U1, Us, tw, a, b, s); break;
+            case 3: xrhs_st<T, 3>(W, U0, U1, Us, tw, a, b, s); break;
+            default: xrhs_st<T, -1>(W, U0, U1, Us, tw, a, b, s); break;
         }
     }
 
     template <int T, int ST>
     static void xstage_st(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
-                          hipStream_t s) {
-        hipLaunchKernelGGL((k_xstage<R, N, T, ST>), dim3(x_groups<T>()), dim3(G * T), 0, s,
-                           (C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a);
+                          const Batch& b, hipStream_t s) {
+        hipLaunchKernelGGL((k_xstage<R, N, T, ST>), dim3(x_groups<T>(), b.members), dim3(G * T), 0, s,
+                           (C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a, b.sst, b.wst);
     }
     template <int T>
     static void xstage(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
-                       hipStream_t s) {
+                       const Batch& b, hipStream_t s) {
         switch (a.stage) {
-            case 0: xstage_st<T, 0>(W, U0, U1, Us, tw, a, s); break;
-            case 1: xstage_st<T, 1>(W, U0, U1, Us, tw, a, s); break;
-            case 2: xstage_st<T, 2>(W, U0, U1, Us, tw, a, s); break;
-            default: xstage_st<T, 3>(W, U0, U1, Us, tw, a, s); break;
+            case 0: xstage_st<T, 0>(W, U0, U1, Us, tw, a, b, s); break;
+            case 1: xstage_st<T, 1>(W, U0, U1, Us, tw, a, b, s); break;
+            case 2: xstage_st<T, 2>(W, U0, U1, Us, tw, a, b, s); break;
+            default: xstage_st<T, 3>(W, U0, U1, Us, tw, a, b, s); break;
         }
     }
 
@@ -101,7 +106,8 @@ template <typename R, int N> struct Impl {
         hipLaunchKernelGGL((k_xplain<R, N, TS, -1, 3>), dim3(x_groups<TS>()), dim3(G * TS), 0, s,
                            (const C*)W, (C*)U, (const C*)tw);
     }
-    static void yinv3(void* W, const void* tw, hipStream_t s) { ypass<YS, +1, 3>(W, tw, s); }
+    static void yinv3(void* W, const void* tw, hipStream_t s) { ypass<YS, +1, 3>(W, tw, Batch{1, 0, 0}, s); }
+    static void yfwd3s(void* W, const void* tw, hipStream_t s) { ypass<YS, -1, 3>(W, tw, Batch{1, 0, 0}, s); }
     static void zr2c(const void* u, void* W, const void* tw, hipStream_t s) {
         hipLaunchKernelGGL((k_zr2c<R, N, LS>), dim3((N * N) / LS), dim3(G * LS), 0, s,
                            (const R*)u, (C*)W, (const C*)tw);
@@ -123,6 +129,21 @@ template <typename R, int N> struct Impl {
     }
     static void diag_partial(const void* U, double* part, hipStream_t s) {
         hipLaunchKernelGGL((k_diag_partial<R, N>), dim3(DIAG_BLOCKS), dim3(256), 0, s, (const C*)U, part);
+    }
+
+    static void ic_physical(void* u, int kind, double p0, double p1, double p2, hipStream_t s) {
+        const size_t P = (size_t)N * N * N;
+        hipLaunchKernelGGL((k_ic_physical<R, N>), dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, (R*)u, kind,
+                           p0, p1, p2);
+    }
+    static void ic_random(void* U, unsigned long long seed, double k0, int mask_lim, hipStream_t s) {
+        const size_t FS = field_size(N);
+        hipLaunchKernelGGL((k_ic_random<R, N>), dim3((unsigned)((FS + 255) / 256)), dim3(256), 0, s, (C*)U, seed, k0,
+                           mask_lim);
+    }
+    static void scale(void* U, double factor, hipStream_t s) {
+        const size_t T = 3 * field_size(N);
+        hipLaunchKernelGGL((k_scale<R, N>), dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, (C*)U, factor);
     }
 
     // ---- variant tables ------------------------------------------------------
@@ -187,11 +208,15 @@ template <typename R, int N> struct Impl {
         o.def[P_ZCROSS] = pick(o, P_ZCROSS, 4);
         o.xinv3 = &xinv3;
         o.yinv3 = &yinv3;
+        o.yfwd3s = &yfwd3s;
         o.xfwd3 = &xfwd3;
         o.zr2c = &zr2c;
         o.zc2r = &zc2r;
         o.layout = &layout;
         o.diag_partial = &diag_partial;
+        o.ic_physical = &ic_physical;
+        o.ic_random = &ic_random;
+        o.scale = &scale;
         return o;
     }
     static const Ops* table() {

@@ -49,21 +49,27 @@ template <int N, bool NYQ> struct XCol {
 };
 
 // Element (row g + m G) of field f of the x tile, addressed as a uniform
-// base (field + m G rows, kept in scalar registers) plus one per-thread
-// 32-bit byte offset (column + g rows) shared by every field and row, so
-// that a thread holds one address register instead of one per element.
+// base (field + block start + m G rows, kept in scalar registers) plus one
+// per-thread 32-bit byte offset (column + g rows, relative to its block)
+// shared by every field and row, so that a thread holds one address
+// register instead of one per element.  Relative to the block start the
+// offset stays below 2^32 bytes for every supported N and precision.
 template <typename C, int N, int G, bool NYQ>
 struct XAddr {
-    unsigned tb;                                  // byte offset of (column, row g)
+    static constexpr size_t BLOCK = NYQ ? main_size(N) : 0;   // element offset of the block
+    unsigned tb;                                              // byte offset of (column, row g)
     __device__ __forceinline__ XAddr(const XCol<N, NYQ>& col, int g)
-        : tb((col.base + (unsigned)g * XCol<N, NYQ>::RS) * (unsigned)sizeof(C)) {}
+        : tb(((unsigned)(col.base - BLOCK) + (unsigned)g * XCol<N, NYQ>::RS) * (unsigned)sizeof(C)) {}
     __device__ __forceinline__ C& operator()(C* F, int m) const {
-        return *reinterpret_cast<C*>(reinterpret_cast<char*>(F + (size_t)m * G * XCol<N, NYQ>::RS) + tb);
+        return *reinterpret_cast<C*>(reinterpret_cast<char*>(F + BLOCK + (size_t)m * G * XCol<N, NYQ>::RS) + tb);
     }
     __device__ __forceinline__ const C& operator()(const C* F, int m) const {
-        return *reinterpret_cast<const C*>(reinterpret_cast<const char*>(F + (size_t)m * G * XCol<N, NYQ>::RS) + tb);
+        return *reinterpret_cast<const C*>(reinterpret_cast<const char*>(F + BLOCK + (size_t)m * G * XCol<N, NYQ>::RS) +
+                                           tb);
     }
 };
+
+static_assert((size_t)(1024 / 8) * 1024 * 512 * 16 < (size_t(1) << 32), "x-tile byte offsets must fit 32 bits");
 
 // Number of x-pass workgroups of width T over the main block.
 template <int N, int T> constexpr int x_main_tiles() { return (N * (N / 2)) / T; }
@@ -134,7 +140,10 @@ __device__ __forceinline__ void xinv_curl_tile(const cx<R>* __restrict__ U, cx<R
 
 template <typename R, int N, int T>
 __global__ __launch_bounds__(N / 8 * T)
-void k_xinv_curl(const cx<R>* __restrict__ U, cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
+void k_xinv_curl(const cx<R>* __restrict__ U, cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t sst,
+                 size_t wst) {
+    U += blockIdx.y * sst;
+    W += blockIdx.y * wst;
     __shared__ cx<R> lds[T * N];
     __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
     load_twiddles<R, N>(twl, tw);
@@ -178,7 +187,8 @@ void k_xplain(const cx<R>* __restrict__ S, cx<R>* __restrict__ D, const cx<R>* _
 // ---------------------------------------------------------------------------
 template <typename R, int N, int T, int DIR, int NF>
 __global__ __launch_bounds__(N / 8 * T)
-void k_yline(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
+void k_yline(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
+    W += blockIdx.y * wst;
     constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
     constexpr int ZT = (N / 2) / T;          // tiles per ix
@@ -203,7 +213,8 @@ void k_yline(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
 // y transform of the Nyquist plane (kz = N/2): line ix is contiguous.
 template <typename R, int N, int L, int DIR, int NF>
 __global__ __launch_bounds__(N / 8 * L)
-void k_yline_nyq(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
+void k_yline_nyq(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
+    W += blockIdx.y * wst;
     constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
     constexpr int LP = padded_line<N>(true);
@@ -270,7 +281,8 @@ __device__ __forceinline__ void zsplit(cx<R> pk, cx<R> pnk, cx<R>& A, cx<R>& B) 
 // ---------------------------------------------------------------------------
 template <typename R, int N, int L>
 __global__ __launch_bounds__(N / 8 * L)
-void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale) {
+void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale, size_t wst) {
+    W += blockIdx.y * wst;
     constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
     constexpr int LP = padded_line<N>(true);
@@ -706,7 +718,12 @@ __device__ __forceinline__ void xrhs_tile(const cx<R>* __restrict__ W, cx<R>* __
 template <typename R, int N, int T, int STAGE>
 __global__ __launch_bounds__(N / 8 * T)
 void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
-            cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa) {
+            cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa, size_t sst, size_t wst) {
+    W += blockIdx.y * wst;
+    U0 += blockIdx.y * sst;
+    U1 += blockIdx.y * sst;
+    Us += blockIdx.y * sst;
+    if (sa.diag) sa.diag += 2 * (size_t)gridDim.x * blockIdx.y;
     __shared__ cx<R> lds[T * N];
     __shared__ double red[2][N / 8 * T];
     __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
@@ -779,7 +796,12 @@ __device__ __forceinline__ void xstage_tile(cx<R>* __restrict__ W, cx<R>* __rest
 template <typename R, int N, int T, int STAGE>
 __global__ __launch_bounds__(N / 8 * T)
 void k_xstage(cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
-              cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa) {
+              cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa, size_t sst, size_t wst) {
+    W += blockIdx.y * wst;
+    U0 += blockIdx.y * sst;
+    U1 += blockIdx.y * sst;
+    Us += blockIdx.y * sst;
+    if (sa.diag) sa.diag += 2 * (size_t)gridDim.x * blockIdx.y;
     __shared__ cx<R> lds[T * N];
     __shared__ double red[2][N / 8 * T];
     __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
@@ -855,6 +877,141 @@ void k_diag_partial(const cx<R>* __restrict__ U, double* __restrict__ part) {
         part[2 * blockIdx.x] = se;
         part[2 * blockIdx.x + 1] = sw;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Initial conditions.
+// ---------------------------------------------------------------------------
+enum IcKind { IC_TAYLOR_GREEN = 0, IC_TAYLOR_GREEN_2D = 1, IC_ABC = 2, IC_SHEAR = 3 };
+
+// Analytic velocity on the mesh x_i = 2 pi i / N (Sec. 2, eq. realmesh),
+// written as a (3, N, N, N) real array; sin and cos of 2 pi i / N are taken
+// as sinpi/cospi of 2 i / N, so the angle is exact.
+//   Taylor-Green (Sec. 4.2, Appendix): (sin x cos y cos z, -cos x sin y cos z, 0)
+//   planar Taylor-Green: (sin x cos y, -cos x sin y, 0)
+//   ABC: (A sin z + C cos y, B sin x + A cos z, C sin y + B cos x)
+//   shear: (amp sin(k z), 0, 0)
+template <typename R, int N>
+__global__ __launch_bounds__(256) void k_ic_physical(R* __restrict__ u, int kind, double p0, double p1, double p2) {
+    constexpr size_t P = (size_t)N * N * N;
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= P) return;
+    const int ix = (int)(i / ((size_t)N * N)), iy = (int)((i / N) % N), iz = (int)(i % N);
+    const double tx = 2.0 * ix / N, ty = 2.0 * iy / N, tz = 2.0 * iz / N;
+    double a = 0.0, b = 0.0, c = 0.0;
+    if (kind == IC_TAYLOR_GREEN) {
+        a = sinpi(tx) * cospi(ty) * cospi(tz);
+        b = -cospi(tx) * sinpi(ty) * cospi(tz);
+    } else if (kind == IC_TAYLOR_GREEN_2D) {
+        a = sinpi(tx) * cospi(ty);
+        b = -cospi(tx) * sinpi(ty);
+    } else if (kind == IC_ABC) {
+        a = p0 * sinpi(tz) + p2 * cospi(ty);
+        b = p1 * sinpi(tx) + p0 * cospi(tz);
+        c = p2 * sinpi(ty) + p1 * cospi(tx);
+    } else {
+        // sin(k z) with the integer k reduced modulo N: sinpi(2 (k iz mod N) / N)
+        const long kk = (long)p0;
+        const long r = ((kk % N) * iz % N + N) % N;
+        a = p1 * sinpi(2.0 * r / N);
+    }
+    u[i] = (R)a;
+    u[P + i] = (R)b;
+    u[2 * P + i] = (R)c;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): output function for counter x.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+    unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ double unit53(unsigned long long z) {
+    return ((double)(z >> 11) + 1.0) * 0x1.0p-53;   // (0, 1]
+}
+
+// Random solenoidal spectrum, one thread per stored mode (internal layout):
+// complex Gaussian components from SplitMix64 counters (key = seed << 40 xor
+// the mode's flat index in the external (3, N, N, N/2+1) order; uniforms from
+// counters 2 key and 2 key + 1) via Box-Muller, projected onto k-perpendicular,
+// amplitude sqrt(E(|k|) / (4 pi |k|^2)) N^3 with E(k) = k^4 exp(-2 (k/k0)^2),
+// zero at k = 0 and outside the dealias mask.  On the kz = 0 and kz = N/2
+// planes a mode whose mirror (-kx, -ky) comes first in (iy, ix) order takes
+// the conjugate of the mirror's value (recomputed from the mirror's own
+// counters); a self-mirrored mode keeps its real part.  The energy is
+// normalised afterwards by the host.
+template <typename R, int N>
+__global__ __launch_bounds__(256) void k_ic_random(cx<R>* __restrict__ U, unsigned long long seed, double k0,
+                                                   int mask_lim) {
+    constexpr size_t FS = field_size(N);
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= FS) return;
+    int ix, iy, iz;
+    if (i < main_size(N)) {
+        iz = (int)(i % (N / 2));
+        iy = (int)((i / (N / 2)) % N);
+        ix = (int)(i / ((size_t)N * (N / 2)));
+    } else {
+        const size_t r = i - main_size(N);
+        iz = N / 2;
+        iy = (int)(r % N);
+        ix = (int)(r / N);
+    }
+    int sx = ix, sy = iy;
+    bool conj = false, real_only = false;
+    if (iz == 0 || iz == N / 2) {
+        const int mx = (N - ix) % N, my = (N - iy) % N;
+        if (mx == ix && my == iy) real_only = true;
+        else if (my < iy || (my == iy && mx < ix)) { sx = mx; sy = my; conj = true; }
+    }
+    const int kx = kfreq(sx, N), ky = kfreq(sy, N), kz = iz;
+    const long k2 = (long)kx * kx + (long)ky * ky + (long)kz * kz;
+    const bool keep = (3 * abs(kx) < mask_lim) && (3 * abs(ky) < mask_lim) && (3 * abs(kz) < mask_lim) && k2 > 0;
+    double gr[3], gi[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const unsigned long long idx =
+            (((unsigned long long)c * N + sx) * N + sy) * (unsigned long long)(N / 2 + 1) + (unsigned long long)iz;
+        const unsigned long long key = (seed << 40) ^ idx;
+        const double u1 = unit53(splitmix64(key * 2ull));
+        const double u2 = unit53(splitmix64(key * 2ull + 1ull));
+        const double rad = sqrt(-2.0 * log(u1));
+        const double h = 0.70710678118654752440;
+        gr[c] = rad * cos(2.0 * M_PI * u2) * h;
+        gi[c] = rad * sin(2.0 * M_PI * u2) * h;
+    }
+    double vr[3] = {0.0, 0.0, 0.0}, vi[3] = {0.0, 0.0, 0.0};
+    if (keep) {
+        const double fk[3] = {(double)kx, (double)ky, (double)kz};
+        const double inv = 1.0 / (double)k2;
+        const double pr = (fk[0] * gr[0] + fk[1] * gr[1] + fk[2] * gr[2]) * inv;
+        const double pi_ = (fk[0] * gi[0] + fk[1] * gi[1] + fk[2] * gi[2]) * inv;
+        const double kmag = sqrt((double)k2);
+        const double spec = kmag * kmag * kmag * kmag * exp(-2.0 * (kmag / k0) * (kmag / k0));
+        const double amp = sqrt(spec / (4.0 * M_PI * kmag * kmag)) * ((double)N * N * N);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            vr[c] = (gr[c] - fk[c] * pr) * amp;
+            vi[c] = (gi[c] - fk[c] * pi_) * amp;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double im = conj ? -vi[c] : vi[c];
+        if (real_only) im = 0.0;
+        U[c * FS + i] = {(R)vr[c], (R)im};
+    }
+}
+
+// Multiply the three fields at U by s (energy normalisation).
+template <typename R, int N>
+__global__ __launch_bounds__(256) void k_scale(cx<R>* __restrict__ U, double s) {
+    constexpr size_t TOT = 3 * field_size(N);
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= TOT) return;
+    const cx<R> a = U[i];
+    U[i] = {(R)(a.x * s), (R)(a.y * s)};
 }
 
 }  // namespace dns

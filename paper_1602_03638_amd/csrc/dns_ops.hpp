@@ -16,11 +16,11 @@ constexpr int MAXV = 4;   // variants per pass
 // with the next stage's inverse x pass.
 enum Pass { P_XINV = 0, P_YINV6, P_ZCROSS, P_YFWD3, P_XRHS, P_XSTAGE, P_COUNT };
 
-using XinvFn = void (*)(const void* U, void* W, const void* tw, hipStream_t s);
-using YFn = void (*)(void* W, const void* tw, hipStream_t s);
-using ZFn = void (*)(void* W, const void* tw, hipStream_t s);
+using XinvFn = void (*)(const void* U, void* W, const void* tw, const Batch& b, hipStream_t s);
+using YFn = void (*)(void* W, const void* tw, const Batch& b, hipStream_t s);
+using ZFn = void (*)(void* W, const void* tw, const Batch& b, hipStream_t s);
 using XrhsFn = void (*)(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
-                        hipStream_t s);
+                        const Batch& b, hipStream_t s);
 
 struct Ops {
     int N;
@@ -42,11 +42,15 @@ struct Ops {
     // standalone transforms and utilities (default shapes)
     void (*xinv3)(const void* U, void* W, const void* tw, hipStream_t s);
     void (*yinv3)(void* W, const void* tw, hipStream_t s);
+    void (*yfwd3s)(void* W, const void* tw, hipStream_t s);   // single simulation
     void (*xfwd3)(const void* W, void* U, const void* tw, hipStream_t s);
     void (*zr2c)(const void* u, void* W, const void* tw, hipStream_t s);
     void (*zc2r)(const void* W, void* u, const void* tw, hipStream_t s);
     void (*layout)(const void* src, void* dst, bool to_internal, hipStream_t s);
     void (*diag_partial)(const void* U, double* part, hipStream_t s);
+    void (*ic_physical)(void* u, int kind, double p0, double p1, double p2, hipStream_t s);
+    void (*ic_random)(void* U, unsigned long long seed, double k0, int mask_lim, hipStream_t s);
+    void (*scale)(void* U, double factor, hipStream_t s);
 };
 
 const Ops* ops_f64(int N);

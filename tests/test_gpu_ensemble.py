@@ -1,0 +1,185 @@
+"""Initial-condition kernels and ensembles of independent simulations, on the
+GPU through the C ABI.
+
+Initial conditions: the closed-form fields of dns_init_velocity equal the
+oracle's transform of the same fields sampled on the mesh, and the seeded
+random spectrum of dns_init_random equals oracle.ic.random_isotropic, both to
+FP64 rounding (relative L2 <= 1e-13).
+
+Ensembles: every member of a batched ensemble is bitwise equal to the same
+simulation run alone, batched and per-simulation launches are bitwise equal,
+and a member agrees with the oracle after several steps.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import note, rel_l2, spectral_rel_l2, to_dev, to_host
+from oracle import ic, spectral
+
+pytestmark = pytest.mark.gpu
+
+TOL_F64 = 1e-13
+TOL_F32 = 2e-6
+
+IC_CASES = [
+    ("taylor_green", (), lambda N: workloads.taylor_green(N)),
+    ("taylor_green_2d", (), lambda N: workloads.taylor_green_2d(N)),
+    ("abc", (0.9, 0.7, 0.5), lambda N: workloads.abc_flow(N, 0.9, 0.7, 0.5)),
+    ("abc", (), lambda N: workloads.abc_flow(N)),
+    ("shear", (3, 0.8), lambda N: workloads.shear_mode(N, 3, 0.8)),
+]
+
+
+def _solver(N, nu=0.01, dt=0.005, dtype="f64", **kw):
+    from paper_1602_03638_amd import Solver
+    return Solver(N, nu, dt, dtype=dtype, **kw)
+
+
+def _ensemble(Ns, nus, dts, dtype="f64", **kw):
+    from paper_1602_03638_amd import Ensemble
+    return Ensemble(Ns, nus, dts, dtype=dtype, **kw)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("N", [16, 32])
+@pytest.mark.parametrize("case", range(len(IC_CASES)))
+def test_init_velocity_matches_transformed_field(case, N, dtype):
+    kind, params, field = IC_CASES[case]
+    note(f"init_velocity {kind}{params} N={N} {dtype}")
+    s = _solver(N, dtype=dtype).init_velocity(kind, params)
+    got = to_host(s.get_spectral())
+    ref = spectral.dft3(field(N))
+    assert spectral_rel_l2(got, ref) <= (TOL_F64 if dtype == "f64" else TOL_F32)
+    E = s.energy()
+    assert abs(E - spectral.energy(ref)) <= 1e-12 * spectral.energy(ref) + (0 if dtype == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("N", [16, 32, 64])
+def test_init_random_matches_oracle(N, dtype):
+    note(f"init_random N={N} {dtype}")
+    seed, k0 = 1000 + N, 4.0
+    s = _solver(N, dtype=dtype).init_random(seed, k0=k0, energy=0.5)
+    got = to_host(s.get_spectral())
+    ref = ic.random_isotropic(N, seed, k0=k0, energy_target=0.5)
+    assert spectral_rel_l2(got, ref) <= (TOL_F64 if dtype == "f64" else TOL_F32)
+    assert abs(s.energy() - 0.5) <= (1e-13 if dtype == "f64" else 1e-6)
+
+
+def test_init_random_appendix_rule_and_energy():
+    note("init_random appendix rule")
+    N, seed = 32, 5
+    s = _solver(N, dealias="appendix").init_random(seed, k0=3.0, energy=1.25)
+    ref = ic.random_isotropic(N, seed, k0=3.0, energy_target=1.25, rule="appendix")
+    assert spectral_rel_l2(to_host(s.get_spectral()), ref) <= TOL_F64
+
+
+def test_init_velocity_steps_like_set_velocity():
+    """A step from the kernel-made Taylor-Green field equals a step from the
+    uploaded one to rounding, and the oracle after 10 steps."""
+    note("init_velocity tg32 10 steps")
+    N, nu, dt = 32, 0.01, 0.01
+    s = _solver(N, nu, dt).init_velocity("taylor_green").step(10)
+    orc = spectral.Solver(N, nu, dt).set_velocity(workloads.taylor_green(N)).step(10)
+    assert spectral_rel_l2(to_host(s.get_spectral()), orc.uh) <= 1e-12
+
+
+def test_init_errors():
+    from paper_1602_03638_amd import DnsError
+    note("init errors")
+    s = _solver(16)
+    with pytest.raises(DnsError):
+        s.init_random(1, k0=-1.0)
+    with pytest.raises(DnsError):
+        s.init_random(1, energy=0.0)
+    with pytest.raises(KeyError):
+        s.init_velocity("vortex_sheet")
+
+
+# ---------------------------------------------------------------------------
+# ensembles
+# ---------------------------------------------------------------------------
+
+def _members(Ns, seeds, dtype):
+    return [ic.random_isotropic(N, sd).astype(np.complex64 if dtype == "f32" else np.complex128)
+            for N, sd in zip(Ns, seeds)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("fuse", [True, False])
+def test_ensemble_members_equal_standalone_runs(dtype, fuse):
+    """Mixed sizes and viscosities: three classes; every member after 3 steps
+    is bitwise the standalone run, batched and per-simulation alike."""
+    note(f"ensemble vs standalone {dtype} fuse={fuse}")
+    Ns = [16, 32, 16, 16, 32]
+    nus = [0.01, 0.01, 0.02, 0.01, 0.01]
+    dts = [0.005] * 5
+    seeds = [11, 12, 13, 14, 15]
+    ens = _ensemble(Ns, nus, dts, dtype=dtype, fuse=fuse)
+    assert ens.classes() == 3
+    init = _members(Ns, seeds, dtype)
+    for i, h in enumerate(init):
+        ens.set_spectral(i, to_dev(h, dtype))
+    ens.step(3, batched=True)
+    batched = [to_host(ens.get_spectral(i)) for i in range(len(Ns))]
+    for i, h in enumerate(init):
+        ens.set_spectral(i, to_dev(h, dtype))
+    ens.step(3, batched=False)
+    per_sim = [to_host(ens.get_spectral(i)) for i in range(len(Ns))]
+    for i, (N, nu, dt) in enumerate(zip(Ns, nus, dts)):
+        alone = to_host(_solver(N, nu, dt, dtype=dtype, fuse=fuse).set_spectral(to_dev(init[i], dtype))
+                        .step(3).get_spectral())
+        assert np.array_equal(batched[i], alone), i
+        assert np.array_equal(per_sim[i], alone), i
+
+
+def test_ensemble_batched_graph_replays_and_matches_oracle():
+    """Two members of each of two sizes, 4 steps as 1 + 3 graph replays;
+    member 3 against the oracle (FP64, relative L2 <= 1e-12)."""
+    note("ensemble replays vs oracle")
+    Ns = [16, 32, 16, 32]
+    nu, dt = 0.01, 0.005
+    ens = _ensemble(Ns, [nu] * 4, [dt] * 4)
+    for i, N in enumerate(Ns):
+        ens.init_random(i, 200 + i)
+    ens.step(1).step(3)
+    orc = spectral.Solver(32, nu, dt).set_spectral(ic.random_isotropic(32, 203)).step(4)
+    assert spectral_rel_l2(to_host(ens.get_spectral(3)), orc.uh) <= 1e-12
+    E, W = ens.diagnostics()
+    assert abs(E[3] - orc.energy()) <= 1e-12 * orc.energy()
+    assert abs(W[3] - orc.enstrophy()) <= 1e-12 * orc.enstrophy()
+    # member 0 through the same path as a standalone solver
+    alone = _solver(16, nu, dt).init_random(200).step(4)
+    assert np.array_equal(to_host(ens.get_spectral(0)), to_host(alone.get_spectral()))
+    assert (E[0], W[0]) == alone.diagnostics()
+
+
+def test_ensemble_set_velocity_and_no_graph():
+    note("ensemble set_velocity, no graph")
+    N, nu, dt = 16, 0.01, 0.01
+    ens = _ensemble([N, N], [nu, nu], [dt, dt], use_graph=False)
+    ens.set_velocity(0, to_dev(workloads.taylor_green(N), "f64"))
+    ens.set_velocity(1, to_dev(workloads.abc_flow(N, 0.9, 0.7, 0.5), "f64"))
+    ens.step(5)
+    for i, u0 in enumerate([workloads.taylor_green(N), workloads.abc_flow(N, 0.9, 0.7, 0.5)]):
+        orc = spectral.Solver(N, nu, dt).set_velocity(u0).step(5)
+        assert spectral_rel_l2(to_host(ens.get_spectral(i)), orc.uh) <= 1e-12, i
+
+
+def test_ensemble_errors():
+    from paper_1602_03638_amd import DNS_E_STATE, DnsError
+    note("ensemble errors")
+    ens = _ensemble([16, 16], [0.01, 0.01], [0.01, 0.01])
+    ens.init_random(0, 1)
+    with pytest.raises(DnsError) as e:
+        ens.step(1)
+    assert e.value.status == DNS_E_STATE
+    with pytest.raises(DnsError):
+        ens.get_spectral(1)
+    with pytest.raises(DnsError):
+        ens.init_random(2, 1)
+    with pytest.raises(ValueError):
+        ens.set_spectral(0, to_dev(workloads.random_half_spectrum(8, 1), "f64"))
+    with pytest.raises(DnsError):
+        _ensemble([16, 12], [0.01, 0.01], [0.01, 0.01])
