@@ -98,6 +98,50 @@ def run_gpu(N, dtype, steps, warmup, prof_steps):
     return out
 
 
+# Ensemble workload: 64 members at 32^3, 16 at 64^3 and 4 at 128^3, FP32,
+# seeded random isotropic fields (member j: seed 1000 + j, k0 = 4, E = 0.5).
+ENSEMBLE = [(32, 64), (64, 16), (128, 4)]
+ENS_NU, ENS_DT = 0.01, 0.005
+
+
+def run_ensemble(steps, warmup, per_sim_steps):
+    """Ensemble steps per second, batched (one captured graph per step whose
+    kernels each advance every member of one size) against per-simulation
+    launches of the same kernels."""
+    import torch
+    from paper_1602_03638_amd import Ensemble
+
+    Ns = [N for N, count in ENSEMBLE for _ in range(count)]
+    ens = Ensemble(Ns, [ENS_NU] * len(Ns), [ENS_DT] * len(Ns), dtype="f32")
+    for j in range(len(Ns)):
+        ens.init_random(j, 1000 + j, k0=4.0, energy=0.5)
+
+    def timed(n, batched):
+        ens.step(warmup, batched=batched)
+        ens.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ens.step(n, batched=batched)
+        ens.synchronize()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / n
+
+    ms_b = timed(steps, True)
+    ms_p = timed(per_sim_steps, False)
+    E, _ = ens.diagnostics()
+    ens.close()
+    fields = sum(count * field_bytes(N, "f32") for N, count in ENSEMBLE)
+    return {"workload": "+".join(f"{count}x{N}^3" for N, count in ENSEMBLE) + " f32 random isotropic",
+            "members": len(Ns), "nu": ENS_NU, "dt": ENS_DT,
+            "batched": {"steps": steps, "ms_per_step": round(ms_b, 4), "ens_steps_per_s": round(1e3 / ms_b, 1),
+                        "sim_steps_per_s": round(len(Ns) * 1e3 / ms_b, 1),
+                        "model_GBps": round(FIELDS_PER_STEP * fields / (ms_b * 1e-3) / 1e9, 1)},
+            "per_sim": {"steps": per_sim_steps, "ms_per_step": round(ms_p, 4),
+                        "ens_steps_per_s": round(1e3 / ms_p, 1),
+                        "sim_steps_per_s": round(len(Ns) * 1e3 / ms_p, 1)},
+            "speedup": round(ms_p / ms_b, 2), "energy_mean": sum(E) / len(E)}
+
+
 def cpu_baseline(N):
     """Time the CPU oracle on a bounded sample of the workload: one inverse and
     one forward 3D transform of one velocity component at N^3, scaled to one
@@ -197,6 +241,10 @@ def main(argv=None):
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ensemble-only", action="store_true")
+    ap.add_argument("--ens-steps", type=int, default=100)
+    ap.add_argument("--ens-per-sim-steps", type=int, default=20)
     ap.add_argument("--sweep", action="store_true", help="only time every kernel variant at --N")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="only time a plain device copy of this many GiB (counter calibration)")
@@ -212,6 +260,9 @@ def main(argv=None):
               "(the slab decomposition over several GPUs is described, not built)", file=sys.stderr)
         return 2
 
+    if a.ensemble_only:
+        print(json.dumps({"ensemble": run_ensemble(a.ens_steps, a.warmup, a.ens_per_sim_steps)}), flush=True)
+        return 0
     if a.no_fp64:
         f32 = run_gpu(a.N, "f32", a.steps, a.warmup, a.prof_steps)
         print(json.dumps({"fp32": f32, "N": a.N, "steps": a.steps}), flush=True)
@@ -230,6 +281,7 @@ def main(argv=None):
                 "traffic": None if tr is None else round(tr / 1e9, 3), "traffic_unit": "GB per launch",
                 "bytes_per_launch": FIELDS_PER_LAUNCH[dom] * C,
                 "mean_launch_ms": f64["kernels_ms"][dom]}
+    ens = None if a.no_ensemble else run_ensemble(a.ens_steps, a.warmup, a.ens_per_sim_steps)
     cpu = None if a.no_cpu_baseline else cpu_baseline(a.N)
     line = {
         "metric": METRIC, "value": round(f64["ms_per_step"], 4), "unit": "ms/step",
@@ -250,6 +302,8 @@ def main(argv=None):
                         "energy": f32["energy"], "enstrophy": f32["enstrophy"],
                         "rel_energy_diff_vs_fp64": abs(f32["energy"] - f64["energy"]) / f64["energy"],
                         "kernels_ms": f32["kernels_ms"]}
+    if ens is not None:
+        line["ensemble"] = ens
     print(json.dumps(line), flush=True)
     return 0
 
