@@ -104,7 +104,7 @@ ENSEMBLE = [(32, 64), (64, 16), (128, 4)]
 ENS_NU, ENS_DT = 0.01, 0.005
 
 
-def run_ensemble(steps, warmup, per_sim_steps):
+def run_ensemble(steps, warmup, per_sim_steps, autotune=True):
     """Ensemble steps per second, batched (one captured graph per step whose
     kernels each advance every member of one size) against per-simulation
     launches of the same kernels."""
@@ -112,7 +112,7 @@ def run_ensemble(steps, warmup, per_sim_steps):
     from paper_1602_03638_amd import Ensemble
 
     Ns = [N for N, count in ENSEMBLE for _ in range(count)]
-    ens = Ensemble(Ns, [ENS_NU] * len(Ns), [ENS_DT] * len(Ns), dtype="f32")
+    ens = Ensemble(Ns, [ENS_NU] * len(Ns), [ENS_DT] * len(Ns), dtype="f32", autotune=autotune)
     for j in range(len(Ns)):
         ens.init_random(j, 1000 + j, k0=4.0, energy=0.5)
 
@@ -132,7 +132,7 @@ def run_ensemble(steps, warmup, per_sim_steps):
     ens.close()
     fields = sum(count * field_bytes(N, "f32") for N, count in ENSEMBLE)
     return {"workload": "+".join(f"{count}x{N}^3" for N, count in ENSEMBLE) + " f32 random isotropic",
-            "members": len(Ns), "nu": ENS_NU, "dt": ENS_DT,
+            "members": len(Ns), "nu": ENS_NU, "dt": ENS_DT, "autotuned_tiles": autotune,
             "batched": {"steps": steps, "ms_per_step": round(ms_b, 4), "ens_steps_per_s": round(1e3 / ms_b, 1),
                         "sim_steps_per_s": round(len(Ns) * 1e3 / ms_b, 1),
                         "model_GBps": round(FIELDS_PER_STEP * fields / (ms_b * 1e-3) / 1e9, 1)},
@@ -245,6 +245,7 @@ def main(argv=None):
     ap.add_argument("--ensemble-only", action="store_true")
     ap.add_argument("--ens-steps", type=int, default=100)
     ap.add_argument("--ens-per-sim-steps", type=int, default=20)
+    ap.add_argument("--ens-default-tiles", action="store_true", help="ensemble without the tile autotuner")
     ap.add_argument("--sweep", action="store_true", help="only time every kernel variant at --N")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="only time a plain device copy of this many GiB (counter calibration)")
@@ -261,7 +262,8 @@ def main(argv=None):
         return 2
 
     if a.ensemble_only:
-        print(json.dumps({"ensemble": run_ensemble(a.ens_steps, a.warmup, a.ens_per_sim_steps)}), flush=True)
+        ens = run_ensemble(a.ens_steps, a.warmup, a.ens_per_sim_steps, not a.ens_default_tiles)
+        print(json.dumps({"ensemble": ens}), flush=True)
         return 0
     if a.no_fp64:
         f32 = run_gpu(a.N, "f32", a.steps, a.warmup, a.prof_steps)
@@ -281,7 +283,7 @@ def main(argv=None):
                 "traffic": None if tr is None else round(tr / 1e9, 3), "traffic_unit": "GB per launch",
                 "bytes_per_launch": FIELDS_PER_LAUNCH[dom] * C,
                 "mean_launch_ms": f64["kernels_ms"][dom]}
-    ens = None if a.no_ensemble else run_ensemble(a.ens_steps, a.warmup, a.ens_per_sim_steps)
+    ens = None if a.no_ensemble else run_ensemble(a.ens_steps, a.warmup, a.ens_per_sim_steps, not a.ens_default_tiles)
     cpu = None if a.no_cpu_baseline else cpu_baseline(a.N)
     line = {
         "metric": METRIC, "value": round(f64["ms_per_step"], 4), "unit": "ms/step",

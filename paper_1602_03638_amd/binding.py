@@ -367,7 +367,8 @@ class Ensemble:
     equal (N, nu, dt) are batched into one launch per kernel.
     """
 
-    def __init__(self, Ns, nus, dts, dtype="f64", dealias="text", use_graph=True, fuse=True, stream=None):
+    def __init__(self, Ns, nus, dts, dtype="f64", dealias="text", use_graph=True, fuse=True, autotune=False,
+                 stream=None):
         import torch
         self._torch = torch
         lib = load_library()
@@ -380,6 +381,7 @@ class Ensemble:
         o.dealias = {"text": DNS_DEALIAS_TEXT, "appendix": DNS_DEALIAS_APPENDIX}[dealias]
         o.use_graph = 1 if use_graph else 0
         o.fuse = 1 if fuse else 0
+        o.autotune = 1 if autotune else 0
         if stream is None:
             stream = torch.cuda.current_stream()
         h = ctypes.c_void_p()

@@ -917,6 +917,12 @@ int dns_ens_create(int count, const int* N, const double* nu, const double* dt, 
             return r;
         }
         e->cls.push_back(c);
+        // tile shapes timed on the batched launches of this class
+        if (o.autotune && (r = dns_autotune(c, 3)) != DNS_OK) {
+            ens_release(e);
+            delete e;
+            return r;
+        }
     }
     *out = e;
     return DNS_OK;

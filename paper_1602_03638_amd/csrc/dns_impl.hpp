@@ -2,6 +2,7 @@
 // per-precision translation units, which instantiate every supported N.
 #pragma once
 
+#include <algorithm>
 #include <cmath>
 
 #include "dns_kernels.hpp"
@@ -30,8 +31,9 @@ template <typename R, int N> struct Impl {
     template <int T> static constexpr bool y_ok() {
         return T <= N / 2 && G * T <= 1024 && (size_t)T * N * CB <= LDS_LIMIT;
     }
+    // z shapes: at least 16 threads, and up to 128 threads for small N
     template <int L> static constexpr bool z_ok() {
-        return L <= N * N && G * L <= 1024 &&
+        return L <= N * N && G * L <= 1024 && G * L >= 16 && L <= (128 / G > 8 ? 128 / G : 8) &&
                (size_t)L * padded_line<N>(true) * CB + (size_t)tw_size(N) * CB <= LDS_LIMIT;
     }
     template <int T> static constexpr int x_groups() { return XCOLS / T + N / T; }
@@ -41,11 +43,8 @@ template <typename R, int N> struct Impl {
         hipLaunchKernelGGL((k_xinv_curl<R, N, T>), dim3(x_groups<T>(), b.members), dim3(G * T), 0, s,
                            (const C*)U, (C*)W, (const C*)tw, b.sst, b.wst);
     }
-    static constexpr int LY = (256 / G) < 1 ? 1 : ((256 / G) < N ? 256 / G : N);
     template <int T, int DIR, int NF> static void ypass(void* W, const void* tw, const Batch& b, hipStream_t s) {
-        hipLaunchKernelGGL((k_yline<R, N, T, DIR, NF>), dim3(N * ((N / 2) / T), b.members), dim3(G * T), 0, s,
-                           (C*)W, (const C*)tw, b.wst);
-        hipLaunchKernelGGL((k_yline_nyq<R, N, LY, DIR, NF>), dim3(N / LY, b.members), dim3(G * LY), 0, s,
+        hipLaunchKernelGGL((k_yline<R, N, T, DIR, NF>), dim3(y_tiles<R, N, T>(), b.members), dim3(G * T), 0, s,
                            (C*)W, (const C*)tw, b.wst);
     }
     template <int T> static void yinv6(void* W, const void* tw, const Batch& b, hipStream_t s) {
@@ -97,7 +96,7 @@ template <typename R, int N> struct Impl {
     // ---- standalone transforms (fixed shapes) -------------------------------
     static constexpr int TS = x_ok<8>() ? 8 : (x_ok<4>() ? 4 : (x_ok<2>() ? 2 : 1));
     static constexpr int YS = y_ok<8>() ? 8 : (y_ok<4>() ? 4 : (y_ok<2>() ? 2 : 1));
-    static constexpr int LS = z_ok<4>() ? 4 : (z_ok<2>() ? 2 : 1);
+    static constexpr int LS = N >= 128 ? 4 : 512 / N;
     static void xinv3(const void* U, void* W, const void* tw, hipStream_t s) {
         hipLaunchKernelGGL((k_xplain<R, N, TS, +1, 3>), dim3(x_groups<TS>()), dim3(G * TS), 0, s,
                            (const C*)U, (C*)W, (const C*)tw);
@@ -148,6 +147,7 @@ template <typename R, int N> struct Impl {
 
     // ---- variant tables ------------------------------------------------------
     template <int T> static void add_x(Ops& o) {
+        if constexpr (T > 16 && N > 64) return;    // wide tiles only for small N
         if constexpr (x_ok<T>()) {
             int& n = o.nvar[P_XINV];
             o.xinv[n] = &xinv<T>;
@@ -194,18 +194,21 @@ template <typename R, int N> struct Impl {
         o.N = N;
         o.real_size = sizeof(R);
         o.tw_count = tw_size(N) > 0 ? tw_size(N) : 1;
-        add_x<4>(o); add_x<8>(o); add_x<16>(o);
+        add_x<4>(o); add_x<8>(o); add_x<16>(o); add_x<32>(o);
         add_y<4>(o); add_y<8>(o); add_y<16>(o); add_y<32>(o);
         add_z<1>(o); add_z<2>(o); add_z<4>(o); add_z<8>(o);
+        add_z<16>(o); add_z<32>(o); add_z<64>(o); add_z<128>(o);
         // defaults: 128-byte row segments in the x and y passes, four z lines
-        // per workgroup (the fastest measured on MI355X at 256^3 and 512^3)
-        const int xw = (int)(128 / CB), yw = (int)(128 / CB);
+        // per workgroup (the fastest measured on MI355X at 256^3 and 512^3);
+        // for small N, at least one full 64-lane wave per workgroup
+        const int wave = 64 / G;
+        const int xw = std::max((int)(128 / CB), wave), yw = xw;
         o.def[P_XINV] = pick(o, P_XINV, xw);
         o.def[P_XRHS] = pick(o, P_XRHS, xw);
         o.def[P_XSTAGE] = pick(o, P_XSTAGE, xw);
         o.def[P_YINV6] = pick(o, P_YINV6, yw);
         o.def[P_YFWD3] = pick(o, P_YFWD3, yw);
-        o.def[P_ZCROSS] = pick(o, P_ZCROSS, 4);
+        o.def[P_ZCROSS] = pick(o, P_ZCROSS, std::max(4, wave));
         o.xinv3 = &xinv3;
         o.yinv3 = &yinv3;
         o.yfwd3s = &yfwd3s;

@@ -6,12 +6,12 @@
 // dns_common.hpp:
 //   1. k_xinv      u_hat -> 6 fields: inverse x FFT of u_hat and of
 //                  omega_hat = i k x u_hat formed on the fly
-//   2. k_yline     inverse y FFT of the 6 fields (in place)
-//      k_yline_nyq same for the kz = N/2 plane
+//   2. k_yline     inverse y FFT of the 6 fields (in place; the last
+//                  workgroups take the kz = N/2 plane)
 //   3. k_zcross    per (x, y) line: 6 inverse real z FFTs, u x omega in
 //                  registers, 3 forward real z FFTs; physical fields never
 //                  leave the chip
-//   4. k_yline     forward y FFT of the 3 fields (+ k_yline_nyq)
+//   4. k_yline     forward y FFT of the 3 fields
 //   5. k_xrhs      forward x FFT, dealias mask, pressure projection,
 //                  viscous term and the RK4 stage update (+ diagnostics)
 #pragma once
@@ -182,55 +182,57 @@ void k_xplain(const cx<R>* __restrict__ S, cx<R>* __restrict__ D, const cx<R>* _
 }
 
 // ---------------------------------------------------------------------------
-// Pass 2/4: y transform (direction DIR) of NF fields, in place, main block.
-// Workgroup = TY consecutive iz of one ix; rows iy have stride N/2.
+// Pass 2/4: y transform (direction DIR) of NF fields, in place.
+// Main block: a workgroup takes T consecutive iz of one ix; rows iy have
+// stride N/2, thread (t, g) holds elements g + m G of line t.
+// Nyquist plane (kz = N/2, the last N/T workgroups): a workgroup takes T
+// consecutive ix, whose lines are contiguous; thread (l, g) holds elements
+// g + m G of line l, so consecutive threads read consecutive elements.
 // ---------------------------------------------------------------------------
-template <typename R, int N, int T, int DIR, int NF>
-__global__ __launch_bounds__(N / 8 * T)
-void k_yline(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
-    W += blockIdx.y * wst;
+template <typename R, int N, int T, int DIR, int NF, bool NYQ>
+__device__ __forceinline__ void yline_tile(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, cx<R>* lds,
+                                           int tile) {
     constexpr int E = 8, G = N / E;
     constexpr size_t FS = field_size(N);
-    constexpr int ZT = (N / 2) / T;          // tiles per ix
-    __shared__ cx<R> lds[T * N];
-    const int t = threadIdx.x % T, g = threadIdx.x / T;
-    const int ix = blockIdx.x / ZT;
-    const int iz = (blockIdx.x % ZT) * T + t;
-    const unsigned base = (unsigned)ix * (N * (N / 2)) + iz;
-    constexpr unsigned rs = N / 2;
+    constexpr int ZT = (N / 2) / T;          // main tiles per ix
+    constexpr unsigned rs = NYQ ? 1u : (unsigned)(N / 2);
+    constexpr int ps = NYQ ? 1 : T;
+    int g, lo;
+    unsigned base;
+    if constexpr (NYQ) {
+        g = threadIdx.x % G;
+        const int l = threadIdx.x / G;
+        base = (unsigned)main_size(N) + (unsigned)(tile * T + l) * N;
+        lo = l * N;
+    } else {
+        const int t = threadIdx.x % T;
+        g = threadIdx.x / T;
+        base = (unsigned)(tile / ZT) * (N * (N / 2)) + (unsigned)((tile % ZT) * T + t);
+        lo = t;
+    }
 #pragma unroll 1
     for (int f = 0; f < NF; ++f) {
         cx<R>* F = W + f * FS;
         cx<R> a[E];
 #pragma unroll
         for (int m = 0; m < E; ++m) a[m] = F[base + (unsigned)(g + m * G) * rs];
-        fft_line<R, N, E, DIR>(a, lds + t, T, tw, g);
+        fft_line<R, N, E, DIR>(a, lds + lo, ps, tw, g);
 #pragma unroll
         for (int m = 0; m < E; ++m) F[base + (unsigned)(g + m * G) * rs] = a[m];
     }
 }
 
-// y transform of the Nyquist plane (kz = N/2): line ix is contiguous.
-template <typename R, int N, int L, int DIR, int NF>
-__global__ __launch_bounds__(N / 8 * L)
-void k_yline_nyq(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
+template <typename R, int N, int T> constexpr int y_main_tiles() { return N * ((N / 2) / T); }
+template <typename R, int N, int T> constexpr int y_tiles() { return y_main_tiles<R, N, T>() + N / T; }
+
+template <typename R, int N, int T, int DIR, int NF>
+__global__ __launch_bounds__(N / 8 * T)
+void k_yline(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
     W += blockIdx.y * wst;
-    constexpr int E = 8, G = N / E;
-    constexpr size_t FS = field_size(N);
-    constexpr int LP = padded_line<N>(true);
-    __shared__ cx<R> lds[L * LP];
-    const int g = threadIdx.x % G, l = threadIdx.x / G;
-    const int ix = blockIdx.x * L + l;
-    const size_t base = main_size(N) + (size_t)ix * N;
-#pragma unroll 1
-    for (int f = 0; f < NF; ++f) {
-        cx<R> a[E];
-#pragma unroll
-        for (int m = 0; m < E; ++m) a[m] = W[f * FS + base + g + m * G];
-        fft_line<R, N, E, DIR, false, true>(a, lds + l * LP, 1, tw, g);
-#pragma unroll
-        for (int m = 0; m < E; ++m) W[f * FS + base + g + m * G] = a[m];
-    }
+    __shared__ cx<R> lds[T * N];
+    const int b = blockIdx.x;
+    if (b < y_main_tiles<R, N, T>()) yline_tile<R, N, T, DIR, NF, false>(W, tw, lds, b);
+    else yline_tile<R, N, T, DIR, NF, true>(W, tw, lds, b - y_main_tiles<R, N, T>());
 }
 
 // Load element k (0 <= k < N) of the Hermitian extension of a half-spectrum

@@ -205,7 +205,7 @@ def test_nonfinite_energy_reported():
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("N", [16, 64])
+@pytest.mark.parametrize("N", [8, 16, 32, 64])
 def test_every_plan_variant_is_bitwise_identical(N, dtype):
     """Tile-shape variants change only how lines share a workgroup, never the
     arithmetic: every variant of every pass gives identical bits."""
