@@ -15,7 +15,12 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libdns.so")
-SOURCES = ["dns_api.hip", "dns_f64.hip", "dns_f32.hip"]
+# (object name, source, extra defines): the C ABI, the size dispatch, and the
+# kernels of each (precision, N) pair compiled from dns_inst.hip
+SIZES = (8, 16, 32, 64, 128, 256, 512, 1024)
+UNITS = [("dns_api", "dns_api.hip", []), ("dns_tables", "dns_tables.hip", [])] + [
+    (f"dns_inst_{tag}_{n}", "dns_inst.hip", [f"-DDNS_INST_REAL={real}", f"-DDNS_INST_N={n}"])
+    for n in reversed(SIZES) for tag, real in (("f64", "double"), ("f32", "float"))]
 ARCH = "gfx950"
 
 
@@ -41,19 +46,24 @@ def common_flags(debug=False):
     ]
 
 
-def compile_one(src, debug):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + common_flags(debug) + ["-c", os.path.join(CSRC, src), "-o", obj]
+def compile_one(unit, debug):
+    name, src, defines = unit
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [hipcc()] + common_flags(debug) + defines + ["-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError(f"compiling {src} failed:\n{res.stderr[-6000:]}")
+        raise RuntimeError(f"compiling {name} ({src}) failed:\n{res.stderr[-6000:]}")
     return obj
 
 
-def build(jobs=3, debug=False, verbose=True):
+def default_jobs():
+    return max(1, min(8, os.cpu_count() or 1))
+
+
+def build(jobs=None, debug=False, verbose=True):
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: compile_one(s, debug), SOURCES))
+    with cf.ThreadPoolExecutor(max_workers=jobs or default_jobs()) as ex:
+        objs = list(ex.map(lambda u: compile_one(u, debug), UNITS))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + [
         "-Wl,-rpath,/opt/rocm/lib"]
@@ -68,7 +78,7 @@ def build(jobs=3, debug=False, verbose=True):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--jobs", type=int, default=3)
+    ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--debug", action="store_true")
     a = ap.parse_args(argv)
     build(a.jobs, a.debug)

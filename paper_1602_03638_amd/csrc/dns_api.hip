@@ -333,7 +333,7 @@ int create_ctx(int N, double nu, double dt, int dtype, const dns_opts& o, hipStr
     c->user = user;
     c->ops = dtype == DNS_FP64 ? dns::ops_f64(N) : dns::ops_f32(N);
     const size_t rs = c->ops->real_size;
-    c->fs = dns::field_size(N);
+    c->fs = c->ops->fs;
     c->cbytes = 2 * rs;
     c->fbytes = c->fs * c->cbytes;
 
@@ -519,8 +519,9 @@ void dns_default_opts(dns_opts* o) {
 
 size_t dns_state_bytes(int N, int dtype) {
     if (!valid_n(N) || (dtype != DNS_FP64 && dtype != DNS_FP32)) return 0;
-    const size_t rs = dtype == DNS_FP64 ? 8 : 4;
-    return 15 * dns::field_size(N) * 2 * rs + (size_t)dns::tw_size(N) * 2 * rs;
+    const dns::Ops* o = dtype == DNS_FP64 ? dns::ops_f64(N) : dns::ops_f32(N);
+    const size_t cb = 2 * o->real_size;
+    return 15 * o->fs * cb + (size_t)o->tw_count * cb;
 }
 
 int dns_create(int N, double nu, double dt, int dtype, dns_t** out) {

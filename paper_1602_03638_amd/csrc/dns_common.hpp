@@ -40,41 +40,48 @@ constexpr int tw_offset(int N, int s) {
 constexpr int tw_size(int N) { return tw_offset(N, num_stages(N)); }
 
 // ---------------------------------------------------------------------------
-// Internal layout of one half-spectrum field of an N^3 grid:
-//   main block [ix][iy][iz] for iz in [0, N/2)  (pitch N/2, power-of-two rows)
-//   Nyquist plane [ix][iy] for iz = N/2, stored after the main block.
+// Internal layout of one half-spectrum field of an N^3 grid (complex values
+// of type cx<R>):
+//   main block, iz in [0, N/2):  element (ix, iy, iz) at ix * XP + iy * ZP + iz
+//   Nyquist plane, iz = N/2:     element (ix, iy) at MAIN + ix * N + iy
+// Every iz row and every ix plane ends in a 128-byte gap (PAD values that no
+// kernel reads or writes): with power-of-two pitches the rows of an x or y
+// tile would all fall on the same few HBM channels; a 128-byte skew spreads
+// them (measured on MI355X: 4.3 -> 5.0 TB/s for x tiles, 4.6 -> 5.1 TB/s for
+// y tiles, contiguous z lines within 4%).
 // The same layout holds partially transformed data: after the inverse x pass
 // ix is the physical x index, after the inverse y pass iy is physical y.
 // ---------------------------------------------------------------------------
-constexpr size_t main_size(int N) { return (size_t)N * N * (N / 2); }
-constexpr size_t field_size(int N) { return main_size(N) + (size_t)N * N; }
-
-// ---------------------------------------------------------------------------
-// Launch shapes.  Every FFT line of length N is held by G = N/E threads, E
-// elements each (thread g holds elements g, g+G, ..., g+(E-1)G).
-//   TX: lines per workgroup of the x pass (consecutive columns, stride-N^2/2
-//       rows), TY: same for the y pass (consecutive iz of one ix),
-//   LZ: contiguous lines per workgroup (z pass, Nyquist-plane y lines).
-// Column groups span 64 bytes (4 complex doubles / 8 complex floats) and
-// are widened so that a workgroup is at least one 64-wide wavefront.
-// ---------------------------------------------------------------------------
-template <typename R, int N> struct Cfg {
-    static constexpr int E = 8;
-    static constexpr int G = N / E;
-    static constexpr int TB = sizeof(R) == 8 ? 4 : 8;
-    static constexpr int TW = (64 / G > TB) ? 64 / G : TB;
-    static constexpr int TX = TW < N ? TW : N;
-    static constexpr int TY = TW < N / 2 ? TW : N / 2;
-    static constexpr int LZ0 = (256 / G) > 1 ? 256 / G : 1;
-    static constexpr int LZ = LZ0 < N * N ? LZ0 : N * N;
-    static constexpr int LY = LZ0 < N ? LZ0 : N;
-    static constexpr int XTHREADS = G * TX;
-    static constexpr int YTHREADS = G * TY;
-    static constexpr int ZTHREADS = G * LZ;
-    static constexpr int NYTHREADS = G * LY;
-    static constexpr int X_TILES = (N * (N / 2)) / TX + N / TX;
-    static constexpr int Y_TILES = N * ((N / 2) / TY);
-    static_assert(N >= 8 && (N & (N - 1)) == 0, "N must be a power of two >= 8");
+template <typename R, int N> struct Lay {
+    static constexpr unsigned PAD = 128 / (2 * sizeof(R));
+    static constexpr unsigned ZP = N / 2 + PAD;            // pitch of the iz rows
+    static constexpr unsigned XP = N * ZP + PAD;           // pitch of the ix planes
+    static constexpr size_t MAIN = (size_t)N * XP;         // start of the Nyquist plane
+    static constexpr size_t FS = MAIN + (size_t)N * N;     // complex values per field
+    // logical modes per field (main block, then Nyquist plane)
+    static constexpr size_t MODES = (size_t)N * N * (N / 2) + (size_t)N * N;
+    __host__ __device__ static constexpr size_t at(int ix, int iy, int iz) {
+        return (size_t)ix * XP + (size_t)iy * ZP + (size_t)iz;
+    }
+    // start of the iz row of z line `line` = ix * N + iy
+    __host__ __device__ static constexpr size_t row(size_t line) { return (line / N) * XP + (line % N) * ZP; }
+    // indices and address of logical mode j (main block in (ix, iy, iz)
+    // order, then the Nyquist plane in (ix, iy) order)
+    __host__ __device__ static void mode(size_t j, int& ix, int& iy, int& iz, size_t& addr) {
+        constexpr size_t MM = (size_t)N * N * (N / 2);
+        if (j < MM) {
+            iz = (int)(j % (N / 2));
+            iy = (int)((j / (N / 2)) % N);
+            ix = (int)(j / ((size_t)N * (N / 2)));
+            addr = at(ix, iy, iz);
+        } else {
+            const size_t r = j - MM;
+            iz = N / 2;
+            iy = (int)(r % N);
+            ix = (int)(r / N);
+            addr = MAIN + r;
+        }
+    }
 };
 
 // Workgroups of the standalone diagnostic reduction (fixed, so the summation

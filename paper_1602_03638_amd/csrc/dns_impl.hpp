@@ -136,12 +136,12 @@ template <typename R, int N> struct Impl {
                            p0, p1, p2);
     }
     static void ic_random(void* U, unsigned long long seed, double k0, int mask_lim, hipStream_t s) {
-        const size_t FS = field_size(N);
-        hipLaunchKernelGGL((k_ic_random<R, N>), dim3((unsigned)((FS + 255) / 256)), dim3(256), 0, s, (C*)U, seed, k0,
+        const size_t M = Lay<R, N>::MODES;
+        hipLaunchKernelGGL((k_ic_random<R, N>), dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, (C*)U, seed, k0,
                            mask_lim);
     }
     static void scale(void* U, double factor, hipStream_t s) {
-        const size_t T = 3 * field_size(N);
+        const size_t T = 3 * Lay<R, N>::FS;
         hipLaunchKernelGGL((k_scale<R, N>), dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, (C*)U, factor);
     }
 
@@ -193,6 +193,7 @@ template <typename R, int N> struct Impl {
         Ops o{};
         o.N = N;
         o.real_size = sizeof(R);
+        o.fs = Lay<R, N>::FS;
         o.tw_count = tw_size(N) > 0 ? tw_size(N) : 1;
         add_x<4>(o); add_x<8>(o); add_x<16>(o); add_x<32>(o);
         add_y<4>(o); add_y<8>(o); add_y<16>(o); add_y<32>(o);
@@ -228,18 +229,10 @@ template <typename R, int N> struct Impl {
     }
 };
 
-template <typename R> const Ops* ops_for(int N) {
-    switch (N) {
-        case 8: return Impl<R, 8>::table();
-        case 16: return Impl<R, 16>::table();
-        case 32: return Impl<R, 32>::table();
-        case 64: return Impl<R, 64>::table();
-        case 128: return Impl<R, 128>::table();
-        case 256: return Impl<R, 256>::table();
-        case 512: return Impl<R, 512>::table();
-        case 1024: return Impl<R, 1024>::table();
-        default: return nullptr;
-    }
-}
+// The table of one (R, N) pair, compiled in a translation unit of its own
+// (dns_inst.hip built once per pair) so that the pairs build in parallel.
+#if defined(DNS_INST_REAL) && defined(DNS_INST_N)
+template <> const Ops* ops_table<DNS_INST_REAL, DNS_INST_N>() { return Impl<DNS_INST_REAL, DNS_INST_N>::table(); }
+#endif
 
 }  // namespace dns

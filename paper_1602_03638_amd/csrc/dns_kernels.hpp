@@ -28,19 +28,21 @@ __device__ __forceinline__ int kfreq(int i, int n) { return i < n / 2 ? i : i - 
 // both), so the kernels branch once on the block and the row stride is a
 // compile-time constant, which lets the compiler see that different rows
 // never alias.
-template <int N, bool NYQ> struct XCol {
-    static constexpr unsigned RS = NYQ ? (unsigned)N : (unsigned)(N * (N / 2));   // offset between rows
+template <typename R, int N, bool NYQ> struct XCol {
+    using L = Lay<R, N>;
+    static constexpr unsigned RS = NYQ ? (unsigned)N : L::XP;   // offset between rows
     unsigned base;   // offset of row 0 in a field
     int ky, kz;
     __device__ __forceinline__ explicit XCol(int c) {
         constexpr int HC = N * (N / 2);
         if constexpr (!NYQ) {
-            base = (unsigned)c;
-            ky = kfreq(c / (N / 2), N);
+            const int iy = c / (N / 2);
             kz = c % (N / 2);
+            ky = kfreq(iy, N);
+            base = (unsigned)iy * L::ZP + (unsigned)kz;
         } else {
             const int iy = c - HC;
-            base = (unsigned)main_size(N) + (unsigned)iy;
+            base = (unsigned)L::MAIN + (unsigned)iy;
             ky = kfreq(iy, N);
             kz = N / 2;
         }
@@ -54,22 +56,28 @@ template <int N, bool NYQ> struct XCol {
 // shared by every field and row, so that a thread holds one address
 // register instead of one per element.  Relative to the block start the
 // offset stays below 2^32 bytes for every supported N and precision.
-template <typename C, int N, int G, bool NYQ>
+template <typename R, int N, bool NYQ>
 struct XAddr {
-    static constexpr size_t BLOCK = NYQ ? main_size(N) : 0;   // element offset of the block
-    unsigned tb;                                              // byte offset of (column, row g)
-    __device__ __forceinline__ XAddr(const XCol<N, NYQ>& col, int g)
-        : tb(((unsigned)(col.base - BLOCK) + (unsigned)g * XCol<N, NYQ>::RS) * (unsigned)sizeof(C)) {}
+    using C = cx<R>;
+    static constexpr int G = N / 8;
+    static constexpr unsigned RS = XCol<R, N, NYQ>::RS;
+    static constexpr size_t BLOCK = NYQ ? Lay<R, N>::MAIN : 0;   // element offset of the block
+    unsigned tb;                                                  // byte offset of (column, row g)
+    __device__ __forceinline__ XAddr(const XCol<R, N, NYQ>& col, int g)
+        : tb(((unsigned)(col.base - BLOCK) + (unsigned)g * RS) * (unsigned)sizeof(C)) {}
     __device__ __forceinline__ C& operator()(C* F, int m) const {
-        return *reinterpret_cast<C*>(reinterpret_cast<char*>(F + BLOCK + (size_t)m * G * XCol<N, NYQ>::RS) + tb);
+        return *reinterpret_cast<C*>(reinterpret_cast<char*>(F + BLOCK + (size_t)m * G * RS) + tb);
     }
     __device__ __forceinline__ const C& operator()(const C* F, int m) const {
-        return *reinterpret_cast<const C*>(reinterpret_cast<const char*>(F + BLOCK + (size_t)m * G * XCol<N, NYQ>::RS) +
-                                           tb);
+        return *reinterpret_cast<const C*>(reinterpret_cast<const char*>(F + BLOCK + (size_t)m * G * RS) + tb);
     }
 };
 
-static_assert((size_t)(1024 / 8) * 1024 * 512 * 16 < (size_t(1) << 32), "x-tile byte offsets must fit 32 bits");
+static_assert((size_t)Lay<double, 1024>::ZP * 1024 + (size_t)(1024 / 8) * Lay<double, 1024>::XP * 16 <
+                  (size_t(1) << 32),
+              "x-tile byte offsets must fit 32 bits");
+static_assert(Lay<double, 1024>::FS < (size_t(1) << 32) && Lay<float, 1024>::FS < (size_t(1) << 32),
+              "element offsets within a field must fit 32 bits");
 
 // Number of x-pass workgroups of width T over the main block.
 template <int N, int T> constexpr int x_main_tiles() { return (N * (N / 2)) / T; }
@@ -90,12 +98,12 @@ template <typename R, int N, int T, bool NYQ>
 __device__ __forceinline__ void xinv_curl_tile(const cx<R>* __restrict__ U, cx<R>* __restrict__ W,
                                                cx<R>* lds, const cx<R>* twl) {
     constexpr int E = 8, G = N / E;
-    constexpr size_t FS = field_size(N);
+    constexpr size_t FS = Lay<R, N>::FS;
     const int t = threadIdx.x % T, g = threadIdx.x / T;
-    const XCol<N, NYQ> col(blockIdx.x * T + t);
+    const XCol<R, N, NYQ> col(blockIdx.x * T + t);
     const R ky = (R)col.ky, kz = (R)col.kz;
     cx<R>* lt = lds + t;
-    const XAddr<cx<R>, N, G, NYQ> A(col, g);
+    const XAddr<R, N, NYQ> A(col, g);
 
     // Loads are issued as early as the register budget allows so that their
     // latency overlaps the transforms (a barrier inside a transform keeps
@@ -157,9 +165,9 @@ template <typename R, int N, int T, int DIR, int NF, bool NYQ>
 __device__ __forceinline__ void xplain_tile(const cx<R>* __restrict__ S, cx<R>* __restrict__ D,
                                             const cx<R>* __restrict__ tw, cx<R>* lds) {
     constexpr int E = 8, G = N / E;
-    constexpr size_t FS = field_size(N);
+    constexpr size_t FS = Lay<R, N>::FS;
     const int t = threadIdx.x % T, g = threadIdx.x / T;
-    const XCol<N, NYQ> col(blockIdx.x * T + t);
+    const XCol<R, N, NYQ> col(blockIdx.x * T + t);
 #pragma unroll 1
     for (int f = 0; f < NF; ++f) {
         const cx<R>* src = S + f * FS;
@@ -193,21 +201,22 @@ template <typename R, int N, int T, int DIR, int NF, bool NYQ>
 __device__ __forceinline__ void yline_tile(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, cx<R>* lds,
                                            int tile) {
     constexpr int E = 8, G = N / E;
-    constexpr size_t FS = field_size(N);
+    constexpr size_t FS = Lay<R, N>::FS;
     constexpr int ZT = (N / 2) / T;          // main tiles per ix
-    constexpr unsigned rs = NYQ ? 1u : (unsigned)(N / 2);
+    using L = Lay<R, N>;
+    constexpr unsigned rs = NYQ ? 1u : L::ZP;
     constexpr int ps = NYQ ? 1 : T;
     int g, lo;
     unsigned base;
     if constexpr (NYQ) {
         g = threadIdx.x % G;
         const int l = threadIdx.x / G;
-        base = (unsigned)main_size(N) + (unsigned)(tile * T + l) * N;
+        base = (unsigned)L::MAIN + (unsigned)(tile * T + l) * N;
         lo = l * N;
     } else {
         const int t = threadIdx.x % T;
         g = threadIdx.x / T;
-        base = (unsigned)(tile / ZT) * (N * (N / 2)) + (unsigned)((tile % ZT) * T + t);
+        base = (unsigned)(tile / ZT) * L::XP + (unsigned)((tile % ZT) * T + t);
         lo = t;
     }
 #pragma unroll 1
@@ -240,16 +249,17 @@ void k_yline(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
 // X_0 and X_{N/2} are dropped (inverse real transform semantics).
 template <typename R, int N>
 __device__ __forceinline__ cx<R> zline_load(const cx<R>* __restrict__ F, size_t line, int k) {
+    using L = Lay<R, N>;
     if (k < N / 2) {
-        cx<R> a = F[line * (N / 2) + k];
+        cx<R> a = F[L::row(line) + k];
         if (k == 0) a.y = R(0);
         return a;
     } else if (k == N / 2) {
-        cx<R> a = F[main_size(N) + line];
+        cx<R> a = F[L::MAIN + line];
         a.y = R(0);
         return a;
     } else {
-        return cconj<R>(F[line * (N / 2) + (N - k)]);
+        return cconj<R>(F[L::row(line) + (N - k)]);
     }
 }
 
@@ -286,12 +296,14 @@ __global__ __launch_bounds__(N / 8 * L)
 void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale, size_t wst) {
     W += blockIdx.y * wst;
     constexpr int E = 8, G = N / E;
-    constexpr size_t FS = field_size(N);
+    constexpr size_t FS = Lay<R, N>::FS;
     constexpr int LP = padded_line<N>(true);
     __shared__ cx<R> lds[L * LP];
     __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
     const int g = threadIdx.x % G, l = threadIdx.x / G;
     const size_t line = (size_t)blockIdx.x * L + l;
+    const size_t zr = Lay<R, N>::row(line);   // start of the line's iz row
+    constexpr size_t NQ = Lay<R, N>::MAIN;     // start of the Nyquist plane
     cx<R>* my = lds + l * LP;
 
     // Each stored coefficient is loaded once (lower half k < N/2 plus the
@@ -305,12 +317,12 @@ void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale, size
         const cx<R>* FY = W + (2 * p + 1) * FS;
 #pragma unroll
         for (int m = 0; m < E / 2; ++m) {
-            xl[p][m] = FX[line * (N / 2) + g + m * G];
-            yl[p][m] = FY[line * (N / 2) + g + m * G];
+            xl[p][m] = FX[zr + g + m * G];
+            yl[p][m] = FY[zr + g + m * G];
         }
         if (g == 0) {
-            xn[p] = FX[main_size(N) + line];
-            yn[p] = FY[main_size(N) + line];
+            xn[p] = FX[NQ + line];
+            yn[p] = FY[NQ + line];
         }
     }
     load_twiddles<R, N>(twl, tw);
@@ -348,8 +360,8 @@ void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale, size
     fft_line<R, N, E, -1, true, true>(P, my, 1, twl, g);
     // c2: Q_k is its half spectrum directly
 #pragma unroll
-    for (int m = 0; m < E / 2; ++m) W[2 * FS + line * (N / 2) + g + m * G] = Q[m];
-    if (g == 0) W[2 * FS + main_size(N) + line] = Q[E / 2];
+    for (int m = 0; m < E / 2; ++m) W[2 * FS + zr + g + m * G] = Q[m];
+    if (g == 0) W[2 * FS + NQ + line] = Q[E / 2];
     // c0, c1: unpack P through LDS (needs P_{N-k})
 #pragma unroll
     for (int m = 0; m < E; ++m) my[g + m * G] = P[m];
@@ -359,14 +371,14 @@ void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale, size
         const int k = g + m * G;
         cx<R> A, B;
         zsplit<R>(my[k], my[(N - k) & (N - 1)], A, B);
-        W[0 * FS + line * (N / 2) + k] = A;
-        W[1 * FS + line * (N / 2) + k] = B;
+        W[0 * FS + zr + k] = A;
+        W[1 * FS + zr + k] = B;
     }
     if (g == 0) {
         cx<R> A, B;
         zsplit<R>(my[N / 2], my[N / 2], A, B);
-        W[0 * FS + main_size(N) + line] = A;
-        W[1 * FS + main_size(N) + line] = B;
+        W[0 * FS + NQ + line] = A;
+        W[1 * FS + NQ + line] = B;
     }
 }
 
@@ -376,12 +388,14 @@ template <typename R, int N, int L>
 __global__ __launch_bounds__(N / 8 * L)
 void k_zr2c(const R* __restrict__ u, cx<R>* __restrict__ W, const cx<R>* __restrict__ tw) {
     constexpr int E = 8, G = N / E;
-    constexpr size_t FS = field_size(N);
+    constexpr size_t FS = Lay<R, N>::FS;
     constexpr size_t PS = (size_t)N * N * N;
     constexpr int LP = padded_line<N>(true);
     __shared__ cx<R> lds[L * LP];
     const int g = threadIdx.x % G, l = threadIdx.x / G;
     const size_t line = (size_t)blockIdx.x * L + l;
+    const size_t zr = Lay<R, N>::row(line);   // start of the line's iz row
+    constexpr size_t NQ = Lay<R, N>::MAIN;     // start of the Nyquist plane
     cx<R>* my = lds + l * LP;
     cx<R> P[E], Q[E];
 #pragma unroll
@@ -393,8 +407,8 @@ void k_zr2c(const R* __restrict__ u, cx<R>* __restrict__ W, const cx<R>* __restr
     fft_line<R, N, E, -1, false, true>(Q, my, 1, tw, g);
     fft_line<R, N, E, -1, false, true>(P, my, 1, tw, g);
 #pragma unroll
-    for (int m = 0; m < E / 2; ++m) W[2 * FS + line * (N / 2) + g + m * G] = Q[m];
-    if (g == 0) W[2 * FS + main_size(N) + line] = Q[E / 2];
+    for (int m = 0; m < E / 2; ++m) W[2 * FS + zr + g + m * G] = Q[m];
+    if (g == 0) W[2 * FS + NQ + line] = Q[E / 2];
 #pragma unroll
     for (int m = 0; m < E; ++m) my[g + m * G] = P[m];
     __syncthreads();
@@ -403,14 +417,14 @@ void k_zr2c(const R* __restrict__ u, cx<R>* __restrict__ W, const cx<R>* __restr
         const int k = g + m * G;
         cx<R> A, B;
         zsplit<R>(my[k], my[(N - k) & (N - 1)], A, B);
-        W[0 * FS + line * (N / 2) + k] = A;
-        W[1 * FS + line * (N / 2) + k] = B;
+        W[0 * FS + zr + k] = A;
+        W[1 * FS + zr + k] = B;
     }
     if (g == 0) {
         cx<R> A, B;
         zsplit<R>(my[N / 2], my[N / 2], A, B);
-        W[0 * FS + main_size(N) + line] = A;
-        W[1 * FS + main_size(N) + line] = B;
+        W[0 * FS + NQ + line] = A;
+        W[1 * FS + NQ + line] = B;
     }
 }
 
@@ -420,7 +434,7 @@ template <typename R, int N, int L>
 __global__ __launch_bounds__(N / 8 * L)
 void k_zc2r(const cx<R>* __restrict__ W, R* __restrict__ u, const cx<R>* __restrict__ tw, R scale) {
     constexpr int E = 8, G = N / E;
-    constexpr size_t FS = field_size(N);
+    constexpr size_t FS = Lay<R, N>::FS;
     constexpr size_t PS = (size_t)N * N * N;
     constexpr int LP = padded_line<N>(true);
     __shared__ cx<R> lds[L * LP];
@@ -469,17 +483,17 @@ void k_zc2r(const cx<R>* __restrict__ W, R* __restrict__ u, const cx<R>* __restr
 // being batched.  Fewer registers than the batched form, for 1024-thread
 // shapes whose register budget is 128 per thread.
 template <typename R, int N, int E, int STAGE, bool NYQ>
-__device__ __forceinline__ void rk_apply_elementwise(cx<R> (&nh)[3][E], const XCol<N, NYQ>& col, int g,
+__device__ __forceinline__ void rk_apply_elementwise(cx<R> (&nh)[3][E], const XCol<R, N, NYQ>& col, int g,
                                                      cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
                                                      cx<R>* __restrict__ Us, const StageArgs& sa,
                                                      double& e_acc, double& w_acc) {
     constexpr int G = N / E;
-    constexpr size_t FS = field_size(N);
+    constexpr size_t FS = Lay<R, N>::FS;
     const int ky = col.ky, kz = col.kz;
     const int lim = sa.mask_lim;
     const bool keep_yz = (3 * abs(ky) < lim) && (3 * abs(kz) < lim);
     const R nu = (R)sa.nu, ca = (R)sa.ca, cb = (R)sa.cb;
-    const XAddr<cx<R>, N, G, NYQ> A(col, g);
+    const XAddr<R, N, NYQ> A(col, g);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int kx = kfreq(g + m * G, N);
@@ -544,17 +558,17 @@ __device__ __forceinline__ void rk_apply_elementwise(cx<R> (&nh)[3][E], const XC
 }
 
 template <typename R, int N, int E, int STAGE, bool NYQ>
-__device__ __forceinline__ void rk_apply_batched(cx<R> (&nh)[3][E], const XCol<N, NYQ>& col, int g,
+__device__ __forceinline__ void rk_apply_batched(cx<R> (&nh)[3][E], const XCol<R, N, NYQ>& col, int g,
                                                cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
                                                cx<R>* __restrict__ Us, const StageArgs& sa, double& e_acc,
                                                double& w_acc) {
     constexpr int G = N / E;
-    constexpr size_t FS = field_size(N);
+    constexpr size_t FS = Lay<R, N>::FS;
     const int ky = col.ky, kz = col.kz;
     const int lim = sa.mask_lim;
     const bool keep_yz = (3 * abs(ky) < lim) && (3 * abs(kz) < lim);
     const R nu = (R)sa.nu, ca = (R)sa.ca, cb = (R)sa.cb;
-    const XAddr<cx<R>, N, G, NYQ> A(col, g);
+    const XAddr<R, N, NYQ> A(col, g);
 
     // dealias and project: N_hat -= k (k . N_hat) / |k|^2
 #pragma unroll
@@ -665,7 +679,7 @@ __device__ __forceinline__ void rk_apply_batched(cx<R> (&nh)[3][E], const XCol<N
 // batched one keeps more loads in flight, the per-element one fits the
 // 128-register budget of 1024-thread workgroups.
 template <typename R, int N, int E, int STAGE, bool NYQ, int NT>
-__device__ __forceinline__ void rk_apply_stage(cx<R> (&nh)[3][E], const XCol<N, NYQ>& col, int g,
+__device__ __forceinline__ void rk_apply_stage(cx<R> (&nh)[3][E], const XCol<R, N, NYQ>& col, int g,
                                                cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
                                                cx<R>* __restrict__ Us, const StageArgs& sa, double& e_acc,
                                                double& w_acc) {
@@ -700,14 +714,14 @@ __device__ __forceinline__ void xrhs_tile(const cx<R>* __restrict__ W, cx<R>* __
                                           double (&red)[2][N / 8 * T]) {
     constexpr int E = 8, G = N / E;
     constexpr int NT = G * T;
-    constexpr size_t FS = field_size(N);
+    constexpr size_t FS = Lay<R, N>::FS;
     const int t = threadIdx.x % T, g = threadIdx.x / T;
-    const XCol<N, NYQ> col(blockIdx.x * T + t);
+    const XCol<R, N, NYQ> col(blockIdx.x * T + t);
     cx<R> nh[3][E];
 #pragma unroll
     for (int f = 0; f < 3; ++f)
 #pragma unroll
-        for (int m = 0; m < E; ++m) nh[f][m] = XAddr<cx<R>, N, G, NYQ>(col, g)(W + f * FS, m);
+        for (int m = 0; m < E; ++m) nh[f][m] = XAddr<R, N, NYQ>(col, g)(W + f * FS, m);
 #pragma unroll
     for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true>(nh[f], lds + t, T, twl, g);
     double e_acc = 0.0, w_acc = 0.0;
@@ -749,10 +763,10 @@ __device__ __forceinline__ void xstage_tile(cx<R>* __restrict__ W, cx<R>* __rest
                                             const cx<R>* twl, double (&red)[2][N / 8 * T]) {
     constexpr int E = 8, G = N / E;
     constexpr int NT = G * T;
-    constexpr size_t FS = field_size(N);
+    constexpr size_t FS = Lay<R, N>::FS;
     const int t = threadIdx.x % T, g = threadIdx.x / T;
-    const XCol<N, NYQ> col(blockIdx.x * T + t);
-    const XAddr<cx<R>, N, G, NYQ> A(col, g);
+    const XCol<R, N, NYQ> col(blockIdx.x * T + t);
+    const XAddr<R, N, NYQ> A(col, g);
 
     cx<R> u[3][E];
 #pragma unroll
@@ -822,12 +836,12 @@ void k_layout(const cx<R>* __restrict__ src, cx<R>* __restrict__ dst, size_t tot
     const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= total) return;
     constexpr size_t M = N / 2 + 1;
-    constexpr size_t FS = field_size(N);
+    constexpr size_t FS = Lay<R, N>::FS;
     const size_t c = i / ((size_t)N * N * M);
     const size_t r = i - c * (size_t)N * N * M;
     const size_t iz = r % M;
     const size_t ixy = r / M;            // ix * N + iy
-    const size_t in = c * FS + (iz < N / 2 ? ixy * (N / 2) + iz : main_size(N) + ixy);
+    const size_t in = c * FS + (iz < N / 2 ? Lay<R, N>::row(ixy) + iz : Lay<R, N>::MAIN + ixy);
     if (TO_INTERNAL) dst[in] = src[i];
     else dst[i] = src[in];
 }
@@ -841,21 +855,13 @@ void k_layout(const cx<R>* __restrict__ src, cx<R>* __restrict__ dst, size_t tot
 template <typename R, int N>
 __global__ __launch_bounds__(256)
 void k_diag_partial(const cx<R>* __restrict__ U, double* __restrict__ part) {
-    constexpr size_t FS = field_size(N);
+    constexpr size_t FS = Lay<R, N>::FS;
     __shared__ double red[2 * 4];
     double e_acc = 0.0, w_acc = 0.0;
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < FS; i += (size_t)DIAG_BLOCKS * 256) {
+    for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < Lay<R, N>::MODES; j += (size_t)DIAG_BLOCKS * 256) {
         int ix, iy, iz;
-        if (i < main_size(N)) {
-            iz = (int)(i % (N / 2));
-            iy = (int)((i / (N / 2)) % N);
-            ix = (int)(i / ((size_t)N * (N / 2)));
-        } else {
-            const size_t r = i - main_size(N);
-            iz = N / 2;
-            iy = (int)(r % N);
-            ix = (int)(r / N);
-        }
+        size_t i;
+        Lay<R, N>::mode(j, ix, iy, iz, i);
         const double kx = kfreq(ix, N), ky = kfreq(iy, N), kz = iz;
         const double wgt = (iz == 0 || iz == N / 2) ? 1.0 : 2.0;
         const cx<R> a = U[i], b = U[FS + i], c = U[2 * FS + i];
@@ -946,20 +952,12 @@ __device__ __forceinline__ double unit53(unsigned long long z) {
 template <typename R, int N>
 __global__ __launch_bounds__(256) void k_ic_random(cx<R>* __restrict__ U, unsigned long long seed, double k0,
                                                    int mask_lim) {
-    constexpr size_t FS = field_size(N);
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= FS) return;
+    constexpr size_t FS = Lay<R, N>::FS;
+    const size_t j = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= Lay<R, N>::MODES) return;
     int ix, iy, iz;
-    if (i < main_size(N)) {
-        iz = (int)(i % (N / 2));
-        iy = (int)((i / (N / 2)) % N);
-        ix = (int)(i / ((size_t)N * (N / 2)));
-    } else {
-        const size_t r = i - main_size(N);
-        iz = N / 2;
-        iy = (int)(r % N);
-        ix = (int)(r / N);
-    }
+    size_t i;
+    Lay<R, N>::mode(j, ix, iy, iz, i);
     int sx = ix, sy = iy;
     bool conj = false, real_only = false;
     if (iz == 0 || iz == N / 2) {
@@ -1009,7 +1007,7 @@ __global__ __launch_bounds__(256) void k_ic_random(cx<R>* __restrict__ U, unsign
 // Multiply the three fields at U by s (energy normalisation).
 template <typename R, int N>
 __global__ __launch_bounds__(256) void k_scale(cx<R>* __restrict__ U, double s) {
-    constexpr size_t TOT = 3 * field_size(N);
+    constexpr size_t TOT = 3 * Lay<R, N>::FS;
     const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= TOT) return;
     const cx<R> a = U[i];

@@ -25,6 +25,7 @@ using XrhsFn = void (*)(const void* W, void* U0, void* U1, void* Us, const void*
 struct Ops {
     int N;
     size_t real_size;      // bytes of one real value
+    size_t fs;             // complex values of one field in the internal layout
     int tw_count;          // complex entries of the twiddle table
     // variants of the five passes of one RK4 stage; width[p][v] is the
     // number of lines per workgroup of variant v of pass p
@@ -53,6 +54,10 @@ struct Ops {
     void (*scale)(void* U, double factor, hipStream_t s);
 };
 
+// Launch table of one (real type, N) pair; defined for N = 8, 16, ..., 1024.
+template <typename R, int N> const Ops* ops_table();
+
+// Launch table of a size N (nullptr for an unsupported N).
 const Ops* ops_f64(int N);
 const Ops* ops_f32(int N);
 

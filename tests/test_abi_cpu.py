@@ -33,10 +33,12 @@ def test_default_opts(lib):
 
 
 def test_state_bytes(lib):
-    # 15 half-spectrum fields of N*N*(N/2+1) complex values (+ a small table)
+    # 15 half-spectrum fields of N*N*(N/2+1) complex values, each iz row and
+    # ix plane padded by 128 bytes (+ a small twiddle table)
     b = dns.state_bytes(512, dns.DNS_FP64)
     field = 512 * 512 * 257 * 16
-    assert 15 * field <= b < 15 * field + 1 << 20
+    padded = (512 * (512 * (256 + 8) + 8) + 512 * 512) * 16
+    assert 15 * field < 15 * padded <= b < 15 * padded + (1 << 20)
     assert dns.state_bytes(512, dns.DNS_FP32) < b
     assert dns.state_bytes(500, dns.DNS_FP64) == 0
     assert dns.state_bytes(2048, dns.DNS_FP64) == 0
