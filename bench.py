@@ -22,14 +22,16 @@ HBM_PEAK_GBPS = 8000.0
 N_DEFAULT, NU, DT = 512, 1.0 / 1600, 1e-3
 
 # Algorithmic HBM traffic of each kernel, in half-spectrum fields
-# C = N^2 (N/2+1) complex values (read + write).  xrhs_rk4 averages the four
-# stages: N_hat reads 3C per stage plus RK4 state traffic of 48C per step.
-# xstage is xrhs_rk4 plus the 6C of inverse-x/curl fields it writes for the
-# next stage.  Unfused step: 4 * 36 C + 60 C = 204 C.  Fused step (the
-# default schedule): 4 * (12 + 9 + 6) C + 4 * 21 C = 192 C.
-FIELDS_PER_LAUNCH = {"xinv_curl": 9.0, "yinv6": 12.0, "zcross": 9.0, "yfwd3": 6.0, "xrhs_rk4": 60.0 / 4,
-                     "xstage": 60.0 / 4 + 6.0}
-FIELDS_PER_STEP = 192.0
+# C = N^2 (N/2+1) complex values (read + write).  The RK4 state moves 36C per
+# step (stage 0: read U0, write Us; stage 1: read Us, U0, write Us, U1;
+# stage 2: read Us, U0, write Us; stage 3: read Us, U1, write U0), and the
+# forward x pass reads N_hat (3C) at every stage, so xrhs_rk4 averages
+# (36 + 12) / 4 = 12C; xstage adds the 6C of inverse-x/curl fields it writes
+# for the next stage.  Fused step (the default schedule):
+# 4 * (12 + 9 + 6) C + 4 * 18 C = 180 C; unfused: 4 * (9 + 27) C + 48 C = 192 C.
+FIELDS_PER_LAUNCH = {"xinv_curl": 9.0, "yinv6": 12.0, "zcross": 9.0, "yfwd3": 6.0, "xrhs_rk4": 48.0 / 4,
+                     "xstage": 48.0 / 4 + 6.0}
+FIELDS_PER_STEP = 180.0
 
 
 def kernel_source_hash():

@@ -167,13 +167,16 @@ int leave(dns_t* c) {
     return DNS_OK;
 }
 
+// Classic RK4 (Appendix solver): stage offsets b and final weights a; the
+// stage kernels use b_s dt and a_3 dt (the other weights enter through the
+// regrouped final sum, see the stage update in dns_kernels.hpp).
 const double RK4_A[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
 const double RK4_B[3] = {0.5, 0.5, 1.0};
 
 dns::StageArgs stage_args(const dns_t* c, int stage, double* diag) {
     dns::StageArgs a;
     a.nu = c->nu;
-    a.ca = stage >= 0 ? RK4_A[stage] * c->dt : 0.0;
+    a.ca = stage == 3 ? RK4_A[3] * c->dt : 0.0;
     a.cb = (stage >= 0 && stage < 3) ? RK4_B[stage] * c->dt : 0.0;
     a.stage = stage;
     a.mask_lim = c->mask_lim;

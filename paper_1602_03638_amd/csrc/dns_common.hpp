@@ -101,7 +101,7 @@ struct Batch {
 // Per-stage coefficients of one RK4 stage of the fused x-forward kernel.
 struct StageArgs {
     double nu;       // viscosity
-    double ca;       // a_s * dt (weight of this stage in the accumulated update)
+    double ca;       // dt / 6, the weight of R in the last stage's update
     double cb;       // b_s * dt (offset of the next stage), unused in the last stage
     int stage;       // 0..3, or -1: write the right-hand side only
     int mask_lim;    // keep a mode iff 3|k_i| < mask_lim on every axis (N or N+2)

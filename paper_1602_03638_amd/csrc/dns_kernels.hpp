@@ -463,11 +463,21 @@ void k_zc2r(const cx<R>* __restrict__ W, R* __restrict__ u, const cx<R>* __restr
 // then per mode (Sec. 3.1 computeRHS; eqs. mod_pressure, NSfinal):
 //   N_hat *= dealias;  P_hat = k . N_hat / |k|^2 (0 at k = 0);
 //   N_hat -= k P_hat;  R = N_hat - nu |k|^2 u_s
-// and the classic RK4 stage update (Appendix solver):
-//   stage 0: U1 = U0 + a0 dt R,  Us = U0 + b0 dt R     (u_s = U0)
-//   stage 1,2: U1 += a_s dt R,    Us = U0 + b_s dt R    (u_s = Us)
-//   stage 3: U0 = U1 + a3 dt R                          (u_s = Us)
+// and one stage of the classic RK4 scheme of the Appendix solver,
+//   u_s1 = u0 + dt/2 k1,  u_s2 = u0 + dt/2 k2,  u_s3 = u0 + dt k3,
+//   u_new = u0 + dt/6 (k1 + 2 k2 + 2 k3 + k4),
+// with the final sum regrouped so that the state moves 36 fields per step
+// instead of 48: dt k1 = 2 (u_s1 - u0), dt k2 = 2 (u_s2 - u0) and
+// dt k3 = u_s3 - u0 give
+//   u_new = S + u_s3 / 3 + dt/6 k4,   S = (u_s1 + 2 u_s2 - u0) / 3,
+// and S is formed at stage 1, where u_s1, u_s2 and u0 are all at hand.
+// Arrays: U0 = u0, Us = the current stage velocity, U1 = S.
+//   stage 0:  Us = U0 + cb R                                   (u_s = U0)
+//   stage 1:  v = U0 + cb R,  U1 = (Us + 2 v - U0) / 3,  Us = v  (u_s = Us)
+//   stage 2:  Us = U0 + cb R                                   (u_s = Us)
+//   stage 3:  U0 = (U1 + Us / 3) + ca R                        (u_s = Us)
 //   stage -1: U1 = R (right-hand side only; u_s = U0)
+// with cb = b_s dt (b = 1/2, 1/2, 1) and ca = dt/6.
 // At stage 3 with diag != nullptr, each workgroup also writes partial sums
 // of w |u_hat|^2 and w |k x u_hat|^2 of the new state (w = 1 on the kz = 0
 // and kz = N/2 planes, 2 elsewhere) to diag[2 blockIdx], diag[2 blockIdx + 1].
@@ -477,11 +487,53 @@ void k_zc2r(const cx<R>* __restrict__ W, R* __restrict__ u, const cx<R>* __restr
 // entry; on return it holds the input of the next stage (Us for stages 0..2,
 // the new U0 for stage 3, R for stage -1), which the fused pass transforms
 // on without reading it back.
-// Per-element variant of the same update (identical arithmetic): each
-// element's state values are loaded, combined and stored before the next
-// element's; a compiler memory barrier between elements keeps the loads from
-// being batched.  Fewer registers than the batched form, for 1024-thread
-// shapes whose register budget is 128 per thread.
+
+// Dealias mask and projection of mode (kx, ky, kz): n -= k (k . n) / |k|^2.
+template <typename R>
+__device__ __forceinline__ void project_mode(cx<R>& n0, cx<R>& n1, cx<R>& n2, int kx, int ky, int kz, bool keep) {
+    if (!keep) {
+        n0 = {R(0), R(0)}; n1 = n0; n2 = n0;
+    }
+    const int k2 = kx * kx + ky * ky + kz * kz;
+    const R fx = (R)kx, fy = (R)ky, fz = (R)kz;
+    const R inv = k2 > 0 ? R(1) / (R)k2 : R(0);
+    // P_hat = sum_i N_i k_i / |k|^2
+    const cx<R> P = {(n0.x * fx + n1.x * fy + n2.x * fz) * inv, (n0.y * fx + n1.y * fy + n2.y * fz) * inv};
+    n0 = csub<R>(n0, cscale<R>(P, fx));
+    n1 = csub<R>(n1, cscale<R>(P, fy));
+    n2 = csub<R>(n2, cscale<R>(P, fz));
+}
+
+// S = (u_s1 + 2 v - u0) / 3 (stage 1) and the new state (U1 + u_s3 / 3) + ca R
+// (stage 3), written once so that both forms of the update round alike.
+template <typename R> __device__ __forceinline__ cx<R> rk_partial_sum(cx<R> us1, cx<R> v, cx<R> u0) {
+    const R third = R(1) / R(3);
+    return cscale<R>(csub<R>(cadd<R>(us1, cscale<R>(v, R(2))), u0), third);
+}
+template <typename R> __device__ __forceinline__ cx<R> rk_final(cx<R> s, cx<R> us3, cx<R> r, R ca) {
+    const R third = R(1) / R(3);
+    return cadd<R>(cadd<R>(s, cscale<R>(us3, third)), cscale<R>(r, ca));
+}
+
+// Partial sums of w |v|^2 and w |k x v|^2 of one mode of the new state.
+template <typename R, int N>
+__device__ __forceinline__ void diag_mode(cx<R> v0, cx<R> v1, cx<R> v2, int kx, int ky, int kz, double& e_acc,
+                                          double& w_acc) {
+    const double wgt = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
+    const double x0 = v0.x, y0 = v0.y, x1 = v1.x, y1 = v1.y, x2 = v2.x, y2 = v2.y;
+    e_acc += wgt * (x0 * x0 + y0 * y0 + x1 * x1 + y1 * y1 + x2 * x2 + y2 * y2);
+    const double dx = kx, dy = ky, dz = kz;
+    const double cxr = dy * x2 - dz * x1, cxi = dy * y2 - dz * y1;
+    const double cyr = dz * x0 - dx * x2, cyi = dz * y0 - dx * y2;
+    const double czr = dx * x1 - dy * x0, czi = dx * y1 - dy * y0;
+    w_acc += wgt * (cxr * cxr + cxi * cxi + cyr * cyr + cyi * cyi + czr * czr + czi * czi);
+}
+
+// Per-element form of the update: each element's state values are loaded,
+// combined and stored before the next element's; a compiler memory barrier
+// between elements keeps the loads from being batched.  Fewer registers than
+// the batched form, for 1024-thread shapes whose register budget is 128 per
+// thread.
 template <typename R, int N, int E, int STAGE, bool NYQ>
 __device__ __forceinline__ void rk_apply_elementwise(cx<R> (&nh)[3][E], const XCol<R, N, NYQ>& col, int g,
                                                      cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
@@ -498,26 +550,16 @@ __device__ __forceinline__ void rk_apply_elementwise(cx<R> (&nh)[3][E], const XC
     for (int m = 0; m < E; ++m) {
         const int kx = kfreq(g + m * G, N);
         const bool keep = keep_yz && (3 * abs(kx) < lim);
-        const int k2 = kx * kx + ky * ky + kz * kz;
         cx<R> n[3] = {nh[0][m], nh[1][m], nh[2][m]};
-        if (!keep) {
-            n[0] = {R(0), R(0)}; n[1] = n[0]; n[2] = n[0];
-        }
-        const R fx = (R)kx, fy = (R)ky, fz = (R)kz;
-        const R inv = k2 > 0 ? R(1) / (R)k2 : R(0);
-        const cx<R> P = {(n[0].x * fx + n[1].x * fy + n[2].x * fz) * inv,
-                         (n[0].y * fx + n[1].y * fy + n[2].y * fz) * inv};
-        n[0] = csub<R>(n[0], cscale<R>(P, fx));
-        n[1] = csub<R>(n[1], cscale<R>(P, fy));
-        n[2] = csub<R>(n[2], cscale<R>(P, fz));
+        project_mode<R>(n[0], n[1], n[2], kx, ky, kz, keep);
         const R visc = nu * (R)(kx * kx + ky * ky + kz * kz);
         const cx<R>* ps = (STAGE <= 0) ? U0 : Us;
-        cx<R> us[3], a0[3], a1[3];
+        cx<R> us[3], other[3];
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             us[f] = A(ps + f * FS, m);
-            if constexpr (STAGE > 0) a1[f] = A(U1 + f * FS, m);
-            if constexpr (STAGE == 1 || STAGE == 2) a0[f] = A(U0 + f * FS, m);
+            if constexpr (STAGE == 1 || STAGE == 2) other[f] = A(U0 + f * FS, m);
+            if constexpr (STAGE == 3) other[f] = A(U1 + f * FS, m);
         }
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
@@ -527,36 +569,34 @@ __device__ __forceinline__ void rk_apply_elementwise(cx<R> (&nh)[3][E], const XC
                 v = r;
                 A(U1 + f * FS, m) = v;
             } else if constexpr (STAGE == 0) {
-                A(U1 + f * FS, m) = cadd<R>(us[f], cscale<R>(r, ca));
                 v = cadd<R>(us[f], cscale<R>(r, cb));
                 A(Us + f * FS, m) = v;
-            } else if constexpr (STAGE < 3) {
-                A(U1 + f * FS, m) = cadd<R>(a1[f], cscale<R>(r, ca));
-                v = cadd<R>(a0[f], cscale<R>(r, cb));
+            } else if constexpr (STAGE == 1) {
+                v = cadd<R>(other[f], cscale<R>(r, cb));
+                A(U1 + f * FS, m) = rk_partial_sum<R>(us[f], v, other[f]);
+                A(Us + f * FS, m) = v;
+            } else if constexpr (STAGE == 2) {
+                v = cadd<R>(other[f], cscale<R>(r, cb));
                 A(Us + f * FS, m) = v;
             } else {
-                v = cadd<R>(a1[f], cscale<R>(r, ca));
+                v = rk_final<R>(other[f], us[f], r, ca);
                 A(U0 + f * FS, m) = v;
             }
             nh[f][m] = v;
         }
         if constexpr (STAGE == 3) {
-            if (sa.diag != nullptr) {
-                const double wgt = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
-                const cx<R> v0 = nh[0][m], v1 = nh[1][m], v2 = nh[2][m];
-                const double x0 = v0.x, y0 = v0.y, x1 = v1.x, y1 = v1.y, x2 = v2.x, y2 = v2.y;
-                e_acc += wgt * (x0 * x0 + y0 * y0 + x1 * x1 + y1 * y1 + x2 * x2 + y2 * y2);
-                const double dx = kx, dy = ky, dz = kz;
-                const double cxr = dy * x2 - dz * x1, cxi = dy * y2 - dz * y1;
-                const double cyr = dz * x0 - dx * x2, cyi = dz * y0 - dx * y2;
-                const double czr = dx * x1 - dy * x0, czi = dx * y1 - dy * y0;
-                w_acc += wgt * (cxr * cxr + cxi * cxi + cyr * cyr + cyi * cyi + czr * czr + czi * czi);
-            }
+            if (sa.diag != nullptr) diag_mode<R, N>(nh[0][m], nh[1][m], nh[2][m], kx, ky, kz, e_acc, w_acc);
         }
         asm volatile("" ::: "memory");
     }
 }
 
+// Batched form: after the projection the three fields are independent, so
+// the state is streamed one field at a time with all of a thread's elements
+// of that field (u_s and, from stage 1 on, the second array) in flight at
+// once; a compiler memory barrier after each field keeps the next field's
+// loads from being hoisted into the same batch (which would exhaust the
+// registers).
 template <typename R, int N, int E, int STAGE, bool NYQ>
 __device__ __forceinline__ void rk_apply_batched(cx<R> (&nh)[3][E], const XCol<R, N, NYQ>& col, int g,
                                                cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
@@ -570,107 +610,55 @@ __device__ __forceinline__ void rk_apply_batched(cx<R> (&nh)[3][E], const XCol<R
     const R nu = (R)sa.nu, ca = (R)sa.ca, cb = (R)sa.cb;
     const XAddr<R, N, NYQ> A(col, g);
 
-    // dealias and project: N_hat -= k (k . N_hat) / |k|^2
+    R visc[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int kx = kfreq(g + m * G, N);
         const bool keep = keep_yz && (3 * abs(kx) < lim);
-        const int k2 = kx * kx + ky * ky + kz * kz;
-        cx<R> n0 = nh[0][m], n1 = nh[1][m], n2 = nh[2][m];
-        if (!keep) {
-            n0 = {R(0), R(0)}; n1 = n0; n2 = n0;
+        project_mode<R>(nh[0][m], nh[1][m], nh[2][m], kx, ky, kz, keep);
+        visc[m] = nu * (R)(kx * kx + ky * ky + kz * kz);
+    }
+    const cx<R>* ps = (STAGE <= 0) ? U0 : Us;               // u_s
+    const cx<R>* po = (STAGE == 3) ? U1 : U0;                // second array of stages 1..3
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        cx<R> us[E], o[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            us[m] = A(ps + f * FS, m);
+            if constexpr (STAGE > 0) o[m] = A(po + f * FS, m);
         }
-        const R fx = (R)kx, fy = (R)ky, fz = (R)kz;
-        const R inv = k2 > 0 ? R(1) / (R)k2 : R(0);
-        // P_hat = sum_i N_i k_i / |k|^2
-        const cx<R> P = {(n0.x * fx + n1.x * fy + n2.x * fz) * inv, (n0.y * fx + n1.y * fy + n2.y * fz) * inv};
-        nh[0][m] = csub<R>(n0, cscale<R>(P, fx));
-        nh[1][m] = csub<R>(n1, cscale<R>(P, fy));
-        nh[2][m] = csub<R>(n2, cscale<R>(P, fz));
-    }
-    // The state arrays are streamed one at a time, all elements of a thread
-    // at once, so that many loads are in flight together; a compiler memory
-    // barrier after each array keeps the next array's loads from being
-    // hoisted into the same batch (which would exhaust the registers).
-    // R = N_hat - nu |k|^2 u_s   (u_s = U0 at stage 0 and for the RHS alone)
-    cx<R> us[3][E];
-    const cx<R>* ps = (STAGE <= 0) ? U0 : Us;
 #pragma unroll
-    for (int f = 0; f < 3; ++f)
-#pragma unroll
-        for (int m = 0; m < E; ++m) us[f][m] = A(ps + f * FS, m);
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const int kx = kfreq(g + m * G, N);
-        const R visc = nu * (R)(kx * kx + ky * ky + kz * kz);
-#pragma unroll
-        for (int f = 0; f < 3; ++f) nh[f][m] = csub<R>(nh[f][m], cscale<R>(us[f][m], visc));
-    }
-    if constexpr (STAGE != 0) asm volatile("" ::: "memory");
-    if constexpr (STAGE < 0) {
-#pragma unroll
-        for (int f = 0; f < 3; ++f)
-#pragma unroll
-            for (int m = 0; m < E; ++m) A(U1 + f * FS, m) = nh[f][m];
-    } else if constexpr (STAGE == 0) {
-        // U1 = U0 + a0 dt R;  Us = U0 + b0 dt R
-#pragma unroll
-        for (int f = 0; f < 3; ++f)
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                A(U1 + f * FS, m) = cadd<R>(us[f][m], cscale<R>(nh[f][m], ca));
-                nh[f][m] = cadd<R>(us[f][m], cscale<R>(nh[f][m], cb));
-                A(Us + f * FS, m) = nh[f][m];
+        for (int m = 0; m < E; ++m) {
+            // R = N_hat - nu |k|^2 u_s
+            const cx<R> r = csub<R>(nh[f][m], cscale<R>(us[m], visc[m]));
+            cx<R> v;
+            if constexpr (STAGE < 0) {
+                v = r;
+                A(U1 + f * FS, m) = v;
+            } else if constexpr (STAGE == 0) {
+                v = cadd<R>(us[m], cscale<R>(r, cb));
+                A(Us + f * FS, m) = v;
+            } else if constexpr (STAGE == 1) {
+                v = cadd<R>(o[m], cscale<R>(r, cb));
+                A(U1 + f * FS, m) = rk_partial_sum<R>(us[m], v, o[m]);
+                A(Us + f * FS, m) = v;
+            } else if constexpr (STAGE == 2) {
+                v = cadd<R>(o[m], cscale<R>(r, cb));
+                A(Us + f * FS, m) = v;
+            } else {
+                v = rk_final<R>(o[m], us[m], r, ca);
+                A(U0 + f * FS, m) = v;
             }
-    } else if constexpr (STAGE < 3) {
-        // U1 += a_s dt R;  Us = U0 + b_s dt R
-#pragma unroll
-        for (int f = 0; f < 3; ++f)
-#pragma unroll
-            for (int m = 0; m < E; ++m) us[f][m] = A(U1 + f * FS, m);
-#pragma unroll
-        for (int f = 0; f < 3; ++f)
-#pragma unroll
-            for (int m = 0; m < E; ++m) A(U1 + f * FS, m) = cadd<R>(us[f][m], cscale<R>(nh[f][m], ca));
+            nh[f][m] = v;
+        }
         asm volatile("" ::: "memory");
-#pragma unroll
-        for (int f = 0; f < 3; ++f)
-#pragma unroll
-            for (int m = 0; m < E; ++m) us[f][m] = A(U0 + f * FS, m);
-#pragma unroll
-        for (int f = 0; f < 3; ++f)
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                nh[f][m] = cadd<R>(us[f][m], cscale<R>(nh[f][m], cb));
-                A(Us + f * FS, m) = nh[f][m];
-            }
-    } else {
-        // U0 = U1 + a3 dt R  (the new state)
-#pragma unroll
-        for (int f = 0; f < 3; ++f)
-#pragma unroll
-            for (int m = 0; m < E; ++m) us[f][m] = A(U1 + f * FS, m);
-#pragma unroll
-        for (int f = 0; f < 3; ++f)
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                nh[f][m] = cadd<R>(us[f][m], cscale<R>(nh[f][m], ca));
-                A(U0 + f * FS, m) = nh[f][m];
-            }
+    }
+    if constexpr (STAGE == 3) {
         if (sa.diag != nullptr) {
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int kx = kfreq(g + m * G, N);
-                const double wgt = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
-                const cx<R> v0 = nh[0][m], v1 = nh[1][m], v2 = nh[2][m];
-                const double x0 = v0.x, y0 = v0.y, x1 = v1.x, y1 = v1.y, x2 = v2.x, y2 = v2.y;
-                e_acc += wgt * (x0 * x0 + y0 * y0 + x1 * x1 + y1 * y1 + x2 * x2 + y2 * y2);
-                const double dx = kx, dy = ky, dz = kz;
-                const double cxr = dy * x2 - dz * x1, cxi = dy * y2 - dz * y1;
-                const double cyr = dz * x0 - dx * x2, cyi = dz * y0 - dx * y2;
-                const double czr = dx * x1 - dy * x0, czi = dx * y1 - dy * y0;
-                w_acc += wgt * (cxr * cxr + cxi * cxi + cyr * cyr + cyi * cyi + czr * czr + czi * czi);
-            }
+            for (int m = 0; m < E; ++m)
+                diag_mode<R, N>(nh[0][m], nh[1][m], nh[2][m], kfreq(g + m * G, N), ky, kz, e_acc, w_acc);
         }
     }
 }
