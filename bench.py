@@ -144,6 +144,66 @@ def run_ensemble(steps, warmup, per_sim_steps, autotune=True):
             "speedup": round(ms_p / ms_b, 2), "energy_mean": sum(E) / len(E)}
 
 
+# Random isotropic field at 1024^3 (seed 1, k0 = 4, E = 0.5): FP32 path
+# timed, FP64 path as its reference (the CPU oracle cannot hold 1024^3).
+ISO_N, ISO_NU, ISO_DT, ISO_STEPS, ISO_SEED = 1024, 1e-3, 5e-4, 20, 1
+
+
+def run_isotropic(N=ISO_N, steps=ISO_STEPS, warmup=2):
+    """ms per RK4 step of the random isotropic field in FP32 and FP64, and
+    the FP32 errors against the FP64 path after `steps` steps (relative
+    energy and enstrophy differences, relative L2 of the spectral velocity).
+    Both start from the same FP64-generated spectrum (FP32 takes it rounded),
+    so the difference is the FP32 arithmetic alone."""
+    import torch
+    from paper_1602_03638_amd import Solver
+
+    def run(dtype, uh0):
+        s = Solver(N, ISO_NU, ISO_DT, dtype=dtype)
+        s.set_spectral(uh0.to(s.complex).contiguous())
+        s.step(warmup)
+        s.synchronize()
+        s.set_spectral(uh0.to(s.complex).contiguous())   # timed run from the initial field
+        s.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.synchronize()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        E, W = s.diagnostics()
+        out = s.get_spectral()
+        s.close()
+        return ms, E, W, out
+
+    s = Solver(N, ISO_NU, ISO_DT, dtype="f64")
+    s.init_random(ISO_SEED, k0=4.0, energy=0.5)
+    E0, W0 = s.diagnostics()
+    uh0 = s.get_spectral()
+    s.close()
+    torch.cuda.empty_cache()
+    ms32, E32, W32, u32 = run("f32", uh0)
+    u32 = u32.cpu()
+    torch.cuda.empty_cache()
+    ms64, E64, W64, u64 = run("f64", uh0)
+    del uh0
+    torch.cuda.empty_cache()
+    diff = (u32.to(u64.device).to(torch.complex128) - u64)
+    rel_l2 = float(torch.linalg.vector_norm(diff) / torch.linalg.vector_norm(u64))
+    del diff, u64, u32
+    torch.cuda.empty_cache()
+    C = field_bytes(N, "f32")
+    return {"workload": f"random_isotropic_{N}_rk4", "N": N, "nu": ISO_NU, "dt": ISO_DT, "steps": steps,
+            "seed": ISO_SEED, "k0": 4.0, "E0": E0, "Omega0": W0,
+            "fp32": {"ms_per_step": round(ms32, 3), "model_GBps": round(FIELDS_PER_STEP * C / (ms32 * 1e-3) / 1e9, 1),
+                     "energy": E32, "enstrophy": W32},
+            "fp64": {"ms_per_step": round(ms64, 3),
+                     "model_GBps": round(FIELDS_PER_STEP * 2 * C / (ms64 * 1e-3) / 1e9, 1),
+                     "energy": E64, "enstrophy": W64},
+            "fp32_vs_fp64": {"rel_energy": abs(E32 - E64) / E64, "rel_enstrophy": abs(W32 - W64) / W64,
+                             "rel_l2_spectral_velocity": rel_l2}}
+
+
 def cpu_baseline(N):
     """Time the CPU oracle on a bounded sample of the workload: one inverse and
     one forward 3D transform of one velocity component at N^3, scaled to one
@@ -245,6 +305,8 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--ensemble-only", action="store_true")
+    ap.add_argument("--no-isotropic", action="store_true", help="skip the 1024^3 random isotropic leg")
+    ap.add_argument("--isotropic-only", action="store_true")
     ap.add_argument("--ens-steps", type=int, default=100)
     ap.add_argument("--ens-per-sim-steps", type=int, default=20)
     ap.add_argument("--ens-default-tiles", action="store_true", help="ensemble without the tile autotuner")
@@ -263,6 +325,9 @@ def main(argv=None):
               "(the slab decomposition over several GPUs is described, not built)", file=sys.stderr)
         return 2
 
+    if a.isotropic_only:
+        print(json.dumps({"random_isotropic": run_isotropic()}), flush=True)
+        return 0
     if a.ensemble_only:
         ens = run_ensemble(a.ens_steps, a.warmup, a.ens_per_sim_steps, not a.ens_default_tiles)
         print(json.dumps({"ensemble": ens}), flush=True)
@@ -286,6 +351,7 @@ def main(argv=None):
                 "bytes_per_launch": FIELDS_PER_LAUNCH[dom] * C,
                 "mean_launch_ms": f64["kernels_ms"][dom]}
     ens = None if a.no_ensemble else run_ensemble(a.ens_steps, a.warmup, a.ens_per_sim_steps, not a.ens_default_tiles)
+    iso = None if a.no_isotropic else run_isotropic()
     cpu = None if a.no_cpu_baseline else cpu_baseline(a.N)
     line = {
         "metric": METRIC, "value": round(f64["ms_per_step"], 4), "unit": "ms/step",
@@ -308,6 +374,8 @@ def main(argv=None):
                         "kernels_ms": f32["kernels_ms"]}
     if ens is not None:
         line["ensemble"] = ens
+    if iso is not None:
+        line["random_isotropic"] = iso
     print(json.dumps(line), flush=True)
     return 0
 

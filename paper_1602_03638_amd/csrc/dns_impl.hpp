@@ -94,8 +94,13 @@ template <typename R, int N> struct Impl {
     }
 
     // ---- standalone transforms (fixed shapes) -------------------------------
-    static constexpr int TS = x_ok<8>() ? 8 : (x_ok<4>() ? 4 : (x_ok<2>() ? 2 : 1));
-    static constexpr int YS = y_ok<8>() ? 8 : (y_ok<4>() ? 4 : (y_ok<2>() ? 2 : 1));
+    // FP64 lines of 8 complex doubles per thread need more than the 128
+    // registers a 1024-thread workgroup leaves each thread: at most 512.
+    static constexpr int MAXT = sizeof(R) == 8 ? 512 : 1024;
+    template <int T> static constexpr bool xs_ok() { return x_ok<T>() && G * T <= MAXT; }
+    template <int T> static constexpr bool ys_ok() { return y_ok<T>() && G * T <= MAXT; }
+    static constexpr int TS = xs_ok<8>() ? 8 : (xs_ok<4>() ? 4 : (xs_ok<2>() ? 2 : 1));
+    static constexpr int YS = ys_ok<8>() ? 8 : (ys_ok<4>() ? 4 : (ys_ok<2>() ? 2 : 1));
     static constexpr int LS = N >= 128 ? 4 : 512 / N;
     static void xinv3(const void* U, void* W, const void* tw, hipStream_t s) {
         hipLaunchKernelGGL((k_xplain<R, N, TS, +1, 3>), dim3(x_groups<TS>()), dim3(G * TS), 0, s,
@@ -182,11 +187,12 @@ template <typename R, int N> struct Impl {
             o.width[P_ZCROSS][n++] = L;
         }
     }
-    // index of the widest variant of pass p not wider than w
+    // index of the widest variant of pass p not wider than w whose
+    // workgroup has at most MAXT threads (lines of G threads; the z pass too)
     static int pick(const Ops& o, int p, int w) {
         int best = 0;
         for (int v = 0; v < o.nvar[p]; ++v)
-            if (o.width[p][v] <= w) best = v;
+            if (o.width[p][v] <= w && G * o.width[p][v] <= MAXT) best = v;
         return best;
     }
     static Ops make() {

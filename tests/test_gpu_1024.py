@@ -1,0 +1,111 @@
+"""GPU checks at 1024^3, the size of the random isotropic workload (FP32,
+nu = 1e-3, dt = 5e-4, seed 1, k0 = 4, E = 0.5).
+
+The oracle cannot hold a 1024^3 field, so the checks use results fixed by
+the mathematics at any size:
+  * the forward transform of a sum of plane waves a cos(k . x + phi) is
+    N^3 a e^{i phi} / 2 at k and zero at every other stored mode (closed form
+    of the DFT, which pins axis order, sign and normalisation);
+  * the random initial field has E = 0.5 and the semi-discrete energy budget
+    dE/dt = -2 nu Omega holds over RK4 steps (trapezoid rule);
+  * FP32 and FP64 runs from the same spectrum agree in energy to 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import note, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+N = 1024
+NU, DT = 1e-3, 5e-4
+
+# (kx, ky, kz, amplitude, phase) per component; 0 < kz < N/2, distinct k
+WAVES = [
+    [(1, 0, 1, 1.0, 0.3), (-37, 200, 5, 0.25, -1.1)],
+    [(0, 3, 2, 0.5, 2.0), (511, -512, 511, 0.125, 0.7)],
+    [(-1, -1, 3, 0.75, -0.4), (300, 17, 250, 0.0625, 1.9)],
+]
+
+
+def _plane_waves(torch, dtype):
+    """Physical (3, N, N, N) field of the waves above on x_i = 2 pi i / N; the
+    phase (k . i mod N) is reduced in integers before the angle is formed."""
+    real = torch.float64 if dtype == "f64" else torch.float32
+    u = torch.empty((3, N, N, N), dtype=real, device="cuda")
+    i = torch.arange(N, device="cuda", dtype=torch.int64)
+    for c, waves in enumerate(WAVES):
+        acc = torch.zeros((N, N, N), dtype=torch.float64, device="cuda")
+        for kx, ky, kz, a, phi in waves:
+            m = ((kx * i)[:, None, None] + (ky * i)[None, :, None] + (kz * i)[None, None, :]) % N
+            acc += a * torch.cos(m.to(torch.float64) * (2.0 * math.pi / N) + phi)
+            del m
+        u[c] = acc.to(real)
+        del acc
+    return u
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 2e-6)])
+def test_forward_1024_plane_waves(dtype, tol):
+    note(f"forward 1024 {dtype} plane waves")
+    torch = torch_mod()
+    from paper_1602_03638_amd import Solver
+    u = _plane_waves(torch, dtype)
+    torch.cuda.empty_cache()             # the library allocates outside torch's cache
+    s = Solver(N, NU, DT, dtype=dtype)
+    uh = s.forward(u)
+    s.close()
+    del u
+    scale = float(N) ** 3
+    for c, waves in enumerate(WAVES):
+        for kx, ky, kz, a, phi in waves:
+            want = scale * a * complex(math.cos(phi), math.sin(phi)) / 2
+            got = complex(uh[c, kx % N, ky % N, kz].item())
+            assert abs(got - want) / scale <= tol, (c, kx, ky, kz, got, want)
+            uh[c, kx % N, ky % N, kz] = 0
+    rest = float(uh.abs().max().item()) / scale
+    assert rest <= tol, rest
+    del uh
+    torch.cuda.empty_cache()
+
+
+def test_random_isotropic_1024_budget_and_precision():
+    """Seeded random isotropic field at 1024^3: E0 = 0.5; after each of two
+    FP64 RK4 steps (E_{n+1} - E_n) / dt = -nu (Omega_n + Omega_{n+1}) to the
+    time-discretisation error; FP32 from the same spectrum agrees in energy and
+    enstrophy to 1e-5 relative."""
+    note("random isotropic 1024 fp64 budget")
+    torch = torch_mod()
+    from paper_1602_03638_amd import Solver
+    s = Solver(N, NU, DT, dtype="f64")
+    s.init_random(1, k0=4.0, energy=0.5)
+    E, W = [], []
+    e, w = s.diagnostics()
+    E.append(e)
+    W.append(w)
+    assert abs(E[0] - 0.5) <= 1e-12
+    uh0 = s.get_spectral()
+    for _ in range(2):
+        s.step(1)
+        e, w = s.diagnostics()
+        E.append(e)
+        W.append(w)
+    s.close()
+    for n in range(2):
+        lhs = (E[n + 1] - E[n]) / DT
+        rhs = -NU * (W[n] + W[n + 1])
+        # trapezoid error ~ dt^2 Omega'' / (12 Omega) ~ 1e-7 relative here
+        assert abs(lhs - rhs) <= 1e-5 * abs(rhs), (n, lhs, rhs)
+    note("random isotropic 1024 fp32 vs fp64")
+    s = Solver(N, NU, DT, dtype="f32")
+    s.set_spectral(uh0.to(torch.complex64).contiguous())
+    del uh0
+    torch.cuda.empty_cache()
+    s.step(2)
+    e32, w32 = s.diagnostics()
+    s.close()
+    assert abs(e32 - E[2]) / E[2] <= 1e-5
+    assert abs(w32 - W[2]) / W[2] <= 1e-5
+    assert np.isfinite(e32) and np.isfinite(w32)
