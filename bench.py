@@ -204,6 +204,58 @@ def run_isotropic(N=ISO_N, steps=ISO_STEPS, warmup=2):
                              "rel_l2_spectral_velocity": rel_l2}}
 
 
+# The paper's FFT benchmark (Sec. 4.3): one forward and one inverse 3D real
+# transform, fastest of 10, here of a 3-component field held in HBM.
+FFT_SIZES = (128, 256, 512, 1024)
+
+
+def run_fft(sizes=FFT_SIZES, dtypes=("f32", "f64"), reps=10):
+    """Time dns_set_velocity (z r2c, y, x: physical -> internal spectrum) plus
+    dns_get_velocity (x, y, z c2r) of a random 3-component field: fastest
+    and mean of `reps` pairs (torch events on the caller's stream, which the
+    library's stream is ordered with).  Algorithmic traffic of one pair:
+    forward 3R + 15C (z pass reads 3 real fields, writes 3 spectra; y in
+    place; x out of place), inverse the same, R = N^3 reals, C = N^2 (N/2+1)
+    complex values."""
+    import torch
+    from paper_1602_03638_amd import Solver
+    out = []
+    for dtype in dtypes:
+        for N in sizes:
+            real = torch.float64 if dtype == "f64" else torch.float32
+            g = torch.Generator(device="cuda").manual_seed(N)
+            u = torch.randn((3, N, N, N), generator=g, dtype=real, device="cuda")
+            v = torch.empty_like(u)
+            torch.cuda.empty_cache()
+            s = Solver(N, NU, DT, dtype=dtype)
+            for _ in range(2):
+                s.set_velocity(u)
+                s.get_velocity(v)
+            times = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                s.set_velocity(u)
+                s.get_velocity(v)
+                e1.record()
+                e1.synchronize()
+                times.append(e0.elapsed_time(e1))
+            err = float(torch.linalg.vector_norm(v - u) / torch.linalg.vector_norm(u))
+            s.close()
+            del u, v
+            torch.cuda.empty_cache()
+            S = 8 if dtype == "f64" else 4
+            nbytes = 2 * (3 * N ** 3 * S + 15 * field_bytes(N, dtype))
+            best = min(times)
+            out.append({"N": N, "dtype": dtype, "ms_pair_best": round(best, 4),
+                        "ms_pair_mean": round(sum(times) / len(times), 4),
+                        "ms_pair_per_component": round(best / 3, 4),
+                        "GBps_best": round(nbytes / (best * 1e-3) / 1e9, 1),
+                        "roundtrip_rel_l2": err})
+    return {"workload": "forward + inverse 3D real FFT of a 3-component random field, fastest of "
+                        f"{reps}", "results": out}
+
+
 def cpu_baseline(N):
     """Time the CPU oracle on a bounded sample of the workload: one inverse and
     one forward 3D transform of one velocity component at N^3, scaled to one
@@ -307,6 +359,8 @@ def main(argv=None):
     ap.add_argument("--ensemble-only", action="store_true")
     ap.add_argument("--no-isotropic", action="store_true", help="skip the 1024^3 random isotropic leg")
     ap.add_argument("--isotropic-only", action="store_true")
+    ap.add_argument("--no-fft", action="store_true", help="skip the FFT-only leg")
+    ap.add_argument("--fft-only", action="store_true")
     ap.add_argument("--ens-steps", type=int, default=100)
     ap.add_argument("--ens-per-sim-steps", type=int, default=20)
     ap.add_argument("--ens-default-tiles", action="store_true", help="ensemble without the tile autotuner")
@@ -325,6 +379,9 @@ def main(argv=None):
               "(the slab decomposition over several GPUs is described, not built)", file=sys.stderr)
         return 2
 
+    if a.fft_only:
+        print(json.dumps({"fft": run_fft()}), flush=True)
+        return 0
     if a.isotropic_only:
         print(json.dumps({"random_isotropic": run_isotropic()}), flush=True)
         return 0
@@ -352,6 +409,7 @@ def main(argv=None):
                 "mean_launch_ms": f64["kernels_ms"][dom]}
     ens = None if a.no_ensemble else run_ensemble(a.ens_steps, a.warmup, a.ens_per_sim_steps, not a.ens_default_tiles)
     iso = None if a.no_isotropic else run_isotropic()
+    fft = None if a.no_fft else run_fft()
     cpu = None if a.no_cpu_baseline else cpu_baseline(a.N)
     line = {
         "metric": METRIC, "value": round(f64["ms_per_step"], 4), "unit": "ms/step",
@@ -376,6 +434,8 @@ def main(argv=None):
         line["ensemble"] = ens
     if iso is not None:
         line["random_isotropic"] = iso
+    if fft is not None:
+        line["fft"] = fft
     print(json.dumps(line), flush=True)
     return 0
 

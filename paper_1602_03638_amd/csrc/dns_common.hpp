@@ -84,6 +84,16 @@ template <typename R, int N> struct Lay {
     }
 };
 
+// Elements per thread of the y-pass line transforms.  Lines of 1024 take
+// 16 (FP64) or 32 (FP32) complex values per thread, so that a workgroup of
+// 128-byte row segments (8 FP64 or 16 FP32 columns) has 512 threads, each
+// holding one 256-byte line slice; shorter lines take 8.
+template <typename R> constexpr int y_elems(int N) { return N >= 1024 ? (sizeof(R) == 8 ? 16 : 32) : 8; }
+// With more than 8 elements per thread the y pass reads its twiddles from
+// shared memory at every stage (kept in registers they would crowd out the
+// line).
+template <typename R> constexpr bool y_twiddles_in_lds(int N) { return y_elems<R>(N) > 8; }
+
 // Workgroups of the standalone diagnostic reduction (fixed, so the summation
 // order and hence the result are reproducible).
 constexpr int DIAG_BLOCKS = 1024;

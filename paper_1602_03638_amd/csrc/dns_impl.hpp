@@ -28,8 +28,10 @@ template <typename R, int N> struct Impl {
         return x_ok<T>() && (sizeof(R) == 4 || G * T <= 512) &&
                (size_t)T * N * CB + 2 * 8 * (size_t)G * T <= LDS_LIMIT;
     }
+    static constexpr int GY = N / y_elems<R>(N);   // threads per y line
     template <int T> static constexpr bool y_ok() {
-        return T <= N / 2 && G * T <= 1024 && (size_t)T * N * CB <= LDS_LIMIT;
+        return T <= N / 2 && GY * T <= 1024 &&
+               ((size_t)T * N + (y_twiddles_in_lds<R>(N) ? (size_t)tw_size(N) : 0)) * CB <= LDS_LIMIT;
     }
     // z shapes: at least 16 threads, and up to 128 threads for small N
     template <int L> static constexpr bool z_ok() {
@@ -44,7 +46,7 @@ template <typename R, int N> struct Impl {
                            (const C*)U, (C*)W, (const C*)tw, b.sst, b.wst);
     }
     template <int T, int DIR, int NF> static void ypass(void* W, const void* tw, const Batch& b, hipStream_t s) {
-        hipLaunchKernelGGL((k_yline<R, N, T, DIR, NF>), dim3(y_tiles<R, N, T>(), b.members), dim3(G * T), 0, s,
+        hipLaunchKernelGGL((k_yline<R, N, T, DIR, NF>), dim3(y_tiles<R, N, T>(), b.members), dim3(GY * T), 0, s,
                            (C*)W, (const C*)tw, b.wst);
     }
     template <int T> static void yinv6(void* W, const void* tw, const Batch& b, hipStream_t s) {
@@ -98,7 +100,7 @@ template <typename R, int N> struct Impl {
     // registers a 1024-thread workgroup leaves each thread: at most 512.
     static constexpr int MAXT = sizeof(R) == 8 ? 512 : 1024;
     template <int T> static constexpr bool xs_ok() { return x_ok<T>() && G * T <= MAXT; }
-    template <int T> static constexpr bool ys_ok() { return y_ok<T>() && G * T <= MAXT; }
+    template <int T> static constexpr bool ys_ok() { return y_ok<T>() && GY * T <= MAXT; }
     static constexpr int TS = xs_ok<8>() ? 8 : (xs_ok<4>() ? 4 : (xs_ok<2>() ? 2 : 1));
     static constexpr int YS = ys_ok<8>() ? 8 : (ys_ok<4>() ? 4 : (ys_ok<2>() ? 2 : 1));
     static constexpr int LS = N >= 128 ? 4 : 512 / N;
@@ -188,11 +190,12 @@ template <typename R, int N> struct Impl {
         }
     }
     // index of the widest variant of pass p not wider than w whose
-    // workgroup has at most MAXT threads (lines of G threads; the z pass too)
+    // workgroup has at most MAXT threads
     static int pick(const Ops& o, int p, int w) {
+        const int per_line = (p == P_YINV6 || p == P_YFWD3) ? GY : G;
         int best = 0;
         for (int v = 0; v < o.nvar[p]; ++v)
-            if (o.width[p][v] <= w && G * o.width[p][v] <= MAXT) best = v;
+            if (o.width[p][v] <= w && per_line * o.width[p][v] <= MAXT) best = v;
         return best;
     }
     static Ops make() {

@@ -191,8 +191,9 @@ void k_xplain(const cx<R>* __restrict__ S, cx<R>* __restrict__ D, const cx<R>* _
 
 // ---------------------------------------------------------------------------
 // Pass 2/4: y transform (direction DIR) of NF fields, in place.
-// Main block: a workgroup takes T consecutive iz of one ix; rows iy have
-// stride N/2, thread (t, g) holds elements g + m G of line t.
+// Main block: a workgroup takes T consecutive iz of one ix; rows iy are one
+// row pitch apart, thread (t, g) holds elements g + m G of line t
+// (E = y_elems<R>(N) elements per thread, G = N / E).
 // Nyquist plane (kz = N/2, the last N/T workgroups): a workgroup takes T
 // consecutive ix, whose lines are contiguous; thread (l, g) holds elements
 // g + m G of line l, so consecutive threads read consecutive elements.
@@ -200,7 +201,8 @@ void k_xplain(const cx<R>* __restrict__ S, cx<R>* __restrict__ D, const cx<R>* _
 template <typename R, int N, int T, int DIR, int NF, bool NYQ>
 __device__ __forceinline__ void yline_tile(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, cx<R>* lds,
                                            int tile) {
-    constexpr int E = 8, G = N / E;
+    constexpr bool TWL = y_twiddles_in_lds<R>(N);
+    constexpr int E = y_elems<R>(N), G = N / E;
     constexpr size_t FS = Lay<R, N>::FS;
     constexpr int ZT = (N / 2) / T;          // main tiles per ix
     using L = Lay<R, N>;
@@ -225,7 +227,7 @@ __device__ __forceinline__ void yline_tile(cx<R>* __restrict__ W, const cx<R>* _
         cx<R> a[E];
 #pragma unroll
         for (int m = 0; m < E; ++m) a[m] = F[base + (unsigned)(g + m * G) * rs];
-        fft_line<R, N, E, DIR>(a, lds + lo, ps, tw, g);
+        fft_line<R, N, E, DIR, TWL>(a, lds + lo, ps, tw, g);
 #pragma unroll
         for (int m = 0; m < E; ++m) F[base + (unsigned)(g + m * G) * rs] = a[m];
     }
@@ -235,13 +237,20 @@ template <typename R, int N, int T> constexpr int y_main_tiles() { return N * ((
 template <typename R, int N, int T> constexpr int y_tiles() { return y_main_tiles<R, N, T>() + N / T; }
 
 template <typename R, int N, int T, int DIR, int NF>
-__global__ __launch_bounds__(N / 8 * T)
+__global__ __launch_bounds__(N / y_elems<R>(N) * T)
 void k_yline(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
     W += blockIdx.y * wst;
     __shared__ cx<R> lds[T * N];
+    constexpr bool TWL = y_twiddles_in_lds<R>(N);
+    __shared__ cx<R> twl[TWL ? tw_size(N) : 1];
+    const cx<R>* t = tw;
+    if constexpr (TWL) {
+        load_twiddles<R, N>(twl, tw);
+        t = twl;
+    }
     const int b = blockIdx.x;
-    if (b < y_main_tiles<R, N, T>()) yline_tile<R, N, T, DIR, NF, false>(W, tw, lds, b);
-    else yline_tile<R, N, T, DIR, NF, true>(W, tw, lds, b - y_main_tiles<R, N, T>());
+    if (b < y_main_tiles<R, N, T>()) yline_tile<R, N, T, DIR, NF, false>(W, t, lds, b);
+    else yline_tile<R, N, T, DIR, NF, true>(W, t, lds, b - y_main_tiles<R, N, T>());
 }
 
 // Load element k (0 <= k < N) of the Hermitian extension of a half-spectrum
