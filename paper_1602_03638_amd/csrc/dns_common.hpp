@@ -94,6 +94,12 @@ template <typename R> constexpr int y_elems(int N) { return N >= 1024 ? (sizeof(
 // line).
 template <typename R> constexpr bool y_twiddles_in_lds(int N) { return y_elems<R>(N) > 8; }
 
+// Elements per thread of the x-pass line transforms.  8 for every size: the
+// fused stage kernel holds three lines per thread, and 16 per thread (which
+// would fit 128-byte FP32 rows of 1024-lines into fewer threads) spilled and
+// measured slower at 1024^3 (24.7 vs 22.1 ms per launch on MI355X).
+template <typename R> constexpr int x_elems(int) { return 8; }
+
 // Workgroups of the standalone diagnostic reduction (fixed, so the summation
 // order and hence the result are reproducible).
 constexpr int DIAG_BLOCKS = 1024;

@@ -14,19 +14,22 @@ constexpr size_t LDS_LIMIT = 160 * 1024;
 
 template <typename R, int N> struct Impl {
     using C = cx<R>;
-    static constexpr int G = N / 8;
+    static constexpr int G = N / 8;                // threads per z line
+    static constexpr int GX = N / x_elems<R>(N);   // threads per x line
     static constexpr size_t CB = sizeof(C);
     static constexpr int XCOLS = N * (N / 2);
 
     // Feasibility of a workgroup shape: at most 1024 threads and the LDS limit.
+    // (lines of more than 8 elements per thread need more than the 128
+    // registers a 1024-thread workgroup leaves each thread)
     template <int T> static constexpr bool x_ok() {
-        return T <= N && G * T <= 1024 && (size_t)T * N * CB <= LDS_LIMIT;
+        return T <= N && GX * T <= (x_elems<R>(N) > 8 ? 512 : 1024) && (size_t)T * N * CB <= LDS_LIMIT;
     }
     // The RHS/RK4 passes hold three lines plus state per thread: in FP64
     // their 1024-thread shapes (128 registers per thread) only spill.
     template <int T> static constexpr bool xr_ok() {
-        return x_ok<T>() && (sizeof(R) == 4 || G * T <= 512) &&
-               (size_t)T * N * CB + 2 * 8 * (size_t)G * T <= LDS_LIMIT;
+        return x_ok<T>() && (sizeof(R) == 4 || GX * T <= 512) &&
+               (size_t)T * N * CB + 2 * 8 * (size_t)GX * T <= LDS_LIMIT;
     }
     static constexpr int GY = N / y_elems<R>(N);   // threads per y line
     template <int T> static constexpr bool y_ok() {
@@ -42,7 +45,7 @@ template <typename R, int N> struct Impl {
 
     // ---- pass launchers ----------------------------------------------------
     template <int T> static void xinv(const void* U, void* W, const void* tw, const Batch& b, hipStream_t s) {
-        hipLaunchKernelGGL((k_xinv_curl<R, N, T>), dim3(x_groups<T>(), b.members), dim3(G * T), 0, s,
+        hipLaunchKernelGGL((k_xinv_curl<R, N, T>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0, s,
                            (const C*)U, (C*)W, (const C*)tw, b.sst, b.wst);
     }
     template <int T, int DIR, int NF> static void ypass(void* W, const void* tw, const Batch& b, hipStream_t s) {
@@ -63,7 +66,7 @@ template <typename R, int N> struct Impl {
     template <int T, int ST>
     static void xrhs_st(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
                         const Batch& b, hipStream_t s) {
-        hipLaunchKernelGGL((k_xrhs<R, N, T, ST>), dim3(x_groups<T>(), b.members), dim3(G * T), 0, s,
+        hipLaunchKernelGGL((k_xrhs<R, N, T, ST>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0, s,
                            (const C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a, b.sst, b.wst);
     }
     template <int T>
@@ -81,7 +84,7 @@ template <typename R, int N> struct Impl {
     template <int T, int ST>
     static void xstage_st(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
                           const Batch& b, hipStream_t s) {
-        hipLaunchKernelGGL((k_xstage<R, N, T, ST>), dim3(x_groups<T>(), b.members), dim3(G * T), 0, s,
+        hipLaunchKernelGGL((k_xstage<R, N, T, ST>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0, s,
                            (C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a, b.sst, b.wst);
     }
     template <int T>
@@ -99,17 +102,17 @@ template <typename R, int N> struct Impl {
     // FP64 lines of 8 complex doubles per thread need more than the 128
     // registers a 1024-thread workgroup leaves each thread: at most 512.
     static constexpr int MAXT = sizeof(R) == 8 ? 512 : 1024;
-    template <int T> static constexpr bool xs_ok() { return x_ok<T>() && G * T <= MAXT; }
+    template <int T> static constexpr bool xs_ok() { return x_ok<T>() && GX * T <= MAXT; }
     template <int T> static constexpr bool ys_ok() { return y_ok<T>() && GY * T <= MAXT; }
     static constexpr int TS = xs_ok<8>() ? 8 : (xs_ok<4>() ? 4 : (xs_ok<2>() ? 2 : 1));
     static constexpr int YS = ys_ok<8>() ? 8 : (ys_ok<4>() ? 4 : (ys_ok<2>() ? 2 : 1));
     static constexpr int LS = N >= 128 ? 4 : 512 / N;
     static void xinv3(const void* U, void* W, const void* tw, hipStream_t s) {
-        hipLaunchKernelGGL((k_xplain<R, N, TS, +1, 3>), dim3(x_groups<TS>()), dim3(G * TS), 0, s,
+        hipLaunchKernelGGL((k_xplain<R, N, TS, +1, 3>), dim3(x_groups<TS>()), dim3(GX * TS), 0, s,
                            (const C*)U, (C*)W, (const C*)tw);
     }
     static void xfwd3(const void* W, void* U, const void* tw, hipStream_t s) {
-        hipLaunchKernelGGL((k_xplain<R, N, TS, -1, 3>), dim3(x_groups<TS>()), dim3(G * TS), 0, s,
+        hipLaunchKernelGGL((k_xplain<R, N, TS, -1, 3>), dim3(x_groups<TS>()), dim3(GX * TS), 0, s,
                            (const C*)W, (C*)U, (const C*)tw);
     }
     static void yinv3(void* W, const void* tw, hipStream_t s) { ypass<YS, +1, 3>(W, tw, Batch{1, 0, 0}, s); }
@@ -192,7 +195,7 @@ template <typename R, int N> struct Impl {
     // index of the widest variant of pass p not wider than w whose
     // workgroup has at most MAXT threads
     static int pick(const Ops& o, int p, int w) {
-        const int per_line = (p == P_YINV6 || p == P_YFWD3) ? GY : G;
+        const int per_line = (p == P_YINV6 || p == P_YFWD3) ? GY : (p == P_ZCROSS ? G : GX);
         int best = 0;
         for (int v = 0; v < o.nvar[p]; ++v)
             if (o.width[p][v] <= w && per_line * o.width[p][v] <= MAXT) best = v;
@@ -209,8 +212,9 @@ template <typename R, int N> struct Impl {
         add_z<1>(o); add_z<2>(o); add_z<4>(o); add_z<8>(o);
         add_z<16>(o); add_z<32>(o); add_z<64>(o); add_z<128>(o);
         // defaults: 128-byte row segments in the x and y passes, four z lines
-        // per workgroup (the fastest measured on MI355X at 256^3 and 512^3);
-        // for small N, at least one full 64-lane wave per workgroup
+        // per workgroup (two for N = 1024), the fastest measured on MI355X at
+        // 256^3, 512^3 and 1024^3; for small N, at least one full 64-lane
+        // wave per workgroup
         const int wave = 64 / G;
         const int xw = std::max((int)(128 / CB), wave), yw = xw;
         o.def[P_XINV] = pick(o, P_XINV, xw);
@@ -218,7 +222,7 @@ template <typename R, int N> struct Impl {
         o.def[P_XSTAGE] = pick(o, P_XSTAGE, xw);
         o.def[P_YINV6] = pick(o, P_YINV6, yw);
         o.def[P_YFWD3] = pick(o, P_YFWD3, yw);
-        o.def[P_ZCROSS] = pick(o, P_ZCROSS, std::max(4, wave));
+        o.def[P_ZCROSS] = pick(o, P_ZCROSS, std::max(N >= 1024 ? 2 : 4, wave));
         o.xinv3 = &xinv3;
         o.yinv3 = &yinv3;
         o.yfwd3s = &yfwd3s;

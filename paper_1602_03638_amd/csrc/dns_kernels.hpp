@@ -59,7 +59,7 @@ template <typename R, int N, bool NYQ> struct XCol {
 template <typename R, int N, bool NYQ>
 struct XAddr {
     using C = cx<R>;
-    static constexpr int G = N / 8;
+    static constexpr int G = N / x_elems<R>(N);
     static constexpr unsigned RS = XCol<R, N, NYQ>::RS;
     static constexpr size_t BLOCK = NYQ ? Lay<R, N>::MAIN : 0;   // element offset of the block
     unsigned tb;                                                  // byte offset of (column, row g)
@@ -97,7 +97,7 @@ template <int N, int T> constexpr int x_main_tiles() { return (N * (N / 2)) / T;
 template <typename R, int N, int T, bool NYQ>
 __device__ __forceinline__ void xinv_curl_tile(const cx<R>* __restrict__ U, cx<R>* __restrict__ W,
                                                cx<R>* lds, const cx<R>* twl) {
-    constexpr int E = 8, G = N / E;
+    constexpr int E = x_elems<R>(N), G = N / E;
     constexpr size_t FS = Lay<R, N>::FS;
     const int t = threadIdx.x % T, g = threadIdx.x / T;
     const XCol<R, N, NYQ> col(blockIdx.x * T + t);
@@ -147,7 +147,7 @@ __device__ __forceinline__ void xinv_curl_tile(const cx<R>* __restrict__ U, cx<R
 }
 
 template <typename R, int N, int T>
-__global__ __launch_bounds__(N / 8 * T)
+__global__ __launch_bounds__(N / x_elems<R>(N) * T)
 void k_xinv_curl(const cx<R>* __restrict__ U, cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t sst,
                  size_t wst) {
     U += blockIdx.y * sst;
@@ -164,7 +164,7 @@ void k_xinv_curl(const cx<R>* __restrict__ U, cx<R>* __restrict__ W, const cx<R>
 template <typename R, int N, int T, int DIR, int NF, bool NYQ>
 __device__ __forceinline__ void xplain_tile(const cx<R>* __restrict__ S, cx<R>* __restrict__ D,
                                             const cx<R>* __restrict__ tw, cx<R>* lds) {
-    constexpr int E = 8, G = N / E;
+    constexpr int E = x_elems<R>(N), G = N / E;
     constexpr size_t FS = Lay<R, N>::FS;
     const int t = threadIdx.x % T, g = threadIdx.x / T;
     const XCol<R, N, NYQ> col(blockIdx.x * T + t);
@@ -182,7 +182,7 @@ __device__ __forceinline__ void xplain_tile(const cx<R>* __restrict__ S, cx<R>* 
 }
 
 template <typename R, int N, int T, int DIR, int NF>
-__global__ __launch_bounds__(N / 8 * T)
+__global__ __launch_bounds__(N / x_elems<R>(N) * T)
 void k_xplain(const cx<R>* __restrict__ S, cx<R>* __restrict__ D, const cx<R>* __restrict__ tw) {
     __shared__ cx<R> lds[T * N];
     if ((int)blockIdx.x < x_main_tiles<N, T>()) xplain_tile<R, N, T, DIR, NF, false>(S, D, tw, lds);
@@ -708,8 +708,8 @@ __device__ __forceinline__ void diag_reduce(double (&red)[2][NT], double e_acc, 
 template <typename R, int N, int T, int STAGE, bool NYQ>
 __device__ __forceinline__ void xrhs_tile(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
                                           cx<R>* __restrict__ Us, const StageArgs& sa, cx<R>* lds, const cx<R>* twl,
-                                          double (&red)[2][N / 8 * T]) {
-    constexpr int E = 8, G = N / E;
+                                          double (&red)[2][N / x_elems<R>(N) * T]) {
+    constexpr int E = x_elems<R>(N), G = N / E;
     constexpr int NT = G * T;
     constexpr size_t FS = Lay<R, N>::FS;
     const int t = threadIdx.x % T, g = threadIdx.x / T;
@@ -729,7 +729,7 @@ __device__ __forceinline__ void xrhs_tile(const cx<R>* __restrict__ W, cx<R>* __
 // The RK stage is a template parameter: one kernel per stage gives each
 // its own straight-line code and register allocation.
 template <typename R, int N, int T, int STAGE>
-__global__ __launch_bounds__(N / 8 * T)
+__global__ __launch_bounds__(N / x_elems<R>(N) * T)
 void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
             cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa, size_t sst, size_t wst) {
     W += blockIdx.y * wst;
@@ -738,7 +738,7 @@ void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restri
     Us += blockIdx.y * sst;
     if (sa.diag) sa.diag += 2 * (size_t)gridDim.x * blockIdx.y;
     __shared__ cx<R> lds[T * N];
-    __shared__ double red[2][N / 8 * T];
+    __shared__ double red[2][N / x_elems<R>(N) * T];
     __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
     load_twiddles<R, N>(twl, tw);
     if ((int)blockIdx.x < x_main_tiles<N, T>()) xrhs_tile<R, N, T, STAGE, false>(W, U0, U1, Us, sa, lds, twl, red);
@@ -757,8 +757,8 @@ void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restri
 template <typename R, int N, int T, int STAGE, bool NYQ>
 __device__ __forceinline__ void xstage_tile(cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
                                             cx<R>* __restrict__ Us, const StageArgs& sa, cx<R>* lds,
-                                            const cx<R>* twl, double (&red)[2][N / 8 * T]) {
-    constexpr int E = 8, G = N / E;
+                                            const cx<R>* twl, double (&red)[2][N / x_elems<R>(N) * T]) {
+    constexpr int E = x_elems<R>(N), G = N / E;
     constexpr int NT = G * T;
     constexpr size_t FS = Lay<R, N>::FS;
     const int t = threadIdx.x % T, g = threadIdx.x / T;
@@ -807,7 +807,7 @@ __device__ __forceinline__ void xstage_tile(cx<R>* __restrict__ W, cx<R>* __rest
 }
 
 template <typename R, int N, int T, int STAGE>
-__global__ __launch_bounds__(N / 8 * T)
+__global__ __launch_bounds__(N / x_elems<R>(N) * T)
 void k_xstage(cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
               cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa, size_t sst, size_t wst) {
     W += blockIdx.y * wst;
@@ -816,7 +816,7 @@ void k_xstage(cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__
     Us += blockIdx.y * sst;
     if (sa.diag) sa.diag += 2 * (size_t)gridDim.x * blockIdx.y;
     __shared__ cx<R> lds[T * N];
-    __shared__ double red[2][N / 8 * T];
+    __shared__ double red[2][N / x_elems<R>(N) * T];
     __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
     load_twiddles<R, N>(twl, tw);
     if ((int)blockIdx.x < x_main_tiles<N, T>()) xstage_tile<R, N, T, STAGE, false>(W, U0, U1, Us, sa, lds, twl, red);
