@@ -16,6 +16,6 @@ is pinned by its invariants and by published SplitMix64 outputs.
 """
 from .spectral import (  # noqa: F401
     wavenumbers, dealias_mask, dft_matrix, dft3, dft3_mode, idft3, curl_hat, cross,
-    rhs, rk4_step, energy, enstrophy, energy_physical, divergence_max,
+    rhs, rk4_step, euler_step, energy, enstrophy, energy_physical, divergence_max,
     Solver,
 )

@@ -264,6 +264,12 @@ def rk4_step(uh, nu, dt, mesh, mask):
     return U1
 
 
+def euler_step(uh, nu, dt, mesh, mask):
+    """One forward Euler step as in the main loop of the Sec. 3.1 listing:
+    u_hat += computeRHS * dt."""
+    return uh + rhs(uh, nu, mesh, mask) * dt
+
+
 # ----------------------------------------------------------------------------
 # Diagnostics (Appendix: energy reduce; Sec. 4.2: energy and vorticity)
 # ----------------------------------------------------------------------------
@@ -307,14 +313,17 @@ def divergence_max(uh):
 
 
 class Solver:
-    """Holds u_hat and advances it with rk4_step; mirrors the C ABI calls.
+    """Holds u_hat and advances it with rk4_step (or euler_step); mirrors the
+    C ABI calls.
 
-    Solver(N, nu, dt, rule).set_velocity(u) / set_spectral(uh); step(n);
-    energy(); enstrophy(); get_velocity(); get_spectral().
+    Solver(N, nu, dt, rule, integrator).set_velocity(u) / set_spectral(uh);
+    step(n); energy(); enstrophy(); get_velocity(); get_spectral().
+    integrator: "rk4" (Appendix solver, default) or "euler" (Sec. 3.1 loop).
     """
 
-    def __init__(self, N, nu, dt, rule="text"):
+    def __init__(self, N, nu, dt, rule="text", integrator="rk4"):
         self.N, self.nu, self.dt = int(N), float(nu), float(dt)
+        self._step = {"rk4": rk4_step, "euler": euler_step}[integrator]
         self.mesh = wavenumber_mesh(self.N)
         self.mask = dealias_mask(self.N, rule)
         self.uh = None
@@ -330,7 +339,7 @@ class Solver:
 
     def step(self, n=1, callback=None):
         for _ in range(int(n)):
-            self.uh = rk4_step(self.uh, self.nu, self.dt, self.mesh, self.mask)
+            self.uh = self._step(self.uh, self.nu, self.dt, self.mesh, self.mask)
             self.steps += 1
             if callback is not None:
                 callback(self)

@@ -30,12 +30,15 @@ TOL = {
     "tg_initial_tendency": 1e-14,
     "tg_initial_diagnostics": 1e-15,
     "rk4_decay": 1e-14,
+    "euler_decay": 1e-14,
     "masked_linear": 1e-14,
     "divergence": 1e-13,
     "energy_budget": 1e-7,
     "appendix": 5e-13,
     "rk4_order_lo": 14.0,
     "rk4_order_hi": 18.0,
+    "euler_order_lo": 1.8,
+    "euler_order_hi": 2.2,
 }
 
 
@@ -204,6 +207,33 @@ def rk4_decay_error(N=16, nu=0.01, dt=0.01, steps=10):
     return max(errs)
 
 
+def euler_decay_error(N=16, nu=0.01, dt=0.01, steps=10):
+    """Forward Euler on nonlinearity-free flows multiplies the amplitude by
+    1 + z per step, z = -nu |k|^2 dt, so E_n / E_0 = (1 + z)^(2n)."""
+    errs = []
+    for field, k2 in ((workloads.abc_flow(N, 1.0, 0.7, 0.4), 1.0), (workloads.taylor_green_2d(N), 2.0)):
+        s = spectral.Solver(N, nu, dt, integrator="euler").set_velocity(field)
+        e0 = s.energy()
+        s.step(steps)
+        g = (1 - nu * k2 * dt) ** (2 * steps)
+        errs.append(abs(s.energy() / e0 - g) / g)
+    return max(errs)
+
+
+def euler_order_ratio(N=16, nu=0.05, T=0.05, seed=8):
+    """Self-convergence of forward Euler: error(dt) / error(dt/2) ~ 2, against
+    an RK4 run (whose error is negligible at this dt) on a nonlinear flow."""
+    uh0 = ic.random_isotropic(N, seed, k0=3.0)
+    ref = spectral.Solver(N, nu, T / 16).set_spectral(uh0).step(16).uh
+
+    def run(n):
+        return spectral.Solver(N, nu, T / n, integrator="euler").set_spectral(uh0).step(n).uh
+
+    e1 = np.linalg.norm(run(8) - ref)
+    e2 = np.linalg.norm(run(16) - ref)
+    return float(e1 / e2)
+
+
 def masked_linear_error(N=16, nu=0.02, seed=3):
     """Outside the dealias mask the nonlinear term is removed, so there
     RHS = -nu |k|^2 u_hat exactly; inside, RHS + nu |k|^2 u_hat is
@@ -281,6 +311,7 @@ FAST_PINS = {
     "tg_initial_tendency": tg_initial_tendency_error,
     "tg_initial_diagnostics": tg_initial_diagnostics_error,
     "rk4_decay": rk4_decay_error,
+    "euler_decay": euler_decay_error,
     "masked_linear": masked_linear_error,
     "divergence": divergence_error,
     "energy_budget": energy_budget_error,
@@ -301,4 +332,7 @@ def fast_pin_failures():
     r = rk4_order_ratio()
     if not (TOL["rk4_order_lo"] <= r <= TOL["rk4_order_hi"]):
         bad.append("rk4_order")
+    r = euler_order_ratio()
+    if not (TOL["euler_order_lo"] <= r <= TOL["euler_order_hi"]):
+        bad.append("euler_order")
     return bad

@@ -1,7 +1,7 @@
 """Plant plausible mistakes in the CPU oracle and check that the pins catch
 each one: evidence that the pins constrain every part of the oracle
 (transforms, curl, cross product, mask, projection, viscous term, RK4,
-diagnostics).  Mistakes are planted on the CPU only, by monkeypatching."""
+forward Euler, diagnostics).  Mistakes are planted on the CPU only, by monkeypatching."""
 import numpy as np
 import pytest
 
@@ -124,6 +124,13 @@ def _rk4_wrong_b(uh, nu, dt, mesh, mask):
 
 
 MUTATIONS["rk4_stage_offset"] = ("rk4_step", _rk4_wrong_b)
+
+
+def _euler_half_step(uh, nu, dt, mesh, mask):
+    return uh + spectral.rhs(uh, nu, mesh, mask) * (0.5 * dt)
+
+
+MUTATIONS["euler_half_step"] = ("euler_step", _euler_half_step)
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))

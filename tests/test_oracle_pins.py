@@ -21,6 +21,11 @@ def test_rk4_fourth_order():
     assert pins.TOL["rk4_order_lo"] <= r <= pins.TOL["rk4_order_hi"], r
 
 
+def test_euler_first_order():
+    r = pins.euler_order_ratio()
+    assert pins.TOL["euler_order_lo"] <= r <= pins.TOL["euler_order_hi"], r
+
+
 @pytest.mark.slow
 def test_appendix_worked_example():
     """Appendix TG solver, N = 128, 10 steps: final energy as printed."""
