@@ -65,6 +65,10 @@ typedef enum dns_dtype { DNS_FP64 = 0, DNS_FP32 = 1 } dns_dtype;
  * (APPENDIX) on all three axes. */
 typedef enum dns_dealias { DNS_DEALIAS_TEXT = 0, DNS_DEALIAS_APPENDIX = 1 } dns_dealias;
 
+/* Time integrator: classic RK4 (Appendix solver; default) or forward Euler,
+ * u_hat += RHS(u_hat) dt (the main loop of the Sec. 3.1 listing). */
+typedef enum dns_integrator { DNS_RK4 = 0, DNS_EULER = 1 } dns_integrator;
+
 typedef struct dns_opts {
     int dealias;      /* dns_dealias; default DNS_DEALIAS_TEXT */
     int diag_every;   /* record E and Omega after every k-th step into the
@@ -77,6 +81,8 @@ typedef struct dns_opts {
                          stage's inverse x pass (16 kernels per step, default);
                          0 = unfused schedule (20 kernels per step).  Both give
                          bitwise identical results. */
+    int integrator;   /* dns_integrator; default DNS_RK4.  A forward Euler
+                         step is one stage (4 kernels fused, 5 unfused). */
 } dns_opts;
 
 typedef struct dns_ctx dns_t;

@@ -176,7 +176,7 @@ const double RK4_B[3] = {0.5, 0.5, 1.0};
 dns::StageArgs stage_args(const dns_t* c, int stage, double* diag) {
     dns::StageArgs a;
     a.nu = c->nu;
-    a.ca = stage == 3 ? RK4_A[3] * c->dt : 0.0;
+    a.ca = stage == 3 ? RK4_A[3] * c->dt : (stage == 4 ? c->dt : 0.0);
     a.cb = (stage >= 0 && stage < 3) ? RK4_B[stage] * c->dt : 0.0;
     a.stage = stage;
     a.mask_lim = c->mask_lim;
@@ -185,6 +185,12 @@ dns::StageArgs stage_args(const dns_t* c, int stage, double* diag) {
 }
 
 double inv_norm(int N) { return 1.0 / (2.0 * std::pow((double)N, 6)); }
+
+// Stages of one time step: the four RK4 stages 0..3 (Appendix solver), or
+// the single forward Euler stage 4 (Sec. 3.1 main loop).
+int step_stages(const dns_t* c) { return c->opts.integrator == DNS_EULER ? 1 : 4; }
+int stage_id(const dns_t* c, int i) { return c->opts.integrator == DNS_EULER ? 4 : i; }
+int last_stage(const dns_t* c) { return stage_id(c, step_stages(c) - 1); }
 
 int diag_groups(const dns_t* c) {
     return c->opts.fuse ? c->ops->xstage_groups[c->sel[dns::P_XSTAGE]] : c->ops->xrhs_groups[c->sel[dns::P_XRHS]];
@@ -199,7 +205,13 @@ void launch_pass(dns_t* c, int pass, int variant, int stage, double* diag, hipSt
     const dns::Batch b = member < 0 ? c->batch() : dns::Batch{1, 0, 0};
     double* dg = diag ? diag + (size_t)2 * diag_groups(c) * m : nullptr;
     switch (pass) {
-        case dns::P_XINV: o->xinv[variant](stage <= 0 ? c->U0(m) : c->Us(m), c->W(m), c->tw, b, s); break;
+        case dns::P_XINV: {
+            // the stage's velocity: U0 at RK4 stage 0, for the RHS alone and
+            // for the Euler step; the stage velocity Us at RK4 stages 1..3
+            const bool from_u0 = stage <= 0 || stage == 4;
+            o->xinv[variant](from_u0 ? c->U0(m) : c->Us(m), c->W(m), c->tw, b, s);
+            break;
+        }
         case dns::P_YINV6: o->yinv6[variant](c->W(m), c->tw, b, s); break;
         case dns::P_ZCROSS: o->zcross[variant](c->W(m), c->tw, b, s); break;
         case dns::P_YFWD3: o->yfwd3[variant](c->W(m), c->tw, b, s); break;
@@ -218,7 +230,7 @@ void launch_pass(dns_t* c, int pass, int variant, int stage, double* diag, hipSt
 // Unfused stage: inverse x (+curl), inverse y, z, forward y, RHS + RK4.
 void enqueue_stage(dns_t* c, int stage, bool with_diag, hipStream_t s, int member = -1) {
     for (int p = dns::P_XINV; p <= dns::P_XRHS; ++p)
-        launch_pass(c, p, c->sel[p], stage, (p == dns::P_XRHS && stage == 3 && with_diag) ? c->part : nullptr, s,
+        launch_pass(c, p, c->sel[p], stage, (p == dns::P_XRHS && stage == last_stage(c) && with_diag) ? c->part : nullptr, s,
                     member);
 }
 
@@ -236,13 +248,14 @@ void enqueue_diag_final(dns_t* c, hipStream_t s, int member) {
 // stage's inverse x pass, so a step is 16 kernels.  Unfused: 20 kernels.
 void enqueue_step(dns_t* c, bool with_diag, hipStream_t s, int member = -1) {
     if (c->opts.fuse) {
-        for (int st = 0; st < 4; ++st) {
+        for (int i = 0; i < step_stages(c); ++i) {
+            const int st = stage_id(c, i);
             for (int p = dns::P_YINV6; p <= dns::P_YFWD3; ++p) launch_pass(c, p, c->sel[p], st, nullptr, s, member);
-            launch_pass(c, dns::P_XSTAGE, c->sel[dns::P_XSTAGE], st, (st == 3 && with_diag) ? c->part : nullptr, s,
-                        member);
+            launch_pass(c, dns::P_XSTAGE, c->sel[dns::P_XSTAGE], st,
+                        (st == last_stage(c) && with_diag) ? c->part : nullptr, s, member);
         }
     } else {
-        for (int st = 0; st < 4; ++st) enqueue_stage(c, st, with_diag, s, member);
+        for (int i = 0; i < step_stages(c); ++i) enqueue_stage(c, stage_id(c, i), with_diag, s, member);
     }
     if (with_diag) enqueue_diag_final(c, s, member);
 }
@@ -314,7 +327,8 @@ int check_args(int N, double nu, double dt, int dtype, const dns_opts& o) {
         (dtype != DNS_FP64 && dtype != DNS_FP32))
         return DNS_E_INVAL;
     if ((o.dealias != DNS_DEALIAS_TEXT && o.dealias != DNS_DEALIAS_APPENDIX) || o.diag_every < 0 ||
-        o.history_cap < 0 || (o.fuse != 0 && o.fuse != 1))
+        o.history_cap < 0 || (o.fuse != 0 && o.fuse != 1) ||
+        (o.integrator != DNS_RK4 && o.integrator != DNS_EULER))
         return DNS_E_INVAL;
     return DNS_OK;
 }
@@ -518,6 +532,7 @@ void dns_default_opts(dns_opts* o) {
     o->use_graph = 1;
     o->autotune = 0;
     o->fuse = 1;
+    o->integrator = DNS_RK4;
 }
 
 size_t dns_state_bytes(int N, int dtype) {
@@ -715,16 +730,16 @@ int dns_profile_step(dns_t* c, int nsteps, float* ms, const char** names, int ma
     for (int n = 0; n < nsteps; ++n) {
         if (c->opts.fuse) {
             if (!c->w_ready && (r = timed(dns::P_XINV, 0))) return r;
-            for (int st = 0; st < 4; ++st) {
+            for (int i = 0; i < step_stages(c); ++i) {
                 for (int k = dns::P_YINV6; k <= dns::P_YFWD3; ++k)
-                    if ((r = timed(k, st))) return r;
-                if ((r = timed(dns::P_XSTAGE, st))) return r;
+                    if ((r = timed(k, stage_id(c, i)))) return r;
+                if ((r = timed(dns::P_XSTAGE, stage_id(c, i)))) return r;
             }
             c->w_ready = true;
         } else {
-            for (int st = 0; st < 4; ++st)
+            for (int i = 0; i < step_stages(c); ++i)
                 for (int k = dns::P_XINV; k <= dns::P_XRHS; ++k)
-                    if ((r = timed(k, st))) return r;
+                    if ((r = timed(k, stage_id(c, i)))) return r;
         }
         c->steps += 1;
     }

@@ -77,6 +77,7 @@ template <typename R, int N> struct Impl {
             case 1: xrhs_st<T, 1>(W, U0, U1, Us, tw, a, b, s); break;
             case 2: xrhs_st<T, 2>(W, U0, U1, Us, tw, a, b, s); break;
             case 3: xrhs_st<T, 3>(W, U0, U1, Us, tw, a, b, s); break;
+            case 4: xrhs_st<T, 4>(W, U0, U1, Us, tw, a, b, s); break;
             default: xrhs_st<T, -1>(W, U0, U1, Us, tw, a, b, s); break;
         }
     }
@@ -94,7 +95,8 @@ template <typename R, int N> struct Impl {
             case 0: xstage_st<T, 0>(W, U0, U1, Us, tw, a, b, s); break;
             case 1: xstage_st<T, 1>(W, U0, U1, Us, tw, a, b, s); break;
             case 2: xstage_st<T, 2>(W, U0, U1, Us, tw, a, b, s); break;
-            default: xstage_st<T, 3>(W, U0, U1, Us, tw, a, b, s); break;
+            case 3: xstage_st<T, 3>(W, U0, U1, Us, tw, a, b, s); break;
+            default: xstage_st<T, 4>(W, U0, U1, Us, tw, a, b, s); break;
         }
     }
 

@@ -486,8 +486,11 @@ void k_zc2r(const cx<R>* __restrict__ W, R* __restrict__ u, const cx<R>* __restr
 //   stage 2:  Us = U0 + cb R                                   (u_s = Us)
 //   stage 3:  U0 = (U1 + Us / 3) + ca R                        (u_s = Us)
 //   stage -1: U1 = R (right-hand side only; u_s = U0)
-// with cb = b_s dt (b = 1/2, 1/2, 1) and ca = dt/6.
-// At stage 3 with diag != nullptr, each workgroup also writes partial sums
+// with cb = b_s dt (b = 1/2, 1/2, 1) and ca = dt/6.  Stage 4 is the whole
+// forward Euler step of the Sec. 3.1 main loop, u_hat += R dt:
+//   stage 4:  U0 = U0 + ca R, ca = dt                          (u_s = U0)
+// At the last stage of a step (3, or 4 for Euler) with diag != nullptr,
+// each workgroup also writes partial sums
 // of w |u_hat|^2 and w |k x u_hat|^2 of the new state (w = 1 on the kz = 0
 // and kz = N/2 planes, 2 elsewhere) to diag[2 blockIdx], diag[2 blockIdx + 1].
 // ---------------------------------------------------------------------------
@@ -562,7 +565,7 @@ __device__ __forceinline__ void rk_apply_elementwise(cx<R> (&nh)[3][E], const XC
         cx<R> n[3] = {nh[0][m], nh[1][m], nh[2][m]};
         project_mode<R>(n[0], n[1], n[2], kx, ky, kz, keep);
         const R visc = nu * (R)(kx * kx + ky * ky + kz * kz);
-        const cx<R>* ps = (STAGE <= 0) ? U0 : Us;
+        const cx<R>* ps = (STAGE <= 0 || STAGE == 4) ? U0 : Us;
         cx<R> us[3], other[3];
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
@@ -587,13 +590,16 @@ __device__ __forceinline__ void rk_apply_elementwise(cx<R> (&nh)[3][E], const XC
             } else if constexpr (STAGE == 2) {
                 v = cadd<R>(other[f], cscale<R>(r, cb));
                 A(Us + f * FS, m) = v;
-            } else {
+            } else if constexpr (STAGE == 3) {
                 v = rk_final<R>(other[f], us[f], r, ca);
+                A(U0 + f * FS, m) = v;
+            } else {
+                v = cadd<R>(us[f], cscale<R>(r, ca));
                 A(U0 + f * FS, m) = v;
             }
             nh[f][m] = v;
         }
-        if constexpr (STAGE == 3) {
+        if constexpr (STAGE >= 3) {
             if (sa.diag != nullptr) diag_mode<R, N>(nh[0][m], nh[1][m], nh[2][m], kx, ky, kz, e_acc, w_acc);
         }
         asm volatile("" ::: "memory");
@@ -627,15 +633,16 @@ __device__ __forceinline__ void rk_apply_batched(cx<R> (&nh)[3][E], const XCol<R
         project_mode<R>(nh[0][m], nh[1][m], nh[2][m], kx, ky, kz, keep);
         visc[m] = nu * (R)(kx * kx + ky * ky + kz * kz);
     }
-    const cx<R>* ps = (STAGE <= 0) ? U0 : Us;               // u_s
+    const cx<R>* ps = (STAGE <= 0 || STAGE == 4) ? U0 : Us;  // u_s
     const cx<R>* po = (STAGE == 3) ? U1 : U0;                // second array of stages 1..3
+    constexpr bool TWO = STAGE >= 1 && STAGE <= 3;
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
         cx<R> us[E], o[E];
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             us[m] = A(ps + f * FS, m);
-            if constexpr (STAGE > 0) o[m] = A(po + f * FS, m);
+            if constexpr (TWO) o[m] = A(po + f * FS, m);
         }
 #pragma unroll
         for (int m = 0; m < E; ++m) {
@@ -655,15 +662,18 @@ __device__ __forceinline__ void rk_apply_batched(cx<R> (&nh)[3][E], const XCol<R
             } else if constexpr (STAGE == 2) {
                 v = cadd<R>(o[m], cscale<R>(r, cb));
                 A(Us + f * FS, m) = v;
-            } else {
+            } else if constexpr (STAGE == 3) {
                 v = rk_final<R>(o[m], us[m], r, ca);
+                A(U0 + f * FS, m) = v;
+            } else {
+                v = cadd<R>(us[m], cscale<R>(r, ca));
                 A(U0 + f * FS, m) = v;
             }
             nh[f][m] = v;
         }
         asm volatile("" ::: "memory");
     }
-    if constexpr (STAGE == 3) {
+    if constexpr (STAGE >= 3) {
         if (sa.diag != nullptr) {
 #pragma unroll
             for (int m = 0; m < E; ++m)
@@ -723,7 +733,7 @@ __device__ __forceinline__ void xrhs_tile(const cx<R>* __restrict__ W, cx<R>* __
     for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true>(nh[f], lds + t, T, twl, g);
     double e_acc = 0.0, w_acc = 0.0;
     rk_apply_stage<R, N, E, STAGE, NYQ, NT>(nh, col, g, U0, U1, Us, sa, e_acc, w_acc);
-    if (STAGE == 3 && sa.diag) diag_reduce<NT>(red, e_acc, w_acc, sa.diag);
+    if (STAGE >= 3 && sa.diag) diag_reduce<NT>(red, e_acc, w_acc, sa.diag);
 }
 
 // The RK stage is a template parameter: one kernel per stage gives each
@@ -775,7 +785,7 @@ __device__ __forceinline__ void xstage_tile(cx<R>* __restrict__ W, cx<R>* __rest
     for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true>(u[f], lt, T, twl, g);
     double e_acc = 0.0, w_acc = 0.0;
     rk_apply_stage<R, N, E, STAGE, NYQ, NT>(u, col, g, U0, U1, Us, sa, e_acc, w_acc);
-    if (STAGE == 3 && sa.diag) diag_reduce<NT>(red, e_acc, w_acc, sa.diag);
+    if (STAGE >= 3 && sa.diag) diag_reduce<NT>(red, e_acc, w_acc, sa.diag);
 
     // curl and inverse x transforms of the next stage's velocity u
     const R ky = (R)col.ky, kz = (R)col.kz;

@@ -245,3 +245,37 @@ def test_fused_schedule_matches_unfused_bitwise(N, dtype):
     b.step(3)
     assert np.array_equal(to_host(a.get_spectral()), to_host(b.get_spectral()))
     assert a.diagnostics() == b.diagnostics()
+
+
+@pytest.mark.parametrize("N", [16, 32])
+def test_forward_euler_against_oracle(N):
+    """Forward Euler (Sec. 3.1 main loop, u_hat += RHS dt), 10 steps of the
+    Taylor-Green field and of a random solenoidal field, FP64: velocity to
+    1e-12 relative L2 and the per-step energy history to 1e-12."""
+    note(f"euler N={N}")
+    nu, dt = 0.01, 0.005
+    for uh0 in (spectral.dft3(workloads.taylor_green(N)), ic.random_isotropic(N, seed=1001)):
+        E_ref = []
+        orc = spectral.Solver(N, nu, dt, integrator="euler").set_spectral(uh0).step(
+            10, callback=lambda o: E_ref.append(o.energy()))
+        s = _solver(N, nu, dt, integrator="euler", diag_every=1).set_spectral(to_dev(uh0, "f64")).step(10)
+        assert spectral_rel_l2(to_host(s.get_spectral()), orc.uh) <= TOL_STEP10
+        E, _ = s.history()
+        assert np.max(np.abs(np.array(E) - E_ref) / np.array(E_ref)) <= 1e-12
+        s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_forward_euler_fused_matches_unfused_and_fp32(dtype):
+    """The fused Euler step (RHS pass + next step's inverse x pass) gives the
+    unfused schedule's bits; FP32 energy within 1e-5 of the oracle."""
+    note(f"euler fused vs unfused {dtype}")
+    N, nu, dt = 32, 0.01, 0.005
+    uh0 = ic.random_isotropic(N, seed=1002)
+    a = _solver(N, nu, dt, dtype=dtype, integrator="euler", fuse=True).set_spectral(to_dev(uh0, dtype)).step(4)
+    b = _solver(N, nu, dt, dtype=dtype, integrator="euler", fuse=False).set_spectral(to_dev(uh0, dtype)).step(4)
+    assert np.array_equal(to_host(a.get_spectral()), to_host(b.get_spectral()))
+    if dtype == "f32":
+        orc = spectral.Solver(N, nu, dt, integrator="euler").set_spectral(
+            uh0.astype(np.complex64).astype(np.complex128)).step(4)
+        assert abs(a.energy() - orc.energy()) / orc.energy() <= 1e-5
