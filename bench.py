@@ -150,16 +150,18 @@ ISO_N, ISO_NU, ISO_DT, ISO_STEPS, ISO_SEED = 1024, 1e-3, 5e-4, 20, 1
 
 
 def run_isotropic(N=ISO_N, steps=ISO_STEPS, warmup=2):
-    """ms per RK4 step of the random isotropic field in FP32 and FP64, and
-    the FP32 errors against the FP64 path after `steps` steps (relative
-    energy and enstrophy differences, relative L2 of the spectral velocity).
-    Both start from the same FP64-generated spectrum (FP32 takes it rounded),
-    so the difference is the FP32 arithmetic alone."""
+    """ms per RK4 step of the random isotropic field in FP32 (plain Stockham
+    y passes, and with the radix-16 stage of the y passes on FP16 matrix
+    cores) and in FP64, and each FP32 run's errors against the FP64 path
+    after `steps` steps (relative energy and enstrophy differences, relative
+    L2 of the spectral velocity).  All start from the same FP64-generated
+    spectrum (FP32 takes it rounded), so the differences are the FP32
+    arithmetic alone.  Mean kernel times come from one extra profiled step."""
     import torch
     from paper_1602_03638_amd import Solver
 
-    def run(dtype, uh0):
-        s = Solver(N, ISO_NU, ISO_DT, dtype=dtype)
+    def run(dtype, uh0, **kw):
+        s = Solver(N, ISO_NU, ISO_DT, dtype=dtype, **kw)
         s.set_spectral(uh0.to(s.complex).contiguous())
         s.step(warmup)
         s.synchronize()
@@ -173,8 +175,10 @@ def run_isotropic(N=ISO_N, steps=ISO_STEPS, warmup=2):
         ms = (time.perf_counter() - t0) * 1e3 / steps
         E, W = s.diagnostics()
         out = s.get_spectral()
+        s.set_spectral(uh0.to(s.complex).contiguous())
+        kern = {k: round(v, 3) for k, v in s.profile_step(1).items()}
         s.close()
-        return ms, E, W, out
+        return ms, E, W, out, kern
 
     s = Solver(N, ISO_NU, ISO_DT, dtype="f64")
     s.init_random(ISO_SEED, k0=4.0, energy=0.5)
@@ -182,26 +186,40 @@ def run_isotropic(N=ISO_N, steps=ISO_STEPS, warmup=2):
     uh0 = s.get_spectral()
     s.close()
     torch.cuda.empty_cache()
-    ms32, E32, W32, u32 = run("f32", uh0)
+    ms32, E32, W32, u32, k32 = run("f32", uh0)
     u32 = u32.cpu()
     torch.cuda.empty_cache()
-    ms64, E64, W64, u64 = run("f64", uh0)
+    msm, Em, Wm, um, km = run("f32", uh0, mfma_dft=True)
+    um = um.cpu()
+    torch.cuda.empty_cache()
+    ms64, E64, W64, u64, k64 = run("f64", uh0)
     del uh0
     torch.cuda.empty_cache()
-    diff = (u32.to(u64.device).to(torch.complex128) - u64)
-    rel_l2 = float(torch.linalg.vector_norm(diff) / torch.linalg.vector_norm(u64))
-    del diff, u64, u32
+    norm64 = torch.linalg.vector_norm(u64)
+
+    def errors(E, W, u):
+        d = u.to(u64.device).to(torch.complex128) - u64
+        out = {"rel_energy": abs(E - E64) / E64, "rel_enstrophy": abs(W - W64) / W64,
+               "rel_l2_spectral_velocity": float(torch.linalg.vector_norm(d) / norm64)}
+        del d
+        return out
+
+    err32, errm = errors(E32, W32, u32), errors(Em, Wm, um)
+    del u64, u32, um
     torch.cuda.empty_cache()
     C = field_bytes(N, "f32")
     return {"workload": f"random_isotropic_{N}_rk4", "N": N, "nu": ISO_NU, "dt": ISO_DT, "steps": steps,
             "seed": ISO_SEED, "k0": 4.0, "E0": E0, "Omega0": W0,
             "fp32": {"ms_per_step": round(ms32, 3), "model_GBps": round(FIELDS_PER_STEP * C / (ms32 * 1e-3) / 1e9, 1),
-                     "energy": E32, "enstrophy": W32},
+                     "energy": E32, "enstrophy": W32, "kernels_ms": k32},
+            "fp32_mfma_dft": {"ms_per_step": round(msm, 3),
+                              "model_GBps": round(FIELDS_PER_STEP * C / (msm * 1e-3) / 1e9, 1),
+                              "energy": Em, "enstrophy": Wm, "kernels_ms": km,
+                              "y_stage": "radix-16 DFT on FP16 matrix cores (hi/lo split, FP32 accumulation)"},
             "fp64": {"ms_per_step": round(ms64, 3),
                      "model_GBps": round(FIELDS_PER_STEP * 2 * C / (ms64 * 1e-3) / 1e9, 1),
-                     "energy": E64, "enstrophy": W64},
-            "fp32_vs_fp64": {"rel_energy": abs(E32 - E64) / E64, "rel_enstrophy": abs(W32 - W64) / W64,
-                             "rel_l2_spectral_velocity": rel_l2}}
+                     "energy": E64, "enstrophy": W64, "kernels_ms": k64},
+            "fp32_vs_fp64": err32, "fp32_mfma_dft_vs_fp64": errm}
 
 
 # The paper's FFT benchmark (Sec. 4.3): one forward and one inverse 3D real
@@ -359,6 +377,7 @@ def main(argv=None):
     ap.add_argument("--ensemble-only", action="store_true")
     ap.add_argument("--no-isotropic", action="store_true", help="skip the 1024^3 random isotropic leg")
     ap.add_argument("--isotropic-only", action="store_true")
+    ap.add_argument("--iso-steps", type=int, default=ISO_STEPS, help="timed steps of the 1024^3 leg")
     ap.add_argument("--no-fft", action="store_true", help="skip the FFT-only leg")
     ap.add_argument("--fft-only", action="store_true")
     ap.add_argument("--ens-steps", type=int, default=100)
@@ -383,7 +402,7 @@ def main(argv=None):
         print(json.dumps({"fft": run_fft()}), flush=True)
         return 0
     if a.isotropic_only:
-        print(json.dumps({"random_isotropic": run_isotropic()}), flush=True)
+        print(json.dumps({"random_isotropic": run_isotropic(steps=a.iso_steps)}), flush=True)
         return 0
     if a.ensemble_only:
         ens = run_ensemble(a.ens_steps, a.warmup, a.ens_per_sim_steps, not a.ens_default_tiles)
@@ -408,7 +427,7 @@ def main(argv=None):
                 "bytes_per_launch": FIELDS_PER_LAUNCH[dom] * C,
                 "mean_launch_ms": f64["kernels_ms"][dom]}
     ens = None if a.no_ensemble else run_ensemble(a.ens_steps, a.warmup, a.ens_per_sim_steps, not a.ens_default_tiles)
-    iso = None if a.no_isotropic else run_isotropic()
+    iso = None if a.no_isotropic else run_isotropic(steps=a.iso_steps)
     fft = None if a.no_fft else run_fft()
     cpu = None if a.no_cpu_baseline else cpu_baseline(a.N)
     line = {

@@ -83,6 +83,13 @@ typedef struct dns_opts {
                          bitwise identical results. */
     int integrator;   /* dns_integrator; default DNS_RK4.  A forward Euler
                          step is one stage (4 kernels fused, 5 unfused). */
+    int mfma_dft;     /* 1 = the y passes of the step take one radix-16 DFT
+                         stage on FP16 matrix cores with high/low split
+                         operands and FP32 accumulation (four-step split
+                         N = 16 (N/16); the rest in FP32).  FP32 contexts with
+                         N >= 64 only (DNS_E_UNSUPPORTED otherwise); results
+                         differ from the plain FP32 path at the 1e-6 level.
+                         Default 0. */
 } dns_opts;
 
 typedef struct dns_ctx dns_t;

@@ -39,7 +39,7 @@ class DnsError(RuntimeError):
 class dns_opts(ctypes.Structure):
     _fields_ = [("dealias", ctypes.c_int), ("diag_every", ctypes.c_int),
                 ("history_cap", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("fuse", ctypes.c_int), ("integrator", ctypes.c_int)]
+                ("fuse", ctypes.c_int), ("integrator", ctypes.c_int), ("mfma_dft", ctypes.c_int)]
 
 
 _lib = None
@@ -144,15 +144,16 @@ def state_bytes(N, dtype):
 class Solver:
     """One pseudo-spectral DNS context on the current GPU (see include/dns.h).
 
-    dtype: "f64" or "f32"; integrator: "rk4" (default) or "euler".  Tensors
-    passed in must be contiguous CUDA tensors:
+    dtype: "f64" or "f32"; integrator: "rk4" (default) or "euler"; mfma_dft:
+    y passes with the radix-16 stage on FP16 matrix cores (FP32, N >= 64).
+    Tensors passed in must be contiguous CUDA tensors:
     physical (3, N, N, N) float64/float32, spectral (3, N, N, N/2+1)
     complex128/complex64.  All work is ordered on torch's current stream at
     construction time.
     """
 
     def __init__(self, N, nu, dt, dtype="f64", dealias="text", diag_every=0, use_graph=True,
-                 history_cap=4096, stream=None, autotune=False, fuse=True, integrator="rk4"):
+                 history_cap=4096, stream=None, autotune=False, fuse=True, integrator="rk4", mfma_dft=False):
         import torch
         self._torch = torch
         lib = load_library()
@@ -169,6 +170,7 @@ class Solver:
         o.autotune = 1 if autotune else 0
         o.fuse = 1 if fuse else 0
         o.integrator = INTEGRATORS[integrator]
+        o.mfma_dft = 1 if mfma_dft else 0
         self.history_cap = int(history_cap)
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -373,7 +375,7 @@ class Ensemble:
     """
 
     def __init__(self, Ns, nus, dts, dtype="f64", dealias="text", use_graph=True, fuse=True, autotune=False,
-                 integrator="rk4", stream=None):
+                 integrator="rk4", mfma_dft=False, stream=None):
         import torch
         self._torch = torch
         lib = load_library()
@@ -388,6 +390,7 @@ class Ensemble:
         o.fuse = 1 if fuse else 0
         o.autotune = 1 if autotune else 0
         o.integrator = INTEGRATORS[integrator]
+        o.mfma_dft = 1 if mfma_dft else 0
         if stream is None:
             stream = torch.cuda.current_stream()
         h = ctypes.c_void_p()

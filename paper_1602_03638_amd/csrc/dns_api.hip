@@ -20,7 +20,7 @@ namespace dns {
 // formed, evaluated in long double and exact at the multiples of pi/4 where
 // the value is 0, +-1 or +-sqrt(1/2) per component.
 // ---------------------------------------------------------------------------
-static void unit_root(long m, long n, double* re, double* im) {
+void unit_root(long m, long n, double* re, double* im) {
     m %= n;
     if (m < 0) m += n;
     if ((4 * m) % n == 0) {
@@ -115,6 +115,7 @@ struct dns_ctx {
     char* state = nullptr;          // per member: U0 | U1 | Us, three fields each
     char* work = nullptr;           // per member: W, six fields
     void* tw = nullptr;
+    void* mfma_tw = nullptr;        // w_N^j (j < N), then the N/16-point twiddle table (mfma_dft)
     double* part = nullptr;         // diagnostic partials, npart_cap pairs per member
     int npart_cap = 0;
     double* dout = nullptr;         // [member][E, Omega] of the last reduction
@@ -196,6 +197,9 @@ int diag_groups(const dns_t* c) {
     return c->opts.fuse ? c->ops->xstage_groups[c->sel[dns::P_XSTAGE]] : c->ops->xrhs_groups[c->sel[dns::P_XRHS]];
 }
 
+// The N/16-point twiddle table that follows the N unit roots in mfma_tw.
+const void* mfma_tw2(const dns_t* c) { return (const char*)c->mfma_tw + (size_t)c->N * c->cbytes; }
+
 // Launch one pass of stage `stage` for all members (member < 0, one batched
 // launch) or for one member only.  diag: fused diagnostic partials of
 // member 0; member m's sit 2 * groups * m doubles further.
@@ -212,9 +216,19 @@ void launch_pass(dns_t* c, int pass, int variant, int stage, double* diag, hipSt
             o->xinv[variant](from_u0 ? c->U0(m) : c->Us(m), c->W(m), c->tw, b, s);
             break;
         }
-        case dns::P_YINV6: o->yinv6[variant](c->W(m), c->tw, b, s); break;
+        case dns::P_YINV6:
+            if (c->opts.mfma_dft)
+                o->ymfma_inv6(c->W(m), c->tw, c->mfma_tw, mfma_tw2(c), b, s);
+            else
+                o->yinv6[variant](c->W(m), c->tw, b, s);
+            break;
         case dns::P_ZCROSS: o->zcross[variant](c->W(m), c->tw, b, s); break;
-        case dns::P_YFWD3: o->yfwd3[variant](c->W(m), c->tw, b, s); break;
+        case dns::P_YFWD3:
+            if (c->opts.mfma_dft)
+                o->ymfma_fwd3(c->W(m), c->tw, c->mfma_tw, mfma_tw2(c), b, s);
+            else
+                o->yfwd3[variant](c->W(m), c->tw, b, s);
+            break;
         case dns::P_XRHS: {
             const dns::StageArgs a = stage_args(c, stage, dg);
             o->xrhs[variant](c->W(m), c->U0(m), c->U1(m), c->Us(m), c->tw, a, b, s);
@@ -311,6 +325,7 @@ void release(dns_t* c) {
     if (c->state) (void)hipFree(c->state);
     if (c->work) (void)hipFree(c->work);
     if (c->tw) (void)hipFree(c->tw);
+    if (c->mfma_tw) (void)hipFree(c->mfma_tw);
     if (c->part) (void)hipFree(c->part);
     if (c->dout) (void)hipFree(c->dout);
     if (c->hist) (void)hipFree(c->hist);
@@ -328,8 +343,9 @@ int check_args(int N, double nu, double dt, int dtype, const dns_opts& o) {
         return DNS_E_INVAL;
     if ((o.dealias != DNS_DEALIAS_TEXT && o.dealias != DNS_DEALIAS_APPENDIX) || o.diag_every < 0 ||
         o.history_cap < 0 || (o.fuse != 0 && o.fuse != 1) ||
-        (o.integrator != DNS_RK4 && o.integrator != DNS_EULER))
+        (o.integrator != DNS_RK4 && o.integrator != DNS_EULER) || (o.mfma_dft != 0 && o.mfma_dft != 1))
         return DNS_E_INVAL;
+    if (o.mfma_dft && (dtype != DNS_FP32 || N < 64)) return DNS_E_UNSUPPORTED;
     return DNS_OK;
 }
 
@@ -400,6 +416,20 @@ int create_ctx(int N, double nu, double dt, int dtype, const dns_opts& o, hipStr
         e = hipMemcpy(c->tw, twf.data(), (size_t)ntw * c->cbytes, hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) return bail(DNS_E_HIP, "hipMemcpy(tw)", e);
+    if (o.mfma_dft) {
+        // FP32 only (checked by the caller): the unit roots w_N^j and the
+        // twiddle table of the N/16-point transforms, long-double accurate
+        const int n2 = N / 16, ntw2 = dns::tw_size(n2);
+        std::vector<double> roots(2 * (size_t)N + 2 * (size_t)(ntw2 > 0 ? ntw2 : 1), 0.0);
+        for (int j = 0; j < N; ++j) dns::unit_root(j, N, &roots[2 * j], &roots[2 * j + 1]);
+        if (ntw2 > 0) dns::make_twiddles(n2, roots.data() + 2 * (size_t)N);
+        std::vector<float> rf(roots.size());
+        for (size_t i = 0; i < roots.size(); ++i) rf[i] = (float)roots[i];
+        if ((e = hipMalloc(&c->mfma_tw, rf.size() * sizeof(float))) != hipSuccess)
+            return bail(DNS_E_NOMEM, "hipMalloc(mfma_tw)", e);
+        if ((e = hipMemcpy(c->mfma_tw, rf.data(), rf.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+            return bail(DNS_E_HIP, "hipMemcpy(mfma_tw)", e);
+    }
     if ((e = hipMemset(c->state, 0, (size_t)members * 9 * c->fbytes)) != hipSuccess ||
         (e = hipMemset(c->hist_count, 0, sizeof(int) * (size_t)members)) != hipSuccess)
         return bail(DNS_E_HIP, "hipMemset", e);
@@ -533,6 +563,7 @@ void dns_default_opts(dns_opts* o) {
     o->autotune = 0;
     o->fuse = 1;
     o->integrator = DNS_RK4;
+    o->mfma_dft = 0;
 }
 
 size_t dns_state_bytes(int N, int dtype) {
@@ -894,8 +925,10 @@ int dns_ens_create(int count, const int* N, const double* nu, const double* dt, 
     dns_opts o;
     dns_default_opts(&o);
     if (opts) o = *opts;
-    for (int i = 0; i < count; ++i)
-        if (check_args(N[i], nu[i], dt[i], dtype, o)) return DNS_E_INVAL;
+    for (int i = 0; i < count; ++i) {
+        const int r = check_args(N[i], nu[i], dt[i], dtype, o);
+        if (r) return r;
+    }
     dns_ens_t* e = new (std::nothrow) dns_ens();
     if (!e) return DNS_E_NOMEM;
     e->user = (hipStream_t)stream;

@@ -5,7 +5,10 @@
 #include <algorithm>
 #include <cmath>
 
+#include <type_traits>
+
 #include "dns_kernels.hpp"
+#include "dns_mfma.hpp"
 #include "dns_ops.hpp"
 
 namespace dns {
@@ -51,6 +54,13 @@ template <typename R, int N> struct Impl {
     template <int T, int DIR, int NF> static void ypass(void* W, const void* tw, const Batch& b, hipStream_t s) {
         hipLaunchKernelGGL((k_yline<R, N, T, DIR, NF>), dim3(y_tiles<R, N, T>(), b.members), dim3(GY * T), 0, s,
                            (C*)W, (const C*)tw, b.wst);
+    }
+    template <int DIR, int NF>
+    static void ymfma(void* W, const void* tw, const void* roots, const void* tw2, const Batch& b, hipStream_t s) {
+        if constexpr (std::is_same_v<R, float> && N >= 64) {
+            hipLaunchKernelGGL((k_yline_mfma<N, DIR, NF>), dim3(MfmaY<N>::TILES, b.members), dim3(MfmaY<N>::NT), 0, s,
+                               (C*)W, (const C*)tw, (const C*)roots, (const C*)tw2, b.wst);
+        }
     }
     template <int T> static void yinv6(void* W, const void* tw, const Batch& b, hipStream_t s) {
         ypass<T, +1, 6>(W, tw, b, s);
@@ -236,6 +246,10 @@ template <typename R, int N> struct Impl {
         o.ic_physical = &ic_physical;
         o.ic_random = &ic_random;
         o.scale = &scale;
+        if constexpr (std::is_same_v<R, float> && N >= 64) {
+            o.ymfma_inv6 = &ymfma<+1, 6>;
+            o.ymfma_fwd3 = &ymfma<-1, 3>;
+        }
         return o;
     }
     static const Ops* table() {

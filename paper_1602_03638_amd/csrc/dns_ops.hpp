@@ -21,6 +21,10 @@ using YFn = void (*)(void* W, const void* tw, const Batch& b, hipStream_t s);
 using ZFn = void (*)(void* W, const void* tw, const Batch& b, hipStream_t s);
 using XrhsFn = void (*)(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
                         const Batch& b, hipStream_t s);
+// y pass with the radix-16 stage on FP16 matrix cores: roots = w_N^j
+// (j < N), tw2 = twiddle table of the N/16-point transforms
+using YMfmaFn = void (*)(void* W, const void* tw, const void* roots, const void* tw2, const Batch& b,
+                         hipStream_t s);
 
 struct Ops {
     int N;
@@ -40,6 +44,9 @@ struct Ops {
     XrhsFn xstage[MAXV];
     int xrhs_groups[MAXV]; // workgroups of each xrhs variant (= fused diagnostic partials)
     int xstage_groups[MAXV];
+    // y passes with the matrix-core DFT stage (FP32, N >= 64; else nullptr)
+    YMfmaFn ymfma_inv6;
+    YMfmaFn ymfma_fwd3;
     // standalone transforms and utilities (default shapes)
     void (*xinv3)(const void* U, void* W, const void* tw, hipStream_t s);
     void (*yinv3)(void* W, const void* tw, hipStream_t s);

@@ -29,8 +29,8 @@ def test_strerror_covers_status_codes(lib):
 
 def test_default_opts(lib):
     o = dns.default_opts()
-    assert (o.dealias, o.diag_every, o.history_cap, o.use_graph, o.autotune, o.fuse, o.integrator) == \
-        (0, 0, 4096, 1, 0, 1, 0)
+    assert (o.dealias, o.diag_every, o.history_cap, o.use_graph, o.autotune, o.fuse, o.integrator,
+            o.mfma_dft) == (0, 0, 4096, 1, 0, 1, 0, 0)
 
 
 def test_state_bytes(lib):

@@ -1,0 +1,88 @@
+"""The y passes with one radix-16 DFT stage on FP16 matrix cores (split
+high/low operands, FP32 accumulation; dns_opts.mfma_dft) against the FP64
+oracle, and against the plain FP32 path.
+
+Tolerances: a plain FP32 right-hand side agrees with the oracle to about
+1e-6 relative L2 (the FP32 parity tests allow 2e-5); the split products
+keep about 22 bits per term, so the matrix-core stage adds an error of the
+same order, and the same 2e-5 bound applies.  After 10 RK4 steps the
+energy agrees to 1e-5 relative, as for plain FP32.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import note, spectral_rel_l2, to_dev, to_host
+from oracle import ic, spectral
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(N, nu=0.01, dt=0.005, dtype="f32", **kw):
+    from paper_1602_03638_amd import Solver
+    return Solver(N, nu, dt, dtype=dtype, **kw)
+
+
+def _rhs_input(N, seed):
+    uh = ic.random_isotropic(N, seed, k0=3.0)
+    return uh + 0.05 * np.abs(uh).max() * spectral.dft3(workloads.random_physical(N, seed + 1)) / N ** 1.5
+
+
+@pytest.mark.parametrize("N", [64, 128])
+def test_mfma_rhs_against_oracle(N):
+    """One right-hand side (inverse y of 6 fields and forward y of 3 through
+    the matrix-core stage) on a broadband input including Nyquist planes."""
+    note(f"mfma rhs N={N}")
+    nu = 0.0137
+    uh = _rhs_input(N, seed=60 + N)
+    ref = spectral.rhs(uh.astype(np.complex64).astype(np.complex128), nu, spectral.wavenumber_mesh(N),
+                       spectral.dealias_mask(N))
+    got = to_host(_solver(N, nu=nu, mfma_dft=True).set_spectral(to_dev(uh, "f32")).rhs())
+    plain = to_host(_solver(N, nu=nu).set_spectral(to_dev(uh, "f32")).rhs())
+    err, err_plain = spectral_rel_l2(got, ref), spectral_rel_l2(plain, ref)
+    note(f"  rel L2 vs oracle: mfma {err:.2e}, plain fp32 {err_plain:.2e}")
+    assert err <= 2e-5
+
+
+@pytest.mark.parametrize("N", [64, 128])
+def test_mfma_ten_steps_against_oracle(N):
+    """10 RK4 steps of a random solenoidal field: energy and enstrophy to
+    1e-5, velocity to 1e-5 relative L2 against the FP64 oracle."""
+    note(f"mfma 10 steps N={N}")
+    nu, dt = 0.01, 0.005
+    uh0 = ic.random_isotropic(N, seed=1003)
+    orc = spectral.Solver(N, nu, dt).set_spectral(uh0).step(10)
+    s = _solver(N, nu, dt, mfma_dft=True).set_spectral(to_dev(uh0, "f32")).step(10)
+    E, W = s.diagnostics()
+    assert abs(E - orc.energy()) / orc.energy() <= 1e-5
+    assert abs(W - orc.enstrophy()) / orc.enstrophy() <= 1e-5
+    assert spectral_rel_l2(to_host(s.get_spectral()), orc.uh) <= 1e-5
+
+
+def test_mfma_fused_unfused_and_ensemble_agree():
+    """The matrix-core y pass is deterministic: fused and unfused schedules
+    give the same bits, and a batched ensemble member the same bits as a
+    single simulation."""
+    note("mfma fused/unfused/ensemble")
+    from paper_1602_03638_amd import Ensemble
+    N, nu, dt = 64, 0.01, 0.005
+    uh0 = ic.random_isotropic(N, seed=1004)
+    a = _solver(N, nu, dt, mfma_dft=True, fuse=True).set_spectral(to_dev(uh0, "f32")).step(3)
+    b = _solver(N, nu, dt, mfma_dft=True, fuse=False).set_spectral(to_dev(uh0, "f32")).step(3)
+    ua = to_host(a.get_spectral())
+    assert np.array_equal(ua, to_host(b.get_spectral()))
+    ens = Ensemble([N, N], [nu, nu], [dt, dt], dtype="f32", mfma_dft=True)
+    ens.set_spectral(0, to_dev(uh0, "f32"))
+    ens.set_spectral(1, to_dev(ic.random_isotropic(N, seed=1005), "f32"))
+    ens.step(3)
+    assert np.array_equal(to_host(ens.get_spectral(0)), ua)
+    ens.close()
+
+
+def test_mfma_unsupported_configurations():
+    from paper_1602_03638_amd import DnsError
+    note("mfma unsupported")
+    for N, dtype in ((64, "f64"), (32, "f32")):
+        with pytest.raises(DnsError) as e:
+            _solver(N, dtype=dtype, mfma_dft=True)
+        assert e.value.status == -6        # DNS_E_UNSUPPORTED
