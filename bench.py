@@ -274,6 +274,45 @@ def run_fft(sizes=FFT_SIZES, dtypes=("f32", "f64"), reps=10):
                         f"{reps}", "results": out}
 
 
+def run_tg_long(N, dtype, steps, out_path, chunk=1000):
+    """The paper's Taylor-Green verification run (Sec. 4.2: Re = 1600,
+    nu = 1/1600, dt = 1e-3, t = 0 -> 20): energy and enstrophy after every
+    step, written as JSON to out_path; progress every `chunk` steps.  The
+    energy budget residual (E_{n+1} - E_n)/dt + nu (Omega_n + Omega_{n+1}) is
+    reported alongside (the semi-discrete system has dE/dt = -2 nu Omega)."""
+    import torch
+    import workloads
+    from paper_1602_03638_amd import Solver
+
+    u0 = torch.from_numpy(workloads.taylor_green(N)).to(torch.float64 if dtype == "f64" else torch.float32)
+    s = Solver(N, NU, DT, dtype=dtype, diag_every=1, history_cap=steps)
+    s.set_velocity(u0.cuda().contiguous())
+    del u0
+    E0, W0 = s.diagnostics()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        n = min(chunk, steps - done)
+        s.step(n)
+        s.synchronize()
+        done += n
+        print(f"tg-long N={N} {dtype}: {done}/{steps} steps, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
+    wall = time.perf_counter() - t0
+    E, W = s.history()
+    s.close()
+    E, W = [E0] + list(E), [W0] + list(W)
+    res = [abs((E[n + 1] - E[n]) / DT + NU * (W[n] + W[n + 1])) / (NU * (W[n] + W[n + 1])) for n in range(len(E) - 1)]
+    rec = {"workload": f"taylor_green_{N}_rk4_re1600", "N": N, "dtype": dtype, "nu": NU, "dt": DT, "steps": steps,
+           "ms_per_step": wall * 1e3 / steps, "energy": E, "enstrophy": W, "max_rel_budget_residual": max(res)}
+    with open(out_path, "w") as f:
+        json.dump(rec, f)
+    peak = max(range(len(W)), key=lambda i: W[i])
+    return {"N": N, "dtype": dtype, "steps": steps, "ms_per_step": round(rec["ms_per_step"], 3),
+            "E_final": E[-1], "enstrophy_peak": W[peak], "t_enstrophy_peak": peak * DT,
+            "max_rel_budget_residual": max(res)}
+
+
 def cpu_baseline(N):
     """Time the CPU oracle on a bounded sample of the workload: one inverse and
     one forward 3D transform of one velocity component at N^3, scaled to one
@@ -379,6 +418,9 @@ def main(argv=None):
     ap.add_argument("--isotropic-only", action="store_true")
     ap.add_argument("--iso-steps", type=int, default=ISO_STEPS, help="timed steps of the 1024^3 leg")
     ap.add_argument("--no-fft", action="store_true", help="skip the FFT-only leg")
+    ap.add_argument("--tg-long", nargs=3, metavar=("N", "DTYPE", "STEPS"),
+                    help="only run the long Taylor-Green Re=1600 case (history to --tg-long-out)")
+    ap.add_argument("--tg-long-out", default="tg_long.json")
     ap.add_argument("--fft-only", action="store_true")
     ap.add_argument("--ens-steps", type=int, default=100)
     ap.add_argument("--ens-per-sim-steps", type=int, default=20)
@@ -398,6 +440,10 @@ def main(argv=None):
               "(the slab decomposition over several GPUs is described, not built)", file=sys.stderr)
         return 2
 
+    if a.tg_long:
+        N, dtype, steps = int(a.tg_long[0]), a.tg_long[1], int(a.tg_long[2])
+        print(json.dumps({"tg_long": run_tg_long(N, dtype, steps, a.tg_long_out)}), flush=True)
+        return 0
     if a.fft_only:
         print(json.dumps({"fft": run_fft()}), flush=True)
         return 0

@@ -111,8 +111,24 @@ int dns_create_ex(int N, double nu, double dt, int dtype, const dns_opts* opts,
  * no-op.  Does not touch caller memory. */
 int dns_destroy(dns_t* ctx);
 
-/* Bytes of device memory a context of this size holds. */
+/* Bytes of device memory a context of this size holds with the default
+ * options (the same as dns_workspace_bytes(N, dtype, NULL)). */
 size_t dns_state_bytes(int N, int dtype);
+
+/* Bytes of the device workspace a context with these options needs (opts
+ * may be NULL for the defaults); 0 for invalid arguments.  The workspace
+ * holds the 15 half-spectrum fields (padded layout), the diagnostic and
+ * history buffers and the twiddle tables. */
+size_t dns_workspace_bytes(int N, int dtype, const dns_opts* opts);
+
+/* As dns_create_ex, with every device buffer of the context placed in the
+ * caller's workspace (e.g. memory from PyTorch's allocator) instead of
+ * library allocations: workspace is a device pointer aligned to 256 bytes,
+ * bytes >= dns_workspace_bytes(N, dtype, opts) (DNS_E_INVAL otherwise).  The
+ * caller owns the workspace, must keep it alive until dns_destroy and must
+ * not touch it meanwhile; dns_destroy never frees it. */
+int dns_create_ws(int N, double nu, double dt, int dtype, const dns_opts* opts, void* workspace, size_t bytes,
+                  void* stream, dns_t** out);
 
 /* u_hat = F(u) for the physical (3, N, N, N) real field u_dev: real
  * transform along z, then complex along y, then x (Sec. 2, eq. fft);
@@ -215,11 +231,20 @@ int dns_inverse(dns_t* ctx, const void* uhat_dev, void* u_dev);
  * preserved.  dns_get_plan writes the chosen widths (6 entries);
  * dns_set_plan selects variants by width (DNS_E_INVAL if a width does not
  * exist for this N and dtype); dns_plan_variants lists the widths available
- * for one kernel (pass index 0..5). */
+ * for one kernel (pass index 0..5).
+ *
+ * Tuned plans are cached for the life of the process, keyed by (HIP device,
+ * N, dtype, simulations per launch): dns_autotune stores its choice, and a
+ * context or ensemble created with opts.autotune = 1 takes the cached plan
+ * when one exists instead of timing again.  dns_plan_cache_entries returns
+ * the number of cached plans; dns_plan_cache_clear empties the cache
+ * (both thread-safe). */
 int dns_autotune(dns_t* ctx, int reps);
 int dns_get_plan(const dns_t* ctx, int* widths, int max, int* count);
 int dns_set_plan(dns_t* ctx, const int* widths, int n);
 int dns_plan_variants(const dns_t* ctx, int pass, int* widths, int max, int* count);
+int dns_plan_cache_entries(void);
+int dns_plan_cache_clear(void);
 
 const char* dns_strerror(int status);
 const char* dns_last_error(const dns_t* ctx);

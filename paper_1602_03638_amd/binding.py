@@ -66,6 +66,8 @@ def load_library(path=LIB_PATH):
         "dns_state_bytes": (S, [I, I]),
         "dns_create": (I, [I, D, D, I, PP]),
         "dns_create_ex": (I, [I, D, D, I, ctypes.POINTER(dns_opts), P, PP]),
+        "dns_create_ws": (I, [I, D, D, I, ctypes.POINTER(dns_opts), P, S, P, PP]),
+        "dns_workspace_bytes": (S, [I, I, ctypes.POINTER(dns_opts)]),
         "dns_destroy": (I, [P]),
         "dns_set_velocity": (I, [P, P]),
         "dns_set_spectral": (I, [P, P]),
@@ -89,6 +91,8 @@ def load_library(path=LIB_PATH):
         "dns_get_plan": (I, [P, ctypes.POINTER(I), I, ctypes.POINTER(I)]),
         "dns_set_plan": (I, [P, ctypes.POINTER(I), I]),
         "dns_plan_variants": (I, [P, I, ctypes.POINTER(I), I, ctypes.POINTER(I)]),
+        "dns_plan_cache_entries": (I, []),
+        "dns_plan_cache_clear": (I, []),
         "dns_ens_create": (I, [I, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D), I,
                                ctypes.POINTER(dns_opts), P, PP]),
         "dns_ens_destroy": (I, [P]),
@@ -141,11 +145,31 @@ def state_bytes(N, dtype):
     return int(load_library().dns_state_bytes(int(N), int(dtype)))
 
 
+def workspace_bytes(N, dtype, **opts):
+    """Device bytes a Solver of this size needs (dns_workspace_bytes)."""
+    o = default_opts()
+    for k, v in opts.items():
+        setattr(o, k, int(v))
+    return int(load_library().dns_workspace_bytes(int(N), int(dtype), ctypes.byref(o)))
+
+
+def plan_cache_entries():
+    """Number of autotuned plans cached in this process."""
+    return int(load_library().dns_plan_cache_entries())
+
+
+def plan_cache_clear():
+    load_library().dns_plan_cache_clear()
+
+
 class Solver:
     """One pseudo-spectral DNS context on the current GPU (see include/dns.h).
 
     dtype: "f64" or "f32"; integrator: "rk4" (default) or "euler"; mfma_dft:
-    y passes with the radix-16 stage on FP16 matrix cores (FP32, N >= 64).
+    y passes with the radix-16 stage on FP16 matrix cores (FP32, N >= 64);
+    workspace: None (the library allocates), "torch" (a uint8 tensor from
+    torch's allocator) or a contiguous CUDA tensor of at least
+    dns_workspace_bytes bytes, 256-byte aligned, kept alive by the Solver.
     Tensors passed in must be contiguous CUDA tensors:
     physical (3, N, N, N) float64/float32, spectral (3, N, N, N/2+1)
     complex128/complex64.  All work is ordered on torch's current stream at
@@ -153,7 +177,8 @@ class Solver:
     """
 
     def __init__(self, N, nu, dt, dtype="f64", dealias="text", diag_every=0, use_graph=True,
-                 history_cap=4096, stream=None, autotune=False, fuse=True, integrator="rk4", mfma_dft=False):
+                 history_cap=4096, stream=None, autotune=False, fuse=True, integrator="rk4", mfma_dft=False,
+                 workspace=None):
         import torch
         self._torch = torch
         lib = load_library()
@@ -176,8 +201,23 @@ class Solver:
             stream = torch.cuda.current_stream()
         self.stream = stream
         h = ctypes.c_void_p()
-        _check(lib.dns_create_ex(self.N, self.nu, self.dt, self.code, ctypes.byref(o),
-                                 ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)), None, "dns_create_ex")
+        self._ws = None
+        if workspace is None:
+            _check(lib.dns_create_ex(self.N, self.nu, self.dt, self.code, ctypes.byref(o),
+                                     ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)), None, "dns_create_ex")
+        else:
+            # device memory from torch's allocator: a fresh uint8 tensor of
+            # dns_workspace_bytes, or a caller-provided CUDA tensor
+            nbytes = int(lib.dns_workspace_bytes(self.N, self.code, ctypes.byref(o)))
+            if workspace == "torch":
+                workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            if not workspace.is_cuda or not workspace.is_contiguous():
+                raise ValueError("workspace must be a contiguous CUDA tensor")
+            self._ws = workspace
+            size = workspace.numel() * workspace.element_size()
+            _check(lib.dns_create_ws(self.N, self.nu, self.dt, self.code, ctypes.byref(o),
+                                     ctypes.c_void_p(workspace.data_ptr()), size,
+                                     ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)), None, "dns_create_ws")
         self._h = h
 
     # -- helpers ----------------------------------------------------------
@@ -338,6 +378,7 @@ class Solver:
         if getattr(self, "_h", None) is not None and self._h.value:
             load_library().dns_destroy(self._h)
         self._h = None
+        self._ws = None
 
     def __del__(self):
         try:

@@ -3,11 +3,16 @@
 // transforms, diagnostics and profiling.
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "dns.h"
@@ -112,6 +117,8 @@ struct dns_ctx {
     size_t fs = 0;                  // complex values per half-spectrum field
     size_t cbytes = 0;              // bytes of one complex value
     size_t fbytes = 0;              // bytes of one half-spectrum field
+    char* mem = nullptr;            // one device block holding every buffer below
+    bool own_mem = true;            // false: the block is the caller's workspace
     char* state = nullptr;          // per member: U0 | U1 | Us, three fields each
     char* work = nullptr;           // per member: W, six fields
     void* tw = nullptr;
@@ -322,19 +329,48 @@ int reduce_state(dns_t* c, const void* U, double* E, double* W) {
 
 void release(dns_t* c) {
     drop_graphs(c);
-    if (c->state) (void)hipFree(c->state);
-    if (c->work) (void)hipFree(c->work);
-    if (c->tw) (void)hipFree(c->tw);
-    if (c->mfma_tw) (void)hipFree(c->mfma_tw);
-    if (c->part) (void)hipFree(c->part);
-    if (c->dout) (void)hipFree(c->dout);
-    if (c->hist) (void)hipFree(c->hist);
-    if (c->hist_count) (void)hipFree(c->hist_count);
+    if (c->mem && c->own_mem) (void)hipFree(c->mem);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     for (auto& e : c->ev_prof)
         if (e) (void)hipEventDestroy(e);
     if (c->s && c->own_stream) (void)hipStreamDestroy(c->s);
+}
+
+// Process-wide cache of autotuned plans: the variant chosen for each pass,
+// keyed by (device, N, dtype, members per launch).  dns_autotune stores its
+// result; a context created with opts.autotune takes a cached plan instead of
+// timing again.
+using PlanKey = std::tuple<int, int, int, int>;
+using Plan = std::array<int, dns::P_COUNT>;
+std::mutex g_plan_mu;
+std::map<PlanKey, Plan> g_plans;
+
+PlanKey plan_key(const dns_t* c) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return PlanKey{dev, c->N, c->dtype, c->members};
+}
+
+void store_plan(const dns_t* c) {
+    Plan p;
+    for (int k = 0; k < dns::P_COUNT; ++k) p[k] = c->sel[k];
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    g_plans[plan_key(c)] = p;
+}
+
+bool load_plan(dns_t* c) {
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    auto it = g_plans.find(plan_key(c));
+    if (it == g_plans.end()) return false;
+    for (int k = 0; k < dns::P_COUNT; ++k) c->sel[k] = it->second[k];
+    return true;
+}
+
+// Tuned plan for a new context: from the cache, else timed (and cached).
+int tune_new(dns_t* c) {
+    if (load_plan(c)) return DNS_OK;
+    return dns_autotune(c, 3);
 }
 
 int check_args(int N, double nu, double dt, int dtype, const dns_opts& o) {
@@ -349,10 +385,48 @@ int check_args(int N, double nu, double dt, int dtype, const dns_opts& o) {
     return DNS_OK;
 }
 
+// Byte offsets of a context's device buffers inside its one memory block,
+// each 256-byte aligned.
+struct Carve {
+    size_t state, work, part, dout, hist, hist_count, tw, mfma_tw, total;
+    int npart_cap;
+};
+
+Carve carve(const dns::Ops* ops, int N, const dns_opts& o, int members) {
+    Carve k{};
+    const size_t cb = 2 * ops->real_size, fb = ops->fs * cb;
+    k.npart_cap = dns::DIAG_BLOCKS;
+    for (int v = 0; v < ops->nvar[dns::P_XRHS]; ++v)
+        if (ops->xrhs_groups[v] > k.npart_cap) k.npart_cap = ops->xrhs_groups[v];
+    for (int v = 0; v < ops->nvar[dns::P_XSTAGE]; ++v)
+        if (ops->xstage_groups[v] > k.npart_cap) k.npart_cap = ops->xstage_groups[v];
+    const size_t hist_cap = o.history_cap > 0 ? (size_t)o.history_cap : 1;
+    const int ntw2 = dns::tw_size(N / 16);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    k.state = take((size_t)members * 9 * fb);
+    k.work = take((size_t)members * 6 * fb);
+    k.part = take(2 * sizeof(double) * (size_t)k.npart_cap * members);
+    k.dout = take(2 * sizeof(double) * (size_t)members);
+    k.hist = take(2 * sizeof(double) * hist_cap * members);
+    k.hist_count = take(sizeof(int) * (size_t)members);
+    k.tw = take((size_t)ops->tw_count * cb);
+    k.mfma_tw = o.mfma_dft ? take(((size_t)N + (size_t)(ntw2 > 0 ? ntw2 : 1)) * cb) : 0;
+    k.total = off;
+    return k;
+}
+
 // Create a context of `members` simulations.  lib_stream: when non-null the
 // context enqueues on that stream (owned by an ensemble) instead of its own.
+// workspace: when non-null, a caller-owned device block of `ws_bytes` bytes
+// (256-byte aligned, at least carve().total) that holds every device buffer;
+// otherwise the library allocates the block.
 int create_ctx(int N, double nu, double dt, int dtype, const dns_opts& o, hipStream_t user, int members,
-               hipStream_t lib_stream, dns_t** out) {
+               hipStream_t lib_stream, dns_t** out, void* workspace = nullptr, size_t ws_bytes = 0) {
     *out = nullptr;
     dns_t* c = new (std::nothrow) dns_ctx();
     if (!c) return DNS_E_NOMEM;
@@ -387,27 +461,29 @@ int create_ctx(int N, double nu, double dt, int dtype, const dns_opts& o, hipStr
         (e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventCreate(&c->ev_prof[0])) != hipSuccess || (e = hipEventCreate(&c->ev_prof[1])) != hipSuccess)
         return bail(DNS_E_HIP, "hipEventCreate", e);
-    if ((e = hipMalloc((void**)&c->state, (size_t)members * 9 * c->fbytes)) != hipSuccess)
-        return bail(DNS_E_NOMEM, "hipMalloc(state)", e);
-    if ((e = hipMalloc((void**)&c->work, (size_t)members * 6 * c->fbytes)) != hipSuccess)
-        return bail(DNS_E_NOMEM, "hipMalloc(work)", e);
-    c->npart_cap = dns::DIAG_BLOCKS;
-    for (int v = 0; v < c->ops->nvar[dns::P_XRHS]; ++v)
-        if (c->ops->xrhs_groups[v] > c->npart_cap) c->npart_cap = c->ops->xrhs_groups[v];
-    for (int v = 0; v < c->ops->nvar[dns::P_XSTAGE]; ++v)
-        if (c->ops->xstage_groups[v] > c->npart_cap) c->npart_cap = c->ops->xstage_groups[v];
+    const Carve k = carve(c->ops, N, o, members);
+    if (workspace) {
+        c->mem = (char*)workspace;
+        c->own_mem = false;
+    } else if ((e = hipMalloc((void**)&c->mem, k.total)) != hipSuccess) {
+        return bail(DNS_E_NOMEM, "hipMalloc", e);
+    }
+    (void)ws_bytes;   // checked by the caller against carve().total
+    c->state = c->mem + k.state;
+    c->work = c->mem + k.work;
+    c->part = (double*)(c->mem + k.part);
+    c->dout = (double*)(c->mem + k.dout);
+    c->hist = (double*)(c->mem + k.hist);
+    c->hist_count = (int*)(c->mem + k.hist_count);
+    c->tw = c->mem + k.tw;
+    c->mfma_tw = o.mfma_dft ? (void*)(c->mem + k.mfma_tw) : nullptr;
+    c->npart_cap = k.npart_cap;
     for (int p = 0; p < dns::P_COUNT; ++p) c->sel[p] = c->ops->def[p];
-    if ((e = hipMalloc((void**)&c->part, 2 * sizeof(double) * (size_t)c->npart_cap * members)) != hipSuccess ||
-        (e = hipMalloc((void**)&c->dout, 2 * sizeof(double) * (size_t)members)) != hipSuccess ||
-        (e = hipMalloc((void**)&c->hist, 2 * sizeof(double) * (size_t)c->hist_cap() * members)) != hipSuccess ||
-        (e = hipMalloc((void**)&c->hist_count, sizeof(int) * (size_t)members)) != hipSuccess)
-        return bail(DNS_E_NOMEM, "hipMalloc(diagnostics)", e);
 
     // twiddles: long-double accurate, rounded to the context's precision
     const int ntw = c->ops->tw_count;
     std::vector<double> twd(2 * (size_t)ntw, 0.0);
     dns::make_twiddles(N, twd.data());
-    if ((e = hipMalloc(&c->tw, (size_t)ntw * c->cbytes)) != hipSuccess) return bail(DNS_E_NOMEM, "hipMalloc(tw)", e);
     if (dtype == DNS_FP64) {
         e = hipMemcpy(c->tw, twd.data(), (size_t)ntw * c->cbytes, hipMemcpyHostToDevice);
     } else {
@@ -425,8 +501,6 @@ int create_ctx(int N, double nu, double dt, int dtype, const dns_opts& o, hipStr
         if (ntw2 > 0) dns::make_twiddles(n2, roots.data() + 2 * (size_t)N);
         std::vector<float> rf(roots.size());
         for (size_t i = 0; i < roots.size(); ++i) rf[i] = (float)roots[i];
-        if ((e = hipMalloc(&c->mfma_tw, rf.size() * sizeof(float))) != hipSuccess)
-            return bail(DNS_E_NOMEM, "hipMalloc(mfma_tw)", e);
         if ((e = hipMemcpy(c->mfma_tw, rf.data(), rf.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
             return bail(DNS_E_HIP, "hipMemcpy(mfma_tw)", e);
     }
@@ -567,14 +641,44 @@ void dns_default_opts(dns_opts* o) {
 }
 
 size_t dns_state_bytes(int N, int dtype) {
+    dns_opts o;
+    dns_default_opts(&o);
+    return dns_workspace_bytes(N, dtype, &o);
+}
+
+size_t dns_workspace_bytes(int N, int dtype, const dns_opts* opts) {
     if (!valid_n(N) || (dtype != DNS_FP64 && dtype != DNS_FP32)) return 0;
-    const dns::Ops* o = dtype == DNS_FP64 ? dns::ops_f64(N) : dns::ops_f32(N);
-    const size_t cb = 2 * o->real_size;
-    return 15 * o->fs * cb + (size_t)o->tw_count * cb;
+    dns_opts o;
+    dns_default_opts(&o);
+    if (opts) o = *opts;
+    if (check_args(N, 1.0, 1.0, dtype, o) != DNS_OK) return 0;
+    const dns::Ops* ops = dtype == DNS_FP64 ? dns::ops_f64(N) : dns::ops_f32(N);
+    return carve(ops, N, o, 1).total;
 }
 
 int dns_create(int N, double nu, double dt, int dtype, dns_t** out) {
     return dns_create_ex(N, nu, dt, dtype, nullptr, nullptr, out);
+}
+
+int dns_create_ws(int N, double nu, double dt, int dtype, const dns_opts* opts, void* workspace, size_t bytes,
+                  void* stream, dns_t** out) {
+    if (!out || !workspace) return DNS_E_INVAL;
+    *out = nullptr;
+    dns_opts o;
+    dns_default_opts(&o);
+    if (opts) o = *opts;
+    int r = check_args(N, nu, dt, dtype, o);
+    if (r) return r;
+    if (((uintptr_t)workspace & 255) != 0 || bytes < dns_workspace_bytes(N, dtype, &o)) return DNS_E_INVAL;
+    dns_t* c = nullptr;
+    if ((r = create_ctx(N, nu, dt, dtype, o, (hipStream_t)stream, 1, nullptr, &c, workspace, bytes))) return r;
+    if (o.autotune && (r = tune_new(c)) != DNS_OK) {
+        release(c);
+        delete c;
+        return r;
+    }
+    *out = c;
+    return DNS_OK;
 }
 
 int dns_create_ex(int N, double nu, double dt, int dtype, const dns_opts* opts, void* stream, dns_t** out) {
@@ -587,7 +691,7 @@ int dns_create_ex(int N, double nu, double dt, int dtype, const dns_opts* opts, 
     if (r) return r;
     dns_t* c = nullptr;
     if ((r = create_ctx(N, nu, dt, dtype, o, (hipStream_t)stream, 1, nullptr, &c))) return r;
-    if (o.autotune && (r = dns_autotune(c, 3)) != DNS_OK) {
+    if (o.autotune && (r = tune_new(c)) != DNS_OK) {
         release(c);
         delete c;
         return r;
@@ -809,7 +913,19 @@ int dns_autotune(dns_t* c, int reps) {
         c->sel[p] = bestv;
     }
     c->w_ready = false;
+    store_plan(c);
     return leave(c);
+}
+
+int dns_plan_cache_entries(void) {
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    return (int)g_plans.size();
+}
+
+int dns_plan_cache_clear(void) {
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    g_plans.clear();
+    return DNS_OK;
 }
 
 int dns_get_plan(const dns_t* c, int* widths, int max, int* count) {
@@ -970,7 +1086,7 @@ int dns_ens_create(int count, const int* N, const double* nu, const double* dt, 
         }
         e->cls.push_back(c);
         // tile shapes timed on the batched launches of this class
-        if (o.autotune && (r = dns_autotune(c, 3)) != DNS_OK) {
+        if (o.autotune && (r = tune_new(c)) != DNS_OK) {
             ens_release(e);
             delete e;
             return r;

@@ -93,3 +93,24 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(RuntimeError, match="build"):
         binding.load_library(str(tmp_path / "nope.so"))
+
+
+def test_plan_cache_starts_empty_and_clears(lib):
+    # no context has been tuned in this CPU-only process
+    dns.plan_cache_clear()
+    assert dns.plan_cache_entries() == 0
+
+
+def test_workspace_bytes_and_validation(lib):
+    b = dns.workspace_bytes(512, dns.DNS_FP64)
+    assert b == dns.state_bytes(512, dns.DNS_FP64) > 0
+    assert dns.workspace_bytes(512, dns.DNS_FP32) < b
+    # a longer history needs more room; invalid options need none
+    assert dns.workspace_bytes(64, dns.DNS_FP64, history_cap=100000) > dns.workspace_bytes(64, dns.DNS_FP64)
+    assert dns.workspace_bytes(64, dns.DNS_FP64, mfma_dft=1) == 0       # FP64 has no matrix-core stage
+    assert dns.workspace_bytes(64, dns.DNS_FP32, mfma_dft=1) > dns.workspace_bytes(64, dns.DNS_FP32)
+    assert dns.workspace_bytes(48, dns.DNS_FP64) == 0
+    # a null workspace is rejected before any device call
+    h = ctypes.c_void_p()
+    assert lib.dns_create_ws(64, 0.01, 0.01, dns.DNS_FP64, None, None, 1 << 30, None, ctypes.byref(h)) == \
+        dns.DNS_E_INVAL

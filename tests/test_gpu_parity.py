@@ -279,3 +279,54 @@ def test_forward_euler_fused_matches_unfused_and_fp32(dtype):
         orc = spectral.Solver(N, nu, dt, integrator="euler").set_spectral(
             uh0.astype(np.complex64).astype(np.complex128)).step(4)
         assert abs(a.energy() - orc.energy()) / orc.energy() <= 1e-5
+
+
+def test_autotuned_plan_is_cached():
+    """dns_autotune stores its plan; a context created with autotune reuses
+    the cached plan for the same (N, dtype) and gives the same bits."""
+    import paper_1602_03638_amd as dns
+    note("plan cache")
+    dns.plan_cache_clear()
+    N = 32
+    uh0 = ic.random_isotropic(N, seed=1006)
+    a = _solver(N, autotune=True)
+    assert dns.plan_cache_entries() == 1
+    b = _solver(N, autotune=True)
+    assert dns.plan_cache_entries() == 1
+    assert a.plan() == b.plan()
+    c = _solver(N, dtype="f32", autotune=True)
+    assert dns.plan_cache_entries() == 2
+    a.set_spectral(to_dev(uh0, "f64")).step(2)
+    b.set_spectral(to_dev(uh0, "f64")).step(2)
+    assert np.array_equal(to_host(a.get_spectral()), to_host(b.get_spectral()))
+    for s in (a, b, c):
+        s.close()
+    dns.plan_cache_clear()
+    assert dns.plan_cache_entries() == 0
+
+
+def test_caller_workspace_matches_library_allocation():
+    """A context in a workspace from torch's allocator computes the same bits
+    as one whose memory the library allocates; undersized or misaligned
+    workspaces are rejected."""
+    import torch
+    import paper_1602_03638_amd as dns
+    from paper_1602_03638_amd import DnsError
+    note("caller workspace")
+    N, nu, dt = 32, 0.01, 0.005
+    uh0 = ic.random_isotropic(N, seed=1007)
+    a = _solver(N, nu, dt, diag_every=1, workspace="torch").set_spectral(to_dev(uh0, "f64")).step(3)
+    b = _solver(N, nu, dt, diag_every=1).set_spectral(to_dev(uh0, "f64")).step(3)
+    assert np.array_equal(to_host(a.get_spectral()), to_host(b.get_spectral()))
+    assert a.history() == b.history()
+    a.close()
+    b.close()
+    need = dns.workspace_bytes(N, dns.DNS_FP64)
+    small = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(DnsError) as e:
+        _solver(N, workspace=small)
+    assert e.value.status == dns.DNS_E_INVAL
+    big = torch.empty(need + 1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(DnsError) as e:
+        _solver(N, workspace=big[1:])                 # not 256-byte aligned
+    assert e.value.status == dns.DNS_E_INVAL
