@@ -246,6 +246,13 @@ int dns_plan_variants(const dns_t* ctx, int pass, int* widths, int max, int* cou
 int dns_plan_cache_entries(void);
 int dns_plan_cache_clear(void);
 
+/* dns_strerror: a static description of a status code.  dns_last_error:
+ * the message of the context's last failure ("" if none).
+ *
+ * Testing error paths: with the environment variable DNS_FAULT_INJECT set to
+ * "launch" when a context is created, every launch check of that context
+ * reports DNS_E_HIP ("injected launch failure") after the kernels have been
+ * enqueued normally; no device fault is involved. */
 const char* dns_strerror(int status);
 const char* dns_last_error(const dns_t* ctx);
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -130,6 +131,7 @@ struct dns_ctx {
     int* hist_count = nullptr;      // [member]
     hipGraphExec_t gexec[2] = {nullptr, nullptr};   // step without / with diagnostics
     bool has_state = false;
+    bool inject_fault = false;      // DNS_FAULT_INJECT=launch at creation: launch checks fail
     long long steps = 0;
     std::string err;
 
@@ -156,7 +158,15 @@ int hip_check(dns_t* c, hipError_t e, const char* what) {
 #define DNS_TRY(ctx, call) \
     do { int _r = hip_check((ctx), (call), #call); if (_r != DNS_OK) return _r; } while (0)
 
-int launched(dns_t* c, const char* what) { return hip_check(c, hipGetLastError(), what); }
+// Status of the kernels just enqueued.  With DNS_FAULT_INJECT=launch in the
+// environment when the context was created, every check reports DNS_E_HIP
+// (after consuming the real status), so that callers can test their error
+// handling without a device fault.
+int launched(dns_t* c, const char* what) {
+    const int r = hip_check(c, hipGetLastError(), what);
+    if (r == DNS_OK && c && c->inject_fault) return fail(c, DNS_E_HIP, std::string(what) + ": injected launch failure");
+    return r;
+}
 
 bool valid_n(int N) { return N >= 8 && N <= 1024 && (N & (N - 1)) == 0; }
 
@@ -438,6 +448,8 @@ int create_ctx(int N, double nu, double dt, int dtype, const dns_opts& o, hipStr
     c->members = members;
     c->mask_lim = (o.dealias == DNS_DEALIAS_TEXT) ? N : N + 2;
     c->user = user;
+    const char* fi = std::getenv("DNS_FAULT_INJECT");
+    c->inject_fault = fi != nullptr && std::strcmp(fi, "launch") == 0;
     c->ops = dtype == DNS_FP64 ? dns::ops_f64(N) : dns::ops_f32(N);
     const size_t rs = c->ops->real_size;
     c->fs = c->ops->fs;

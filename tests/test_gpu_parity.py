@@ -330,3 +330,20 @@ def test_caller_workspace_matches_library_allocation():
     with pytest.raises(DnsError) as e:
         _solver(N, workspace=big[1:])                 # not 256-byte aligned
     assert e.value.status == dns.DNS_E_INVAL
+
+
+def test_injected_launch_failure_reports_hip_error(monkeypatch):
+    """DNS_FAULT_INJECT=launch makes the context's launch checks report
+    DNS_E_HIP with a message; a context created without it is unaffected."""
+    from paper_1602_03638_amd import DNS_E_HIP, DnsError
+    note("fault injection")
+    uh0 = ic.random_isotropic(16, seed=1008)
+    monkeypatch.setenv("DNS_FAULT_INJECT", "launch")
+    s = _solver(16)
+    monkeypatch.delenv("DNS_FAULT_INJECT")
+    with pytest.raises(DnsError) as e:
+        s.set_spectral(to_dev(uh0, "f64"))
+    assert e.value.status == DNS_E_HIP and "injected" in str(e.value)
+    s.close()
+    ok = _solver(16).set_spectral(to_dev(uh0, "f64")).step(1)
+    assert np.isfinite(ok.energy())
