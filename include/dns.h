@@ -11,8 +11,9 @@
  *   N_hat = dealias * F(u x omega),  omega = F^-1(i k x u_hat)
  *
  * (Sec. 2, eqs. NSfinal and curl_convection; Sec. 3.1 computeRHS listing),
- * integrated with classic RK4 (Appendix solver).  All compute runs in HIP
- * kernels for gfx950; there is no CPU fallback.
+ * integrated with classic RK4 (Appendix solver) or forward Euler (Sec. 3.1
+ * main loop).  All compute runs in HIP kernels for gfx950; there is no CPU
+ * fallback.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -99,16 +100,21 @@ void dns_default_opts(dns_opts* opts);
 
 /* Create a solver for N^3 points, viscosity nu >= 0, time step dt > 0 and
  * dtype DNS_FP64 or DNS_FP32 (Sec. 3.1: float is a placeholder for single
- * or double precision).  The library allocates its device state (15 half-
- * spectrum fields of N*N*(N/2+1) complex values plus O(N) tables) on the
- * current HIP device.  stream: a hipStream_t cast to void*, or NULL for the
- * null stream.  opts may be NULL.  On success *out owns the context. */
+ * or double precision).  The library allocates its device state in one
+ * block of dns_workspace_bytes (15 half-spectrum fields of N*N*(N/2+1)
+ * complex values in a padded layout, diagnostic buffers and O(N) tables) on
+ * the current HIP device.  stream: a hipStream_t cast to void*, or NULL for
+ * the null stream.  opts may be NULL.  On success *out owns the context.
+ * DNS_E_INVAL for invalid arguments or options, DNS_E_UNSUPPORTED for an
+ * option this dtype or N does not provide, DNS_E_NOMEM if the allocation
+ * fails. */
 int dns_create(int N, double nu, double dt, int dtype, dns_t** out);
 int dns_create_ex(int N, double nu, double dt, int dtype, const dns_opts* opts,
                   void* stream, dns_t** out);
 
-/* Release every allocation of ctx (device state, graphs, stream); NULL is a
- * no-op.  Does not touch caller memory. */
+/* Wait for the context's stream, then release every allocation of ctx
+ * (device state, graphs, stream); NULL is a no-op.  Does not free caller
+ * memory (a workspace given to dns_create_ws). */
 int dns_destroy(dns_t* ctx);
 
 /* Bytes of device memory a context of this size holds with the default
@@ -174,11 +180,13 @@ int dns_get_spectral(dns_t* ctx, void* uhat_dev);
  * not enter (numpy irfftn semantics). */
 int dns_get_velocity(dns_t* ctx, void* u_dev);
 
-/* Advance nsteps >= 0 classic RK4 steps (Appendix solver: a = 1/6, 1/3,
- * 1/3, 1/6; b = 1/2, 1/2, 1).  Each stage evaluates eq. NSfinal: inverse
+/* Advance nsteps >= 0 time steps of the context's integrator: classic RK4
+ * (Appendix solver: a = 1/6, 1/3, 1/3, 1/6; b = 1/2, 1/2, 1), or forward
+ * Euler (u_hat += RHS dt).  Each stage evaluates eq. NSfinal: inverse
  * transforms of u_hat and omega_hat = i k x u_hat, u x omega in physical
  * space, forward transform, dealias mask, pressure projection and viscous
- * term.  Asynchronous. */
+ * term.  Asynchronous; each step is replayed as one captured HIP graph
+ * unless opts.use_graph = 0.  DNS_E_STATE before a velocity is set. */
 int dns_step(dns_t* ctx, int nsteps);
 
 /* One evaluation of the right-hand side of eq. NSfinal at the current
@@ -199,13 +207,13 @@ int dns_diagnostics(dns_t* ctx, double* E, double* Omega);
  * recorded.  Synchronous. */
 int dns_history(dns_t* ctx, double* E, double* Omega, int max, int* count);
 
-/* Number of RK4 steps taken since the last set call. */
+/* Number of time steps taken since the last set call. */
 int dns_steps_taken(const dns_t* ctx, long long* steps);
 
 /* Wait until all work the context enqueued has finished. */
 int dns_synchronize(dns_t* ctx);
 
-/* Time each kernel of one RK4 step: runs nsteps steps with kernels launched
+/* Time each kernel of one time step: runs nsteps steps with kernels launched
  * one by one on the context's stream, bracketed by HIP events, and writes
  * the mean duration in milliseconds of each of the step's kernels (in
  * launch order) into ms[0..*count-1] (at most max entries) and their names
@@ -231,7 +239,9 @@ int dns_inverse(dns_t* ctx, const void* uhat_dev, void* u_dev);
  * preserved.  dns_get_plan writes the chosen widths (6 entries);
  * dns_set_plan selects variants by width (DNS_E_INVAL if a width does not
  * exist for this N and dtype); dns_plan_variants lists the widths available
- * for one kernel (pass index 0..5).
+ * for one kernel (pass index 0..5).  With opts.mfma_dft the y passes run the
+ * matrix-core kernel, which has a single shape; their widths then only
+ * matter for a later context without the option.
  *
  * Tuned plans are cached for the life of the process, keyed by (HIP device,
  * N, dtype, simulations per launch): dns_autotune stores its choice, and a
@@ -279,7 +289,7 @@ int dns_ens_set_velocity(dns_ens_t* ens, int i, const void* u_dev);
 int dns_ens_set_spectral(dns_ens_t* ens, int i, const void* uhat_dev);
 int dns_ens_init_random(dns_ens_t* ens, int i, unsigned long long seed, double k0, double energy);
 int dns_ens_get_spectral(dns_ens_t* ens, int i, void* uhat_dev);
-/* Advance every member nsteps RK4 steps; mode DNS_ENS_BATCHED or
+/* Advance every member nsteps time steps; mode DNS_ENS_BATCHED or
  * DNS_ENS_PER_SIM (bitwise identical results). */
 int dns_ens_step(dns_ens_t* ens, int nsteps, int mode);
 /* E[i], Omega[i] for every member (either pointer may be NULL). Synchronous. */
