@@ -1,10 +1,11 @@
-// HIP kernels of one RK4 stage of the pseudo-spectral solver and of the
-// standalone 3D real transforms (templated on real type R and grid size N).
+// HIP kernels of one time-integration stage of the pseudo-spectral solver
+// and of the standalone 3D real transforms (templated on real type R and
+// grid size N).
 //
 // One stage (Sec. 2 eq. NSfinal, Sec. 3.1 computeRHS) runs as five passes
-// over HBM-resident half-spectrum fields in the internal layout of
+// over HBM-resident half-spectrum fields in the padded internal layout of
 // dns_common.hpp:
-//   1. k_xinv      u_hat -> 6 fields: inverse x FFT of u_hat and of
+//   1. k_xinv_curl u_hat -> 6 fields: inverse x FFT of u_hat and of
 //                  omega_hat = i k x u_hat formed on the fly
 //   2. k_yline     inverse y FFT of the 6 fields (in place; the last
 //                  workgroups take the kz = N/2 plane)
@@ -13,7 +14,10 @@
 //                  leave the chip
 //   4. k_yline     forward y FFT of the 3 fields
 //   5. k_xrhs      forward x FFT, dealias mask, pressure projection,
-//                  viscous term and the RK4 stage update (+ diagnostics)
+//                  viscous term and the RK4 (or forward Euler) stage update
+//                  (+ diagnostics)
+// In the default schedule k_xstage runs pass 5 fused with pass 1 of the next
+// stage.  The FP32 y passes can instead run k_yline_mfma (dns_mfma.hpp).
 #pragma once
 
 #include "fft_device.hpp"
