@@ -35,12 +35,18 @@ FIELDS_PER_STEP = 180.0
 
 
 def kernel_source_hash():
+    """SHA-256 of the HIP sources with // comments and blank lines removed, so
+    that counter summaries stay valid across comment-only edits."""
     import glob
     import hashlib
+    import re
     h = hashlib.sha256()
     for path in sorted(glob.glob(os.path.join(ROOT, "paper_1602_03638_amd", "csrc", "*"))):
-        with open(path, "rb") as f:
-            h.update(f.read())
+        with open(path) as f:
+            for line in f:
+                code = re.sub(r"//.*", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 
