@@ -26,12 +26,26 @@ N_DEFAULT, NU, DT = 512, 1.0 / 1600, 1e-3
 # step (stage 0: read U0, write Us; stage 1: read Us, U0, write Us, U1;
 # stage 2: read Us, U0, write Us; stage 3: read Us, U1, write U0), and the
 # forward x pass reads N_hat (3C) at every stage, so xrhs_rk4 averages
-# (36 + 12) / 4 = 12C; xstage adds the 6C of inverse-x/curl fields it writes
-# for the next stage.  Fused step (the default schedule):
-# 4 * (12 + 9 + 6) C + 4 * 18 C = 180 C; unfused: 4 * (9 + 27) C + 48 C = 192 C.
-FIELDS_PER_LAUNCH = {"xinv_curl": 9.0, "yinv6": 12.0, "zcross": 9.0, "yfwd3": 6.0, "xrhs_rk4": 48.0 / 4,
-                     "xstage": 48.0 / 4 + 6.0}
-FIELDS_PER_STEP = 180.0
+# (36 + 12) / 4 = 12C; xstage adds the inverse-x fields it writes for the
+# next stage.  Below N = 1024 the inverse y pass forms the vorticity from
+# five x-pass fields (U, V, W, F(kx v), F(kx w)): xinv_curl 3C + 5C,
+# yinv6 5C + 6C, xstage 12C + 5C, fused step 4 * (11 + 9 + 6 + 17) C = 172 C.
+# At N = 1024 the x pass writes all six: 9C, 12C, 18C and 180 C per step.
+# Unfused (either): 4 * (9 + 27) C + 48 C = 192 C.
+def curl_in_y(N):
+    """True where the inverse y pass combines the vorticity (N < 1024)."""
+    return N < 1024
+
+
+def fields_per_launch(N):
+    x = 5.0 if curl_in_y(N) else 6.0
+    return {"xinv_curl": 3.0 + x, "yinv6": x + 6.0, "zcross": 9.0, "yfwd3": 6.0, "xrhs_rk4": 48.0 / 4,
+            "xstage": 48.0 / 4 + x}
+
+
+def fields_per_step(N):
+    f = fields_per_launch(N)
+    return 4 * (f["yinv6"] + f["zcross"] + f["yfwd3"] + f["xstage"])
 
 
 def kernel_source_hash():
@@ -117,10 +131,10 @@ def run_gpu(N, dtype, steps, warmup, prof_steps):
     s.close()
     torch.cuda.empty_cache()
     C = field_bytes(N, dtype)
-    out = {"ms_per_step": ms, "model_GBps": FIELDS_PER_STEP * C / (ms * 1e-3) / 1e9,
+    out = {"ms_per_step": ms, "model_GBps": fields_per_step(N) * C / (ms * 1e-3) / 1e9,
            "energy": E, "enstrophy": W, "error_vs_oracle": err, "kernels_ms": kern}
     if kern:
-        achieved = {k: FIELDS_PER_LAUNCH[k] * C / (v * 1e-3) / 1e9 for k, v in kern.items()}
+        achieved = {k: fields_per_launch(N)[k] * C / (v * 1e-3) / 1e9 for k, v in kern.items()}
         out["kernels_GBps"] = achieved
     return out
 
@@ -157,12 +171,12 @@ def run_ensemble(steps, warmup, per_sim_steps, autotune=True):
     ms_p = timed(per_sim_steps, False)
     E, _ = ens.diagnostics()
     ens.close()
-    fields = sum(count * field_bytes(N, "f32") for N, count in ENSEMBLE)
+    traffic = sum(count * fields_per_step(N) * field_bytes(N, "f32") for N, count in ENSEMBLE)
     return {"workload": "+".join(f"{count}x{N}^3" for N, count in ENSEMBLE) + " f32 random isotropic",
             "members": len(Ns), "nu": ENS_NU, "dt": ENS_DT, "autotuned_tiles": autotune,
             "batched": {"steps": steps, "ms_per_step": round(ms_b, 4), "ens_steps_per_s": round(1e3 / ms_b, 1),
                         "sim_steps_per_s": round(len(Ns) * 1e3 / ms_b, 1),
-                        "model_GBps": round(FIELDS_PER_STEP * fields / (ms_b * 1e-3) / 1e9, 1)},
+                        "model_GBps": round(traffic / (ms_b * 1e-3) / 1e9, 1)},
             "per_sim": {"steps": per_sim_steps, "ms_per_step": round(ms_p, 4),
                         "ens_steps_per_s": round(1e3 / ms_p, 1),
                         "sim_steps_per_s": round(len(Ns) * 1e3 / ms_p, 1)},
@@ -235,14 +249,14 @@ def run_isotropic(N=ISO_N, steps=ISO_STEPS, warmup=2):
     C = field_bytes(N, "f32")
     return {"workload": f"random_isotropic_{N}_rk4", "N": N, "nu": ISO_NU, "dt": ISO_DT, "steps": steps,
             "seed": ISO_SEED, "k0": 4.0, "E0": E0, "Omega0": W0,
-            "fp32": {"ms_per_step": round(ms32, 3), "model_GBps": round(FIELDS_PER_STEP * C / (ms32 * 1e-3) / 1e9, 1),
+            "fp32": {"ms_per_step": round(ms32, 3), "model_GBps": round(fields_per_step(N) * C / (ms32 * 1e-3) / 1e9, 1),
                      "energy": E32, "enstrophy": W32, "kernels_ms": k32},
             "fp32_mfma_dft": {"ms_per_step": round(msm, 3),
-                              "model_GBps": round(FIELDS_PER_STEP * C / (msm * 1e-3) / 1e9, 1),
+                              "model_GBps": round(fields_per_step(N) * C / (msm * 1e-3) / 1e9, 1),
                               "energy": Em, "enstrophy": Wm, "kernels_ms": km,
                               "y_stage": "radix-16 DFT on FP16 matrix cores (hi/lo split, FP32 accumulation)"},
             "fp64": {"ms_per_step": round(ms64, 3),
-                     "model_GBps": round(FIELDS_PER_STEP * 2 * C / (ms64 * 1e-3) / 1e9, 1),
+                     "model_GBps": round(fields_per_step(N) * 2 * C / (ms64 * 1e-3) / 1e9, 1),
                      "energy": E64, "enstrophy": W64, "kernels_ms": k64},
             "fp32_vs_fp64": err32, "fp32_mfma_dft_vs_fp64": errm}
 
@@ -495,7 +509,7 @@ def main(argv=None):
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
                 "traffic": None if tr is None else round(tr / 1e9, 3), "traffic_unit": "GB per launch",
-                "bytes_per_launch": FIELDS_PER_LAUNCH[dom] * C,
+                "bytes_per_launch": fields_per_launch(a.N)[dom] * C,
                 "mean_launch_ms": f64["kernels_ms"][dom]}
     ens = None if a.no_ensemble else run_ensemble(a.ens_steps, a.warmup, a.ens_per_sim_steps, not a.ens_default_tiles)
     iso = None if a.no_isotropic else run_isotropic(steps=a.iso_steps)

@@ -84,6 +84,18 @@ template <typename R, int N> struct Lay {
     }
 };
 
+// Element `at` (element offset) of the field starting at F.  Where a field
+// spans less than 4 GiB the byte offset is formed in 32 bits, so a uniform
+// field base plus one 32-bit per-thread register addresses it (no 64-bit
+// address per element); larger fields index in 64 bits.
+template <typename R, int N, typename P> __device__ __forceinline__ P* field_el(P* F, unsigned at) {
+    if constexpr (Lay<R, N>::FS * sizeof(cx<R>) < (size_t(1) << 32))
+        return reinterpret_cast<P*>(reinterpret_cast<char*>(const_cast<void*>(static_cast<const void*>(F))) +
+                                    (size_t)(at * (unsigned)sizeof(cx<R>)));
+    else
+        return F + at;
+}
+
 // Elements per thread of the y-pass line transforms.  Lines of 1024 take
 // 16 (FP64) or 32 (FP32) complex values per thread, so that a workgroup of
 // 128-byte row segments (8 FP64 or 16 FP32 columns) has 512 threads, each
@@ -93,6 +105,15 @@ template <typename R> constexpr int y_elems(int N) { return N >= 1024 ? (sizeof(
 // shared memory at every stage (kept in registers they would crowd out the
 // line).
 template <typename R> constexpr bool y_twiddles_in_lds(int N) { return y_elems<R>(N) > 8; }
+
+// Where the vorticity combinations i (ky w - kz v), i (kz u - kx w),
+// i (kx v - ky u) are formed.  With 8 elements per y-line thread the inverse
+// y pass forms them as it loads (the x pass writes U, V, W, F(kx v_hat) and
+// F(kx w_hat): five fields instead of six, 8 of 180 fields per step less);
+// with longer y slices (N = 1024) three live lines per thread would spill,
+// so there the x pass writes the six fields u, v, w, omega and the y pass
+// transforms them as they are.
+template <typename R> constexpr bool curl_in_y(int N) { return y_elems<R>(N) == 8; }
 
 // Elements per thread of the x-pass line transforms.  8 for every size: the
 // fused stage kernel holds three lines per thread, and 16 per thread (which

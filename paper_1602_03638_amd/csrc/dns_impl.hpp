@@ -37,7 +37,8 @@ template <typename R, int N> struct Impl {
     static constexpr int GY = N / y_elems<R>(N);   // threads per y line
     template <int T> static constexpr bool y_ok() {
         return T <= N / 2 && GY * T <= 1024 &&
-               ((size_t)T * N + (y_twiddles_in_lds<R>(N) ? (size_t)tw_size(N) : 0)) * CB <= LDS_LIMIT;
+               ((size_t)T * N + (y_twiddles_in_lds<R>(N) || curl_in_y<R>(N) ? (size_t)tw_size(N) : 0)) * CB <=
+                   LDS_LIMIT;
     }
     // z shapes: at least 16 threads, and up to 128 threads for small N
     template <int L> static constexpr bool z_ok() {
@@ -62,8 +63,14 @@ template <typename R, int N> struct Impl {
                                (C*)W, (const C*)tw, (const C*)roots, (const C*)tw2, b.wst);
         }
     }
+    // inverse y pass of a stage: the six fields for the z pass, with the
+    // vorticity combinations formed from the x pass's five outputs
     template <int T> static void yinv6(void* W, const void* tw, const Batch& b, hipStream_t s) {
-        ypass<T, +1, 6>(W, tw, b, s);
+        if constexpr (curl_in_y<R>(N))
+            hipLaunchKernelGGL((k_yinv_curl<R, N, T>), dim3(y_tiles<R, N, T>(), b.members), dim3(GY * T), 0, s,
+                               (C*)W, (const C*)tw, b.wst);
+        else
+            ypass<T, +1, 6>(W, tw, b, s);
     }
     template <int T> static void yfwd3(void* W, const void* tw, const Batch& b, hipStream_t s) {
         ypass<T, -1, 3>(W, tw, b, s);

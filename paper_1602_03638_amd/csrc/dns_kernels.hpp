@@ -87,17 +87,79 @@ static_assert(Lay<double, 1024>::FS < (size_t(1) << 32) && Lay<float, 1024>::FS 
 template <int N, int T> constexpr int x_main_tiles() { return (N * (N / 2)) / T; }
 
 // ---------------------------------------------------------------------------
-// Pass 1: inverse x transform of u_hat (3 fields at U) and of the vorticity
-// omega_hat = i k x u_hat (Sec. 3.1 Curl listing):
+// Pass 1: inverse x transforms for the vorticity omega_hat = i k x u_hat
+// (Sec. 3.1 Curl listing):
 //   omega_x = i (ky w - kz v), omega_y = i (kz u - kx w), omega_z = i (kx v - ky u).
 // ky and kz are constant along an x line, so by linearity only kx v_hat and
-// kx w_hat need transforms of their own:
-//   F(omega_x) = i (ky W - kz V),  F(omega_y) = i (kz U - F(kx w_hat)),
-//   F(omega_z) = i (F(kx v_hat) - ky U)          (F = inverse x transform)
-// Five transforms instead of six, and at most three lines per thread live at
-// once.  Output fields at W: u, v, w, omega_x, omega_y, omega_z.
+// kx w_hat need transforms of their own.  Output fields at W (F = inverse x
+// transform), see curl_in_y:
+//   curl_in_y:  U, V, W, F(kx v_hat), F(kx w_hat); the inverse y pass
+//               (k_yinv_curl) forms the combinations with ky and kz;
+//   otherwise:  U, V, W, omega_x = i (ky W - kz V),
+//               omega_y = i (kz U - F(kx w_hat)), omega_z = i (F(kx v_hat) - ky U).
 // T lines (consecutive columns) per workgroup.
 // ---------------------------------------------------------------------------
+// Five inverse x transforms of the velocity held in v[3] (x-spectral), written
+// to W as above.  Shared by the first stage's pass and the fused stage pass.
+template <typename R, int N, int T, bool NYQ>
+__device__ __forceinline__ void xinv_curl_store(cx<R> (&v)[3][x_elems<R>(N)],
+                                                cx<R>* __restrict__ W, const XAddr<R, N, NYQ>& A, cx<R>* lt,
+                                                const cx<R>* twl, int g, int iky, int ikz) {
+    constexpr int E = x_elems<R>(N), G = N / E;
+    constexpr size_t FS = Lay<R, N>::FS;
+    if constexpr (!curl_in_y<R>(N)) {
+        // the six fields u, v, w, omega (combinations formed here)
+        const R ky = (R)iky, kz = (R)ikz;
+        cx<R> b[E];
+        fft_line<R, N, E, +1, true>(v[0], lt, T, twl, g);        // U
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            A(W, m) = v[0][m];
+            b[m] = cscale<R>(v[1][m], (R)kfreq(g + m * G, N));
+        }
+        fft_line<R, N, E, +1, true>(b, lt, T, twl, g);           // F(kx v_hat)
+#pragma unroll
+        for (int m = 0; m < E; ++m) A(W + 5 * FS, m) = cmuli<R>(csub<R>(b[m], cscale<R>(v[0][m], ky)));
+        fft_line<R, N, E, +1, true>(v[1], lt, T, twl, g);        // V
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            A(W + FS, m) = v[1][m];
+            b[m] = cscale<R>(v[2][m], (R)kfreq(g + m * G, N));
+        }
+        fft_line<R, N, E, +1, true>(b, lt, T, twl, g);           // F(kx w_hat)
+#pragma unroll
+        for (int m = 0; m < E; ++m) A(W + 4 * FS, m) = cmuli<R>(csub<R>(cscale<R>(v[0][m], kz), b[m]));
+        fft_line<R, N, E, +1, true>(v[2], lt, T, twl, g);        // W
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            A(W + 2 * FS, m) = v[2][m];
+            A(W + 3 * FS, m) = cmuli<R>(csub<R>(cscale<R>(v[2][m], ky), cscale<R>(v[1][m], kz)));
+        }
+        return;
+    }
+    cx<R> b[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) b[m] = cscale<R>(v[1][m], (R)kfreq(g + m * G, N));
+    fft_line<R, N, E, +1, true>(v[0], lt, T, twl, g);            // U
+#pragma unroll
+    for (int m = 0; m < E; ++m) A(W, m) = v[0][m];
+    fft_line<R, N, E, +1, true>(b, lt, T, twl, g);               // F(kx v_hat)
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        A(W + 3 * FS, m) = b[m];
+        b[m] = cscale<R>(v[2][m], (R)kfreq(g + m * G, N));
+    }
+    fft_line<R, N, E, +1, true>(v[1], lt, T, twl, g);            // V
+#pragma unroll
+    for (int m = 0; m < E; ++m) A(W + FS, m) = v[1][m];
+    fft_line<R, N, E, +1, true>(b, lt, T, twl, g);               // F(kx w_hat)
+#pragma unroll
+    for (int m = 0; m < E; ++m) A(W + 4 * FS, m) = b[m];
+    fft_line<R, N, E, +1, true>(v[2], lt, T, twl, g);            // W
+#pragma unroll
+    for (int m = 0; m < E; ++m) A(W + 2 * FS, m) = v[2][m];
+}
+
 template <typename R, int N, int T, bool NYQ>
 __device__ __forceinline__ void xinv_curl_tile(const cx<R>* __restrict__ U, cx<R>* __restrict__ W,
                                                cx<R>* lds, const cx<R>* twl) {
@@ -105,49 +167,13 @@ __device__ __forceinline__ void xinv_curl_tile(const cx<R>* __restrict__ U, cx<R
     constexpr size_t FS = Lay<R, N>::FS;
     const int t = threadIdx.x % T, g = threadIdx.x / T;
     const XCol<R, N, NYQ> col(blockIdx.x * T + t);
-    const R ky = (R)col.ky, kz = (R)col.kz;
-    cx<R>* lt = lds + t;
     const XAddr<R, N, NYQ> A(col, g);
-
-    // Loads are issued as early as the register budget allows so that their
-    // latency overlaps the transforms (a barrier inside a transform keeps
-    // later loads from being hoisted by the compiler).
-    cx<R> a[E], b[E], c[E];
+    cx<R> v[3][E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        c[m] = A(U, m);                 // u_hat
-        a[m] = A(U + FS, m);            // v_hat
-    }
-    fft_line<R, N, E, +1, true>(c, lt, T, twl, g);          // c = U
+    for (int f = 0; f < 3; ++f)
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        A(W, m) = c[m];
-        b[m] = cscale<R>(a[m], (R)kfreq(g + m * G, N));
-    }
-    fft_line<R, N, E, +1, true>(b, lt, T, twl, g);          // b = F(kx v_hat)
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        A(W + 5 * FS, m) = cmuli<R>(csub<R>(b[m], cscale<R>(c[m], ky)));   // omega_z
-        b[m] = A(U + 2 * FS, m);        // w_hat, in flight during the next transform
-    }
-    fft_line<R, N, E, +1, true>(a, lt, T, twl, g);          // a = V
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        A(W + FS, m) = a[m];
-        b[m] = cscale<R>(b[m], (R)kfreq(g + m * G, N));
-    }
-    fft_line<R, N, E, +1, true>(b, lt, T, twl, g);          // b = F(kx w_hat)
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        A(W + 4 * FS, m) = cmuli<R>(csub<R>(cscale<R>(c[m], kz), b[m]));   // omega_y
-        c[m] = A(U + 2 * FS, m);        // w_hat again (recently read: cache hit)
-    }
-    fft_line<R, N, E, +1, true>(c, lt, T, twl, g);          // c = W
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        A(W + 2 * FS, m) = c[m];
-        A(W + 3 * FS, m) = cmuli<R>(csub<R>(cscale<R>(c[m], ky), cscale<R>(a[m], kz)));   // omega_x
-    }
+        for (int m = 0; m < E; ++m) v[f][m] = A(U + f * FS, m);
+    xinv_curl_store<R, N, T, NYQ>(v, W, A, lds + t, twl, g, col.ky, col.kz);
 }
 
 template <typename R, int N, int T>
@@ -202,39 +228,115 @@ void k_xplain(const cx<R>* __restrict__ S, cx<R>* __restrict__ D, const cx<R>* _
 // consecutive ix, whose lines are contiguous; thread (l, g) holds elements
 // g + m G of line l, so consecutive threads read consecutive elements.
 // ---------------------------------------------------------------------------
+// Tile geometry of the y pass: the row offset of element m of this thread's
+// line, the line's place in shared memory, and the kz of the line.
+template <typename R, int N, int T, bool NYQ> struct YTile {
+    using L = Lay<R, N>;
+    static constexpr int E = y_elems<R>(N), G = N / E;
+    static constexpr int ZT = (N / 2) / T;                 // main tiles per ix
+    static constexpr unsigned RS = NYQ ? 1u : L::ZP;      // offset between rows iy
+    static constexpr int PS = NYQ ? 1 : T;                 // shared-memory stride of a line
+    int g, lo, kz;
+    unsigned base;
+    __device__ __forceinline__ explicit YTile(int tile) {
+        if constexpr (NYQ) {
+            g = threadIdx.x % G;
+            const int l = threadIdx.x / G;
+            base = (unsigned)L::MAIN + (unsigned)(tile * T + l) * N;
+            lo = l * N;
+            kz = N / 2;
+        } else {
+            const int t = threadIdx.x % T;
+            g = threadIdx.x / T;
+            kz = (tile % ZT) * T + t;
+            base = (unsigned)(tile / ZT) * L::XP + (unsigned)kz;
+            lo = t;
+        }
+    }
+    __device__ __forceinline__ unsigned at(int m) const { return base + (unsigned)(g + m * G) * RS; }
+    // element m of the line in the field starting at F
+    template <typename P> __device__ __forceinline__ P* el(P* F, int m) const { return field_el<R, N>(F, at(m)); }
+};
+
 template <typename R, int N, int T, int DIR, int NF, bool NYQ>
 __device__ __forceinline__ void yline_tile(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, cx<R>* lds,
                                            int tile) {
-    constexpr bool TWL = y_twiddles_in_lds<R>(N);
-    constexpr int E = y_elems<R>(N), G = N / E;
+    using Y = YTile<R, N, T, NYQ>;
+    constexpr int E = Y::E;
     constexpr size_t FS = Lay<R, N>::FS;
-    constexpr int ZT = (N / 2) / T;          // main tiles per ix
-    using L = Lay<R, N>;
-    constexpr unsigned rs = NYQ ? 1u : L::ZP;
-    constexpr int ps = NYQ ? 1 : T;
-    int g, lo;
-    unsigned base;
-    if constexpr (NYQ) {
-        g = threadIdx.x % G;
-        const int l = threadIdx.x / G;
-        base = (unsigned)L::MAIN + (unsigned)(tile * T + l) * N;
-        lo = l * N;
-    } else {
-        const int t = threadIdx.x % T;
-        g = threadIdx.x / T;
-        base = (unsigned)(tile / ZT) * L::XP + (unsigned)((tile % ZT) * T + t);
-        lo = t;
-    }
+    constexpr bool TWL = y_twiddles_in_lds<R>(N);
+    const Y y(tile);
 #pragma unroll 1
     for (int f = 0; f < NF; ++f) {
         cx<R>* F = W + f * FS;
         cx<R> a[E];
 #pragma unroll
-        for (int m = 0; m < E; ++m) a[m] = F[base + (unsigned)(g + m * G) * rs];
-        fft_line<R, N, E, DIR, TWL>(a, lds + lo, ps, tw, g);
+        for (int m = 0; m < E; ++m) a[m] = *y.el(F, m);
+        fft_line<R, N, E, DIR, TWL>(a, lds + y.lo, Y::PS, tw, y.g);
 #pragma unroll
-        for (int m = 0; m < E; ++m) F[base + (unsigned)(g + m * G) * rs] = a[m];
+        for (int m = 0; m < E; ++m) *y.el(F, m) = a[m];
     }
+}
+
+// Inverse y transforms of the six fields the z pass needs (u, v, w and
+// omega = i k x u_hat, Sec. 3.1 Curl listing), formed from the five the
+// x pass writes: U, V, W, F(kx v_hat), F(kx w_hat) (x already inverse
+// transformed).  ky varies along the line and kz is the line's, so
+//   omega_x = i (ky W - kz V),  omega_y = i (kz U - F(kx w_hat)),
+//   omega_z = i (F(kx v_hat) - ky U)
+// are combined before the (linear) transform.  Outputs overwrite inputs that
+// are no longer needed: omega_z -> field 5, omega_y -> 4, u -> 0,
+// omega_x -> 3, v -> 1, w -> 2 (each thread reads and writes only its own
+// elements).
+template <typename R, int N, int T, bool NYQ>
+__device__ __forceinline__ void yinv_curl_tile(cx<R>* __restrict__ W, const cx<R>* twl, cx<R>* lds, int tile) {
+    using Y = YTile<R, N, T, NYQ>;
+    constexpr int E = Y::E, G = Y::G;
+    constexpr size_t FS = Lay<R, N>::FS;
+    constexpr bool TWL = true;          // twiddles from shared memory: three lines live
+    const cx<R>* tw = twl;
+    const Y y(tile);
+    const R kz = (R)y.kz;
+    cx<R>* lt = lds + y.lo;
+    cx<R> *F1 = W + FS, *F2 = W + 2 * FS, *F3 = W + 3 * FS, *F4 = W + 4 * FS, *F5 = W + 5 * FS;
+    cx<R> u[E], a[E], b[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        u[m] = *y.el(W, m);
+        a[m] = *y.el(F3, m);
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) a[m] = cmuli<R>(csub<R>(a[m], cscale<R>(u[m], (R)kfreq(y.g + m * G, N))));
+    fft_line<R, N, E, +1, TWL>(a, lt, Y::PS, tw, y.g);                    // omega_z
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        *y.el(F5, m) = a[m];
+        a[m] = *y.el(F4, m);
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) a[m] = cmuli<R>(csub<R>(cscale<R>(u[m], kz), a[m]));
+    fft_line<R, N, E, +1, TWL>(a, lt, Y::PS, tw, y.g);                    // omega_y
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        *y.el(F4, m) = a[m];
+        a[m] = *y.el(F1, m);
+        b[m] = *y.el(F2, m);
+    }
+    fft_line<R, N, E, +1, TWL>(u, lt, Y::PS, tw, y.g);                    // u
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        *y.el(W, m) = u[m];
+        u[m] = cmuli<R>(csub<R>(cscale<R>(b[m], (R)kfreq(y.g + m * G, N)), cscale<R>(a[m], kz)));
+    }
+    fft_line<R, N, E, +1, TWL>(u, lt, Y::PS, tw, y.g);                    // omega_x
+#pragma unroll
+    for (int m = 0; m < E; ++m) *y.el(F3, m) = u[m];
+    fft_line<R, N, E, +1, TWL>(a, lt, Y::PS, tw, y.g);                    // v
+#pragma unroll
+    for (int m = 0; m < E; ++m) *y.el(F1, m) = a[m];
+    fft_line<R, N, E, +1, TWL>(b, lt, Y::PS, tw, y.g);                    // w
+#pragma unroll
+    for (int m = 0; m < E; ++m) *y.el(F2, m) = b[m];
 }
 
 template <typename R, int N, int T> constexpr int y_main_tiles() { return N * ((N / 2) / T); }
@@ -255,6 +357,18 @@ void k_yline(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
     const int b = blockIdx.x;
     if (b < y_main_tiles<R, N, T>()) yline_tile<R, N, T, DIR, NF, false>(W, t, lds, b);
     else yline_tile<R, N, T, DIR, NF, true>(W, t, lds, b - y_main_tiles<R, N, T>());
+}
+
+template <typename R, int N, int T>
+__global__ __launch_bounds__(N / y_elems<R>(N) * T)
+void k_yinv_curl(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
+    W += blockIdx.y * wst;
+    __shared__ cx<R> lds[T * N];
+    __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
+    load_twiddles<R, N>(twl, tw);
+    const int b = blockIdx.x;
+    if (b < y_main_tiles<R, N, T>()) yinv_curl_tile<R, N, T, false>(W, twl, lds, b);
+    else yinv_curl_tile<R, N, T, true>(W, twl, lds, b - y_main_tiles<R, N, T>());
 }
 
 // Load element k (0 <= k < N) of the Hermitian extension of a half-spectrum
@@ -765,11 +879,11 @@ void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restri
 // ---------------------------------------------------------------------------
 // Pass 5 fused with pass 1 of the next stage: after the RK4 update of stage
 // s the tile's next-stage velocity (Us for s < 3, the new U0 for s = 3) is
-// still in registers, so its curl and inverse x transforms are formed right
-// away (same five transforms and combinations as k_xinv_curl, hence the same
-// bits) and the next stage does not read it back from memory.  W fields 0..2
-// are read (N_hat) before fields 0..5 are written; a workgroup owns its
-// columns, so this is safe in place.
+// still in registers, so its five inverse x transforms (xinv_curl_store,
+// as in k_xinv_curl, hence the same bits) are formed right away and the next
+// stage does not read it back from memory.  W fields 0..2 are read (N_hat)
+// before fields 0..4 are written; a workgroup owns its columns, so this is
+// safe in place.
 // ---------------------------------------------------------------------------
 template <typename R, int N, int T, int STAGE, bool NYQ>
 __device__ __forceinline__ void xstage_tile(cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
@@ -794,33 +908,8 @@ __device__ __forceinline__ void xstage_tile(cx<R>* __restrict__ W, cx<R>* __rest
     rk_apply_stage<R, N, E, STAGE, NYQ, NT>(u, col, g, U0, U1, Us, sa, e_acc, w_acc);
     if (STAGE >= 3 && sa.diag) diag_reduce<NT>(red, e_acc, w_acc, sa.diag);
 
-    // curl and inverse x transforms of the next stage's velocity u
-    const R ky = (R)col.ky, kz = (R)col.kz;
-    cx<R> b[E];
-    fft_line<R, N, E, +1, true>(u[0], lt, T, twl, g);          // U
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        A(W, m) = u[0][m];
-        b[m] = cscale<R>(u[1][m], (R)kfreq(g + m * G, N));
-    }
-    fft_line<R, N, E, +1, true>(b, lt, T, twl, g);             // F(kx v_hat)
-#pragma unroll
-    for (int m = 0; m < E; ++m) A(W + 5 * FS, m) = cmuli<R>(csub<R>(b[m], cscale<R>(u[0][m], ky)));
-    fft_line<R, N, E, +1, true>(u[1], lt, T, twl, g);          // V
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        A(W + FS, m) = u[1][m];
-        b[m] = cscale<R>(u[2][m], (R)kfreq(g + m * G, N));
-    }
-    fft_line<R, N, E, +1, true>(b, lt, T, twl, g);             // F(kx w_hat)
-#pragma unroll
-    for (int m = 0; m < E; ++m) A(W + 4 * FS, m) = cmuli<R>(csub<R>(cscale<R>(u[0][m], kz), b[m]));
-    fft_line<R, N, E, +1, true>(u[2], lt, T, twl, g);          // W
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        A(W + 2 * FS, m) = u[2][m];
-        A(W + 3 * FS, m) = cmuli<R>(csub<R>(cscale<R>(u[2][m], ky), cscale<R>(u[1][m], kz)));
-    }
+    // inverse x transforms for the next stage's velocity and vorticity
+    xinv_curl_store<R, N, T, NYQ>(u, W, A, lt, twl, g, col.ky, col.kz);
 }
 
 template <typename R, int N, int T, int STAGE>

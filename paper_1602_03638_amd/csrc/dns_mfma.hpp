@@ -16,6 +16,9 @@
 // Fl xh + Fh xl + Fh xh are accumulated in FP32 (the Fl xl term, 2^-22
 // relative, is dropped).  The remaining stages run in FP32 as in the plain
 // y pass.  Lines of the kz = N/2 plane take the plain FP32 y transform.
+// Where the y pass forms the vorticity combinations (curl_in_y), the inverse
+// pass of a stage (CURL) forms those of k_yinv_curl as it stages each
+// output's tile, in the same field order.
 #pragma once
 
 #include "dns_kernels.hpp"
@@ -53,7 +56,50 @@ __device__ __forceinline__ void split_half(float v, _Float16& hi, _Float16& lo) 
     lo = (_Float16)(v - (float)hi);
 }
 
-template <int N, int DIR, int NF>
+// Step 1 of the matrix-core y pass: stage one output field's tile in shared
+// memory (row iy, column t) and return this thread's largest magnitude.
+// KIND 0 stages field P as it is; KIND 3, 4, 5 form the vorticity
+// combinations of k_yinv_curl from fields P and Q (ky per row, kz per column):
+//   5: i (P - ky Q), P = F(kx v_hat), Q = U
+//   4: i (kz P - Q), P = U, Q = F(kx w_hat)
+//   3: i (ky P - kz Q), P = W, Q = V
+// A thread's rows are loaded in batches of up to 16 loads in flight.
+template <int N, int KIND>
+__device__ __forceinline__ float stage_tile(const cx<float>* __restrict__ P, const cx<float>* __restrict__ Q,
+                                            cx<float>* xs, unsigned base, int th, int t, float kz) {
+    using L = Lay<float, N>;
+    constexpr int RPT = MfmaY<N>::RPT;
+    constexpr int BMAX = KIND == 0 ? 16 : 8;   // rows in flight (two loads each when combining)
+    constexpr int ROWS = N / RPT, B = ROWS < BMAX ? ROWS : BMAX;
+    float amax = 0.f;
+#pragma unroll 1
+    for (int c0 = 0; c0 < ROWS; c0 += B) {
+        cx<float> v[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const int r = th / MFMA_T + RPT * (c0 + j);
+            const unsigned at = base + (unsigned)r * L::ZP + (unsigned)t;
+            const float ky = (float)kfreq(r, N);
+            const cx<float> p = *field_el<float, N>(P, at);
+            if constexpr (KIND == 0) {
+                v[j] = p;
+            } else {
+                const cx<float> q = *field_el<float, N>(Q, at);
+                if constexpr (KIND == 5) v[j] = cmuli<float>(csub<float>(p, cscale<float>(q, ky)));
+                else if constexpr (KIND == 4) v[j] = cmuli<float>(csub<float>(cscale<float>(p, kz), q));
+                else v[j] = cmuli<float>(csub<float>(cscale<float>(p, ky), cscale<float>(q, kz)));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            amax = fmaxf(amax, fmaxf(fabsf(v[j].x), fabsf(v[j].y)));
+            xs[(th / MFMA_T + RPT * (c0 + j)) * MFMA_LP + t] = v[j];
+        }
+    }
+    return amax;
+}
+
+template <int N, int DIR, int NF, bool CURL>
 __device__ __forceinline__ void ymfma_tile(cx<float>* __restrict__ W, const cx<float>* __restrict__ roots,
                                            const cx<float>* tw2l, cx<float>* xs, float* red, int tile) {
     using L = Lay<float, N>;
@@ -86,23 +132,24 @@ __device__ __forceinline__ void ymfma_tile(cx<float>* __restrict__ W, const cx<f
         nfli[j] = -l;
     }
 
+    const float kz = (float)((tile % ZT) * MFMA_T + t);
 #pragma unroll 1
-    for (int f = 0; f < NF; ++f) {
+    for (int i = 0; i < NF; ++i) {
+        // CURL: outputs 5, 4, 0, 3, 1, 2 overwrite only inputs no longer
+        // needed (as in k_yinv_curl)
+        const int f = CURL ? (i == 0 ? 5 : i == 1 ? 4 : i == 2 ? 0 : i == 3 ? 3 : i == 4 ? 1 : 2) : i;
         cx<float>* F = W + f * FS;
-        // 1. tile -> LDS (row iy, column t), and the largest magnitude; the
-        // rows of a thread are loaded in batches of up to 16 in flight
-        float amax = 0.f;
-        constexpr int ROWS = N / RPT, B = ROWS < 16 ? ROWS : 16;
-#pragma unroll 1
-        for (int c0 = 0; c0 < ROWS; c0 += B) {
-            cx<float> v[B];
-#pragma unroll
-            for (int j = 0; j < B; ++j) v[j] = F[base + (unsigned)(th / MFMA_T + RPT * (c0 + j)) * L::ZP + (unsigned)t];
-#pragma unroll
-            for (int j = 0; j < B; ++j) {
-                amax = fmaxf(amax, fmaxf(fabsf(v[j].x), fabsf(v[j].y)));
-                xs[(th / MFMA_T + RPT * (c0 + j)) * MFMA_LP + t] = v[j];
+        // 1. tile -> LDS (row iy, column t), and the largest magnitude
+        float amax;
+        if constexpr (CURL) {
+            switch (f) {
+                case 5: amax = stage_tile<N, 5>(W + 3 * FS, W, xs, base, th, t, kz); break;
+                case 4: amax = stage_tile<N, 4>(W, W + 4 * FS, xs, base, th, t, kz); break;
+                case 3: amax = stage_tile<N, 3>(W + 2 * FS, W + FS, xs, base, th, t, kz); break;
+                default: amax = stage_tile<N, 0>(F, F, xs, base, th, t, kz); break;
             }
+        } else {
+            amax = stage_tile<N, 0>(F, F, xs, base, th, t, kz);
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
@@ -171,7 +218,7 @@ __device__ __forceinline__ void ymfma_tile(cx<float>* __restrict__ W, const cx<f
             fft_line<float, N2, E2, DIR, true>(v, sub, MFMA_LP, tw2l, g2);
 #pragma unroll
             for (int m = 0; m < E2; ++m)
-                F[base + (unsigned)(k1 + 16 * (g2 + m * G2)) * L::ZP + (unsigned)t] = v[m];
+                *field_el<float, N>(F, base + (unsigned)(k1 + 16 * (g2 + m * G2)) * L::ZP + (unsigned)t) = v[m];
             __syncthreads();
         }
     }
@@ -188,17 +235,19 @@ void k_yline_mfma(cx<float>* __restrict__ W, const cx<float>* __restrict__ tw, c
     __shared__ float red[M::WAVES];
     constexpr bool TWL = y_twiddles_in_lds<float>(N);
     __shared__ cx<float> twl[TWL ? tw_size(N) : 1];
+    constexpr bool CURL = curl_in_y<float>(N) && DIR > 0 && NF == 6;   // inverse pass of a stage
     const int b = blockIdx.x;
     if (b < M::MAIN_TILES) {
         load_twiddles<float, M::N2>(tw2l, tw2);
-        ymfma_tile<N, DIR, NF>(W, roots, tw2l, xs, red, b);
+        ymfma_tile<N, DIR, NF, CURL>(W, roots, tw2l, xs, red, b);
     } else {
         const cx<float>* t = tw;
         if constexpr (TWL) {
             load_twiddles<float, N>(twl, tw);
             t = twl;
         }
-        yline_tile<float, N, M::TN, DIR, NF, true>(W, t, xs, b - M::MAIN_TILES);
+        if constexpr (CURL) yinv_curl_tile<float, N, M::TN, true>(W, t, xs, b - M::MAIN_TILES);
+        else yline_tile<float, N, M::TN, DIR, NF, true>(W, t, xs, b - M::MAIN_TILES);
     }
 }
 
