@@ -78,9 +78,10 @@ def measured_traffic(N, dtype, kernel):
         return None
     real = "double" if dtype == "f64" else "float"
     name = {"xstage": "k_xstage", "xrhs_rk4": "k_xrhs", "xinv_curl": "k_xinv_curl", "zcross": "k_zcross",
-            "yinv6": "k_yline", "yfwd3": "k_yline"}[kernel]
+            "yinv6": "k_yinv_curl" if curl_in_y(N) else "k_yline", "yfwd3": "k_yline"}[kernel]
     vals = [v["traffic_bytes_calibrated"] for k, v in rec["kernels"].items()
-            if k.startswith(f"{name}<{real}, {N},") and (kernel != "yinv6" or k.endswith(", 1, 6>"))
+            if k.startswith(f"{name}<{real}, {N},")
+            and (kernel != "yinv6" or curl_in_y(N) or k.endswith(", 1, 6>"))
             and (kernel != "yfwd3" or k.endswith(", -1, 3>"))]
     return sum(vals) / len(vals) if vals else None
 

@@ -137,12 +137,15 @@ __device__ __forceinline__ void xinv_curl_store(cx<R> (&v)[3][x_elems<R>(N)],
         }
         return;
     }
+    // at most three lines live: U is transformed and stored before the
+    // first kx product is formed
     cx<R> b[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) b[m] = cscale<R>(v[1][m], (R)kfreq(g + m * G, N));
     fft_line<R, N, E, +1, true>(v[0], lt, T, twl, g);            // U
 #pragma unroll
-    for (int m = 0; m < E; ++m) A(W, m) = v[0][m];
+    for (int m = 0; m < E; ++m) {
+        A(W, m) = v[0][m];
+        b[m] = cscale<R>(v[1][m], (R)kfreq(g + m * G, N));
+    }
     fft_line<R, N, E, +1, true>(b, lt, T, twl, g);               // F(kx v_hat)
 #pragma unroll
     for (int m = 0; m < E; ++m) {
