@@ -5,10 +5,13 @@
 // One stage (Sec. 2 eq. NSfinal, Sec. 3.1 computeRHS) runs as five passes
 // over HBM-resident half-spectrum fields in the padded internal layout of
 // dns_common.hpp:
-//   1. k_xinv_curl u_hat -> 6 fields: inverse x FFT of u_hat and of
-//                  omega_hat = i k x u_hat formed on the fly
-//   2. k_yline     inverse y FFT of the 6 fields (in place; the last
-//                  workgroups take the kz = N/2 plane)
+//   1. k_xinv_curl u_hat -> inverse x FFTs of u_hat and of the kx products
+//                  that omega_hat = i k x u_hat needs (5 fields: U, V, W,
+//                  F(kx v_hat), F(kx w_hat); at N = 1024 the 6 fields
+//                  u, v, w, omega with the combinations formed here)
+//   2. k_yinv_curl forms omega_hat from the 5 fields, then the inverse y FFT
+//                  of all 6 (in place; the last workgroups take the
+//                  kz = N/2 plane); k_yline<+1, 6> at N = 1024
 //   3. k_zcross    per (x, y) line: 6 inverse real z FFTs, u x omega in
 //                  registers, 3 forward real z FFTs; physical fields never
 //                  leave the chip
