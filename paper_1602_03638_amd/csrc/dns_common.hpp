@@ -84,6 +84,48 @@ template <typename R, int N> struct Lay {
     }
 };
 
+// Global-memory access of one complex value, streaming (non-temporal) or
+// plain.  The stage passes read and write every value once; where that pays
+// (stream_io), their loads and stores are non-temporal.
+template <typename T, bool NT> __device__ __forceinline__ T gload(const T* p) {
+    if constexpr (NT) {
+        using S = decltype(p->x);
+        using V = S __attribute__((ext_vector_type(2)));
+        const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+        return T{v.x, v.y};
+    } else {
+        return *p;
+    }
+}
+template <typename T, bool NT> __device__ __forceinline__ void gstore(T* p, T a) {
+    if constexpr (NT) {
+        using S = decltype(p->x);
+        using V = S __attribute__((ext_vector_type(2)));
+        const V v = {a.x, a.y};
+        __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+    } else {
+        *p = a;
+    }
+}
+// Reference to one complex value in global memory: reads through gload,
+// assignments through gstore.
+template <typename T, bool NT> struct GRef {
+    T* p;
+    __device__ __forceinline__ operator T() const { return gload<T, NT>(p); }
+    __device__ __forceinline__ const GRef& operator=(const T& a) const { gstore<T, NT>(p, a); return *this; }
+};
+
+// Sizes whose stage passes use streaming accesses (measured on MI355X, same
+// build otherwise).  512^3: step 37.1 -> 35.8 ms (FP64), 19.0 -> 18.35 ms
+// (FP32); 256^3: 4.79 -> 4.40 ms (FP64), 2.43 -> 2.25 ms (FP32).  The plain
+// y-line kernel (forward y pass, standalone inverse) stays plain: streaming
+// loads measured 1.23 -> 1.44 ms per forward launch at 512^3 FP64.  1024^3: the x passes lost 18-22% (their 64-byte rows are
+// read in halves by neighbouring workgroups, which plain loads share through
+// L2) and the y passes up to 10%.  32^3 to 128^3 (the ensemble): the batched
+// step lost 12%; all fields of a 128^3 simulation (about 130 MB in FP32) fit
+// in the 256 MB last-level cache between passes.
+template <typename R> constexpr bool stream_io(int N) { return N == 256 || N == 512; }
+
 // Element `at` (element offset) of the field starting at F.  Where a field
 // spans less than 4 GiB the byte offset is formed in 32 bits, so a uniform
 // field base plus one 32-bit per-thread register addresses it (no 64-bit

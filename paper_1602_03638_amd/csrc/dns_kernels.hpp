@@ -72,11 +72,12 @@ struct XAddr {
     unsigned tb;                                                  // byte offset of (column, row g)
     __device__ __forceinline__ XAddr(const XCol<R, N, NYQ>& col, int g)
         : tb(((unsigned)(col.base - BLOCK) + (unsigned)g * RS) * (unsigned)sizeof(C)) {}
-    __device__ __forceinline__ C& operator()(C* F, int m) const {
-        return *reinterpret_cast<C*>(reinterpret_cast<char*>(F + BLOCK + (size_t)m * G * RS) + tb);
+    static constexpr bool S = stream_io<R>(N);
+    __device__ __forceinline__ GRef<C, S> operator()(C* F, int m) const {
+        return {reinterpret_cast<C*>(reinterpret_cast<char*>(F + BLOCK + (size_t)m * G * RS) + tb)};
     }
-    __device__ __forceinline__ const C& operator()(const C* F, int m) const {
-        return *reinterpret_cast<const C*>(reinterpret_cast<const char*>(F + BLOCK + (size_t)m * G * RS) + tb);
+    __device__ __forceinline__ C operator()(const C* F, int m) const {
+        return gload<C, S>(reinterpret_cast<const C*>(reinterpret_cast<const char*>(F + BLOCK + (size_t)m * G * RS) + tb));
     }
 };
 
@@ -261,7 +262,8 @@ template <typename R, int N, int T, bool NYQ> struct YTile {
     }
     __device__ __forceinline__ unsigned at(int m) const { return base + (unsigned)(g + m * G) * RS; }
     // element m of the line in the field starting at F
-    template <typename P> __device__ __forceinline__ P* el(P* F, int m) const { return field_el<R, N>(F, at(m)); }
+    template <bool NT = stream_io<R>(N)>
+    __device__ __forceinline__ GRef<cx<R>, NT> el(cx<R>* F, int m) const { return {field_el<R, N>(F, at(m))}; }
 };
 
 template <typename R, int N, int T, int DIR, int NF, bool NYQ>
@@ -271,16 +273,20 @@ __device__ __forceinline__ void yline_tile(cx<R>* __restrict__ W, const cx<R>* _
     constexpr int E = Y::E;
     constexpr size_t FS = Lay<R, N>::FS;
     constexpr bool TWL = y_twiddles_in_lds<R>(N);
+    // plain accesses: the forward pass, and the inverse pass of the
+    // standalone transform (stage passes below 1024 use k_yinv_curl), whose
+    // 64-byte FP32 rows measured 763 -> 1079 us per 512^3 launch streaming
+    constexpr bool NT = false;
     const Y y(tile);
 #pragma unroll 1
     for (int f = 0; f < NF; ++f) {
         cx<R>* F = W + f * FS;
         cx<R> a[E];
 #pragma unroll
-        for (int m = 0; m < E; ++m) a[m] = *y.el(F, m);
+        for (int m = 0; m < E; ++m) a[m] = y.template el<NT>(F, m);
         fft_line<R, N, E, DIR, TWL>(a, lds + y.lo, Y::PS, tw, y.g);
 #pragma unroll
-        for (int m = 0; m < E; ++m) *y.el(F, m) = a[m];
+        for (int m = 0; m < E; ++m) y.template el<NT>(F, m) = a[m];
     }
 }
 
@@ -308,41 +314,41 @@ __device__ __forceinline__ void yinv_curl_tile(cx<R>* __restrict__ W, const cx<R
     cx<R> u[E], a[E], b[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        u[m] = *y.el(W, m);
-        a[m] = *y.el(F3, m);
+        u[m] = y.el(W, m);
+        a[m] = y.el(F3, m);
     }
 #pragma unroll
     for (int m = 0; m < E; ++m) a[m] = cmuli<R>(csub<R>(a[m], cscale<R>(u[m], (R)kfreq(y.g + m * G, N))));
     fft_line<R, N, E, +1, TWL>(a, lt, Y::PS, tw, y.g);                    // omega_z
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        *y.el(F5, m) = a[m];
-        a[m] = *y.el(F4, m);
+        y.el(F5, m) = a[m];
+        a[m] = y.el(F4, m);
     }
 #pragma unroll
     for (int m = 0; m < E; ++m) a[m] = cmuli<R>(csub<R>(cscale<R>(u[m], kz), a[m]));
     fft_line<R, N, E, +1, TWL>(a, lt, Y::PS, tw, y.g);                    // omega_y
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        *y.el(F4, m) = a[m];
-        a[m] = *y.el(F1, m);
-        b[m] = *y.el(F2, m);
+        y.el(F4, m) = a[m];
+        a[m] = y.el(F1, m);
+        b[m] = y.el(F2, m);
     }
     fft_line<R, N, E, +1, TWL>(u, lt, Y::PS, tw, y.g);                    // u
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        *y.el(W, m) = u[m];
+        y.el(W, m) = u[m];
         u[m] = cmuli<R>(csub<R>(cscale<R>(b[m], (R)kfreq(y.g + m * G, N)), cscale<R>(a[m], kz)));
     }
     fft_line<R, N, E, +1, TWL>(u, lt, Y::PS, tw, y.g);                    // omega_x
 #pragma unroll
-    for (int m = 0; m < E; ++m) *y.el(F3, m) = u[m];
+    for (int m = 0; m < E; ++m) y.el(F3, m) = u[m];
     fft_line<R, N, E, +1, TWL>(a, lt, Y::PS, tw, y.g);                    // v
 #pragma unroll
-    for (int m = 0; m < E; ++m) *y.el(F1, m) = a[m];
+    for (int m = 0; m < E; ++m) y.el(F1, m) = a[m];
     fft_line<R, N, E, +1, TWL>(b, lt, Y::PS, tw, y.g);                    // w
 #pragma unroll
-    for (int m = 0; m < E; ++m) *y.el(F2, m) = b[m];
+    for (int m = 0; m < E; ++m) y.el(F2, m) = b[m];
 }
 
 template <typename R, int N, int T> constexpr int y_main_tiles() { return N * ((N / 2) / T); }
@@ -431,6 +437,7 @@ void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale, size
     constexpr int E = 8, G = N / E;
     constexpr size_t FS = Lay<R, N>::FS;
     constexpr int LP = padded_line<N>(true);
+    constexpr bool SIO = stream_io<R>(N);
     __shared__ cx<R> lds[L * LP];
     __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
     const int g = threadIdx.x % G, l = threadIdx.x / G;
@@ -450,12 +457,12 @@ void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale, size
         const cx<R>* FY = W + (2 * p + 1) * FS;
 #pragma unroll
         for (int m = 0; m < E / 2; ++m) {
-            xl[p][m] = FX[zr + g + m * G];
-            yl[p][m] = FY[zr + g + m * G];
+            xl[p][m] = gload<cx<R>, SIO>(FX + zr + g + m * G);
+            yl[p][m] = gload<cx<R>, SIO>(FY + zr + g + m * G);
         }
         if (g == 0) {
-            xn[p] = FX[NQ + line];
-            yn[p] = FY[NQ + line];
+            xn[p] = gload<cx<R>, SIO>(FX + NQ + line);
+            yn[p] = gload<cx<R>, SIO>(FY + NQ + line);
         }
     }
     load_twiddles<R, N>(twl, tw);
@@ -493,8 +500,8 @@ void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale, size
     fft_line<R, N, E, -1, true, true>(P, my, 1, twl, g);
     // c2: Q_k is its half spectrum directly
 #pragma unroll
-    for (int m = 0; m < E / 2; ++m) W[2 * FS + zr + g + m * G] = Q[m];
-    if (g == 0) W[2 * FS + NQ + line] = Q[E / 2];
+    for (int m = 0; m < E / 2; ++m) gstore<cx<R>, SIO>(W + 2 * FS + zr + g + m * G, Q[m]);
+    if (g == 0) gstore<cx<R>, SIO>(W + 2 * FS + NQ + line, Q[E / 2]);
     // c0, c1: unpack P through LDS (needs P_{N-k})
 #pragma unroll
     for (int m = 0; m < E; ++m) my[g + m * G] = P[m];
@@ -504,14 +511,14 @@ void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale, size
         const int k = g + m * G;
         cx<R> A, B;
         zsplit<R>(my[k], my[(N - k) & (N - 1)], A, B);
-        W[0 * FS + zr + k] = A;
-        W[1 * FS + zr + k] = B;
+        gstore<cx<R>, SIO>(W + zr + k, A);
+        gstore<cx<R>, SIO>(W + FS + zr + k, B);
     }
     if (g == 0) {
         cx<R> A, B;
         zsplit<R>(my[N / 2], my[N / 2], A, B);
-        W[0 * FS + NQ + line] = A;
-        W[1 * FS + NQ + line] = B;
+        gstore<cx<R>, SIO>(W + NQ + line, A);
+        gstore<cx<R>, SIO>(W + FS + NQ + line, B);
     }
 }
 

@@ -63,8 +63,9 @@ __device__ __forceinline__ void split_half(float v, _Float16& hi, _Float16& lo) 
 //   5: i (P - ky Q), P = F(kx v_hat), Q = U
 //   4: i (kz P - Q), P = U, Q = F(kx w_hat)
 //   3: i (ky P - kz Q), P = W, Q = V
-// A thread's rows are loaded in batches of up to 16 loads in flight.
-template <int N, int KIND>
+// A thread's rows are loaded in batches of up to 16 loads in flight;
+// STREAM selects streaming (non-temporal) loads.
+template <int N, int KIND, bool STREAM>
 __device__ __forceinline__ float stage_tile(const cx<float>* __restrict__ P, const cx<float>* __restrict__ Q,
                                             cx<float>* xs, unsigned base, int th, int t, float kz) {
     using L = Lay<float, N>;
@@ -80,11 +81,11 @@ __device__ __forceinline__ float stage_tile(const cx<float>* __restrict__ P, con
             const int r = th / MFMA_T + RPT * (c0 + j);
             const unsigned at = base + (unsigned)r * L::ZP + (unsigned)t;
             const float ky = (float)kfreq(r, N);
-            const cx<float> p = *field_el<float, N>(P, at);
+            const cx<float> p = gload<cx<float>, STREAM>(field_el<float, N>(P, at));
             if constexpr (KIND == 0) {
                 v[j] = p;
             } else {
-                const cx<float> q = *field_el<float, N>(Q, at);
+                const cx<float> q = gload<cx<float>, STREAM>(field_el<float, N>(Q, at));
                 if constexpr (KIND == 5) v[j] = cmuli<float>(csub<float>(p, cscale<float>(q, ky)));
                 else if constexpr (KIND == 4) v[j] = cmuli<float>(csub<float>(cscale<float>(p, kz), q));
                 else v[j] = cmuli<float>(csub<float>(cscale<float>(p, ky), cscale<float>(q, kz)));
@@ -110,6 +111,7 @@ __device__ __forceinline__ void ymfma_tile(cx<float>* __restrict__ W, const cx<f
     constexpr int NT = M::NT, WAVES = M::WAVES, RPT = M::RPT;
     const int th = threadIdx.x, lane = th & 63, wave = th >> 6;
     const int t = th % MFMA_T;
+    constexpr bool STREAM = DIR > 0 && stream_io<float>(N);   // as k_yline
     const unsigned base = (unsigned)(tile / ZT) * L::XP + (unsigned)((tile % ZT) * MFMA_T);
 
     // A operand: F16[k1 = lane % 16][n1 = 4 (lane / 16) + j], hi/lo parts,
@@ -143,13 +145,13 @@ __device__ __forceinline__ void ymfma_tile(cx<float>* __restrict__ W, const cx<f
         float amax;
         if constexpr (CURL) {
             switch (f) {
-                case 5: amax = stage_tile<N, 5>(W + 3 * FS, W, xs, base, th, t, kz); break;
-                case 4: amax = stage_tile<N, 4>(W, W + 4 * FS, xs, base, th, t, kz); break;
-                case 3: amax = stage_tile<N, 3>(W + 2 * FS, W + FS, xs, base, th, t, kz); break;
-                default: amax = stage_tile<N, 0>(F, F, xs, base, th, t, kz); break;
+                case 5: amax = stage_tile<N, 5, STREAM>(W + 3 * FS, W, xs, base, th, t, kz); break;
+                case 4: amax = stage_tile<N, 4, STREAM>(W, W + 4 * FS, xs, base, th, t, kz); break;
+                case 3: amax = stage_tile<N, 3, STREAM>(W + 2 * FS, W + FS, xs, base, th, t, kz); break;
+                default: amax = stage_tile<N, 0, STREAM>(F, F, xs, base, th, t, kz); break;
             }
         } else {
-            amax = stage_tile<N, 0>(F, F, xs, base, th, t, kz);
+            amax = stage_tile<N, 0, STREAM>(F, F, xs, base, th, t, kz);
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
@@ -218,7 +220,8 @@ __device__ __forceinline__ void ymfma_tile(cx<float>* __restrict__ W, const cx<f
             fft_line<float, N2, E2, DIR, true>(v, sub, MFMA_LP, tw2l, g2);
 #pragma unroll
             for (int m = 0; m < E2; ++m)
-                *field_el<float, N>(F, base + (unsigned)(k1 + 16 * (g2 + m * G2)) * L::ZP + (unsigned)t) = v[m];
+                gstore<cx<float>, STREAM>(
+                    field_el<float, N>(F, base + (unsigned)(k1 + 16 * (g2 + m * G2)) * L::ZP + (unsigned)t), v[m]);
             __syncthreads();
         }
     }
