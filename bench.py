@@ -476,8 +476,8 @@ def main(argv=None):
             sweep(a.N, dt)
         return 0
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the slab decomposition over several GPUs is described, not built)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(sharding the slab decomposition over several GPUs is designed, not built)", file=sys.stderr)
         return 2
 
     if a.tg_long:

@@ -56,7 +56,7 @@ typedef enum dns_status {
     DNS_E_HIP = -3,          /* a HIP runtime call or kernel launch failed */
     DNS_E_STATE = -4,        /* call not valid in the context's state (no velocity set) */
     DNS_E_NONFINITE = -5,    /* a diagnostic came out NaN or Inf */
-    DNS_E_UNSUPPORTED = -6   /* valid request this build does not provide */
+    DNS_E_UNSUPPORTED = -6   /* valid request the library does not provide */
 } dns_status;
 
 typedef enum dns_dtype { DNS_FP64 = 0, DNS_FP32 = 1 } dns_dtype;
