@@ -3,6 +3,8 @@
 // and the internal field layout.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
@@ -118,12 +120,13 @@ template <typename T, bool NT> struct GRef {
 // Sizes whose stage passes use streaming accesses (measured on MI355X, same
 // build otherwise).  512^3: step 37.1 -> 35.8 ms (FP64), 19.0 -> 18.35 ms
 // (FP32); 256^3: 4.79 -> 4.40 ms (FP64), 2.43 -> 2.25 ms (FP32).  The plain
-// y-line kernel (forward y pass, standalone inverse) stays plain: streaming
-// loads measured 1.23 -> 1.44 ms per forward launch at 512^3 FP64.  1024^3: the x passes lost 18-22% (their 64-byte rows are
-// read in halves by neighbouring workgroups, which plain loads share through
-// L2) and the y passes up to 10%.  32^3 to 128^3 (the ensemble): the batched
-// step lost 12%; all fields of a 128^3 simulation (about 130 MB in FP32) fit
-// in the 256 MB last-level cache between passes.
+// y-line kernel (forward y pass, standalone inverse) keeps plain accesses:
+// streaming loads measured 1.23 -> 1.44 ms per forward launch at 512^3 FP64.
+// 1024^3: the x passes lost 18-22% (their 64-byte rows are read in halves by
+// neighbouring workgroups, which plain loads share through L2) and the y
+// passes up to 10%.  32^3 to 128^3 (the ensemble): the batched step lost 12%;
+// all fields of a 128^3 simulation (about 130 MB in FP32) fit in the 256 MB
+// last-level cache between passes.
 template <typename R> constexpr bool stream_io(int N) { return N == 256 || N == 512; }
 
 // Element `at` (element offset) of the field starting at F.  Where a field
@@ -131,9 +134,9 @@ template <typename R> constexpr bool stream_io(int N) { return N == 256 || N == 
 // field base plus one 32-bit per-thread register addresses it (no 64-bit
 // address per element); larger fields index in 64 bits.
 template <typename R, int N, typename P> __device__ __forceinline__ P* field_el(P* F, unsigned at) {
+    using B = std::conditional_t<std::is_const_v<P>, const char, char>;
     if constexpr (Lay<R, N>::FS * sizeof(cx<R>) < (size_t(1) << 32))
-        return reinterpret_cast<P*>(reinterpret_cast<char*>(const_cast<void*>(static_cast<const void*>(F))) +
-                                    (size_t)(at * (unsigned)sizeof(cx<R>)));
+        return reinterpret_cast<P*>(reinterpret_cast<B*>(F) + (size_t)(at * (unsigned)sizeof(cx<R>)));
     else
         return F + at;
 }
