@@ -90,30 +90,71 @@ def test_mfma_unsupported_configurations():
 
 def test_mfma_512_against_fp64():
     """At 512^3 a thread's tile rows take several load batches in the stage
-    that forms the vorticity (at 64 and 128 one batch holds them all): two
-    RK4 steps of a seeded random isotropic field through the matrix-core y
-    passes against the FP64 path from the same spectrum (FP64 agrees with the
-    oracle to rounding in the parity tests): velocity to 1e-5 relative L2,
-    energy and enstrophy to 1e-6."""
+    that forms the vorticity (at 64 and 128 one batch holds them all). From a
+    seeded random isotropic field, against the FP64 path from the same
+    spectrum (FP64 agrees with the oracle to rounding in the parity tests):
+    the right-hand side to 2e-5 relative L2, and after two RK4 steps velocity
+    to 1e-5, energy and enstrophy to 1e-6."""
     note("mfma 512 vs fp64")
     import torch
     N, nu, dt = 512, 1e-3, 5e-4
     s = _solver(N, nu, dt, dtype="f64")
     s.init_random(7, k0=4.0, energy=0.5)
     uh0 = s.get_spectral().to(torch.complex64).contiguous()
+    # the FP64 reference starts from the FP32-rounded spectrum as well
+    s.set_spectral(uh0.to(torch.complex128).contiguous())
+    r64 = s.rhs()
     s.step(2)
     E64, W64 = s.diagnostics()
     ref = s.get_spectral()
     s.close()
     torch.cuda.empty_cache()
-    s = _solver(N, nu, dt, mfma_dft=True).set_spectral(uh0).step(2)
+    s = _solver(N, nu, dt, mfma_dft=True).set_spectral(uh0)
+    r32 = s.rhs()
+    s.step(2)
     E, W = s.diagnostics()
     got = s.get_spectral()
     s.close()
     del uh0
+    err_rhs = float(torch.linalg.vector_norm(r32.to(torch.complex128) - r64) / torch.linalg.vector_norm(r64))
     err = float(torch.linalg.vector_norm(got.to(torch.complex128) - ref) / torch.linalg.vector_norm(ref))
-    del got, ref
+    del got, ref, r32, r64
     torch.cuda.empty_cache()
-    note(f"  rel L2 {err:.2e}, energy {abs(E - E64) / E64:.2e}, enstrophy {abs(W - W64) / W64:.2e}")
+    note(f"  rhs rel L2 {err_rhs:.2e}, velocity {err:.2e}, energy {abs(E - E64) / E64:.2e}, "
+         f"enstrophy {abs(W - W64) / W64:.2e}")
+    assert err_rhs <= 2e-5
     assert err <= 1e-5
     assert abs(E - E64) / E64 <= 1e-6 and abs(W - W64) / W64 <= 1e-6
+
+
+def test_mfma_1024_against_plain_fp32():
+    """At 1024^3 (16-point DFT on the matrix cores, 64-point Stockham
+    sub-transforms, plain six-field inverse y pass), from the same seeded
+    random isotropic field: the right-hand side agrees with the plain FP32
+    path to 2e-5 relative L2 (the bound of the 64^3 and 128^3 oracle tests),
+    and after two RK4 steps velocity, energy and enstrophy agree to 1e-6
+    (the paths differ only through dt times the right-hand side)."""
+    note("mfma 1024 vs plain fp32")
+    import torch
+    N, nu, dt = 1024, 1e-3, 5e-4
+    out = []
+    for mfma in (False, True):
+        s = _solver(N, nu, dt, mfma_dft=mfma)
+        s.init_random(1, k0=4.0, energy=0.5)
+        r = s.rhs()
+        s.step(2)
+        out.append((r, s.diagnostics(), s.get_spectral()))
+        s.close()
+        del r
+        torch.cuda.empty_cache()
+    r0, (E0, W0), u0 = out[0]
+    r1, (E1, W1), u1 = out[1]
+    err_rhs = float(torch.linalg.vector_norm(r1 - r0) / torch.linalg.vector_norm(r0))
+    err_u = float(torch.linalg.vector_norm(u1 - u0) / torch.linalg.vector_norm(u0))
+    del out, r0, r1, u0, u1
+    torch.cuda.empty_cache()
+    note(f"  rhs rel L2 {err_rhs:.2e}, velocity {err_u:.2e}, energy {abs(E1 - E0) / E0:.2e}, "
+         f"enstrophy {abs(W1 - W0) / W0:.2e}")
+    assert err_rhs <= 2e-5
+    assert err_u <= 1e-6
+    assert abs(E1 - E0) / E0 <= 1e-6 and abs(W1 - W0) / W0 <= 1e-6
