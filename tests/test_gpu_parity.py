@@ -86,6 +86,31 @@ def test_rhs_matches_oracle(N, dealias):
     assert spectral_rel_l2(got, ref) <= TOL_F64
 
 
+@pytest.fixture(scope="module")
+def rhs_input_256():
+    return _rhs_input(256, seed=296)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("N", [128, 256])
+def test_rhs_matches_oracle_at_larger_sizes(N, dtype, rhs_input_256):
+    """Broadband right-hand side against the oracle where the stage passes
+    change form: 128^3 uses plain global accesses, 256^3 streaming ones; both
+    form the vorticity in the inverse y pass from five x-pass fields, with
+    multi-tile y and x passes and ragged Nyquist-plane workgroups."""
+    note(f"rhs N={N} {dtype}")
+    nu = 0.0137
+    uh = rhs_input_256 if N == 256 else _rhs_input(N, seed=40 + N)
+    s = _solver(N, nu=nu, dtype=dtype)
+    got = to_host(s.set_spectral(to_dev(uh, dtype)).rhs())
+    s.close()
+    src = uh if dtype == "f64" else uh.astype(np.complex64).astype(np.complex128)
+    ref = spectral.rhs(src, nu, spectral.wavenumber_mesh(N), spectral.dealias_mask(N))
+    err = spectral_rel_l2(got, ref)
+    note(f"  rel L2 {err:.2e}")
+    assert err <= (TOL_F64 if dtype == "f64" else 2e-5)
+
+
 @pytest.mark.parametrize("N", [16, 32])
 def test_rhs_fp32(N):
     note(f"rhs fp32 N={N}")
