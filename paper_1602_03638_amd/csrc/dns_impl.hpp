@@ -231,9 +231,9 @@ template <typename R, int N> struct Impl {
         add_z<1>(o); add_z<2>(o); add_z<4>(o); add_z<8>(o);
         add_z<16>(o); add_z<32>(o); add_z<64>(o); add_z<128>(o);
         // defaults: 128-byte row segments in the x and y passes, four z lines
-        // per workgroup (two for N = 1024), the fastest measured on MI355X at
-        // 256^3, 512^3 and 1024^3; for small N, at least one full 64-lane
-        // wave per workgroup
+        // per workgroup (eight for N = 256, two for N = 1024), the fastest
+        // measured on MI355X at 256^3, 512^3 and 1024^3; for small N, at
+        // least one full 64-lane wave per workgroup
         const int wave = 64 / G;
         const int xw = std::max((int)(128 / CB), wave), yw = xw;
         o.def[P_XINV] = pick(o, P_XINV, xw);
@@ -241,7 +241,7 @@ template <typename R, int N> struct Impl {
         o.def[P_XSTAGE] = pick(o, P_XSTAGE, xw);
         o.def[P_YINV6] = pick(o, P_YINV6, yw);
         o.def[P_YFWD3] = pick(o, P_YFWD3, yw);
-        o.def[P_ZCROSS] = pick(o, P_ZCROSS, std::max(N >= 1024 ? 2 : 4, wave));
+        o.def[P_ZCROSS] = pick(o, P_ZCROSS, std::max(N >= 1024 ? 2 : (N == 256 ? 8 : 4), wave));
         o.xinv3 = &xinv3;
         o.yinv3 = &yinv3;
         o.yfwd3s = &yfwd3s;
