@@ -15,7 +15,8 @@ brute force and the paper's printed worked example.  ``ic.random_isotropic``
 is pinned by its invariants and by published SplitMix64 outputs.
 """
 from .spectral import (  # noqa: F401
-    wavenumbers, dealias_mask, dft_matrix, dft3, dft3_mode, idft3, curl_hat, cross,
-    rhs, rk4_step, euler_step, energy, enstrophy, energy_physical, divergence_max,
+    wavenumbers, wavenumber_mesh, dealias_mask, dft_matrix, dft3, dft3_mode, idft3, idft3_point, curl_hat,
+    cross, project, nonlinear_hat, rhs, rk4_step, euler_step, energy, enstrophy, energy_physical,
+    divergence_max,
     Solver,
 )

@@ -28,7 +28,7 @@ shell spectrum shape on a large grid.
 """
 import numpy as np
 
-from .spectral import dealias_mask, energy, wavenumber_mesh
+from .spectral import dealias_mask, energy, project, wavenumber_mesh
 
 _GAMMA = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
@@ -90,9 +90,9 @@ def _hermitian_planes(uh):
 def random_isotropic(N, seed, k0=4.0, energy_target=0.5, rule="text"):
     """Random solenoidal half-spectrum (3, N, N, N/2+1) complex128; see the
     module docstring for the exact recipe."""
-    K, K2, K_over_K2 = wavenumber_mesh(N)
+    K, K2 = wavenumber_mesh(N)
     g = _gaussian_field(N, seed)
-    g = g - K * np.sum(K_over_K2 * g, axis=0)                 # step 3
+    g = project(g, K, K2)                                      # step 3
     kmag = np.sqrt(K2.astype(np.float64))
     safe = np.where(K2 == 0, 1.0, kmag)
     spec = safe ** 4 * np.exp(-2.0 * (safe / k0) ** 2)

@@ -22,12 +22,9 @@ import numpy as np
 
 _TWO_PI = 2.0 * np.pi
 
-RK4_A = (1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0)   # Appendix solver, weights
-RK4_B = (0.5, 0.5, 1.0)                                 # Appendix solver, stage offsets
-
 
 # ----------------------------------------------------------------------------
-# Meshes (Sec. 3.1: wavenumber-mesh listing; Appendix: K, K2, K_over_K2)
+# Wavenumbers (Sec. 2: k in the set of eq. kmesh; Sec. 3.1: storage order)
 # ----------------------------------------------------------------------------
 def wavenumbers(N):
     """Integer wavenumber vectors (kx, ky, kz) in storage order (Sec. 3.1).
@@ -43,16 +40,18 @@ def wavenumbers(N):
 
 
 def wavenumber_mesh(N):
-    """K (3, N, N, N/2+1) int64, K2 = |k|^2 int64 and K_over_K2 float64.
+    """The wavenumber vector of every stored mode and its squared length.
 
-    K_over_K2 = K / K2 with K2 replaced by 1 where it is 0, so it is 0 at
-    k = 0 (Sec. 3.1 listing and the Appendix solver).
+    Returns (K, K2): K[c, ix, iy, iz] is component c of k at storage index
+    (ix, iy, iz), int64 of shape (3, N, N, N/2+1); K2 = |k|^2, int64 of shape
+    (N, N, N/2+1), exact.
     """
     kx, ky, kz = wavenumbers(N)
-    K = np.array(np.meshgrid(kx, ky, kz, indexing="ij"), dtype=np.int64)
-    K2 = np.sum(K * K, axis=0, dtype=np.int64)
-    K_over_K2 = K.astype(np.float64) / np.where(K2 == 0, 1, K2).astype(np.float64)
-    return K, K2, K_over_K2
+    shape = (N, N, N // 2 + 1)
+    K = np.stack([np.broadcast_to(kx[:, None, None], shape), np.broadcast_to(ky[None, :, None], shape),
+                  np.broadcast_to(kz[None, None, :], shape)]).astype(np.int64)
+    K2 = kx[:, None, None] ** 2 + ky[None, :, None] ** 2 + kz[None, None, :] ** 2
+    return K, K2.astype(np.int64)
 
 
 def dealias_mask(N, rule="text"):
@@ -188,6 +187,33 @@ def idft3(uh):
     return _apply_z(Cz.T, np.ascontiguousarray(a.real)) + _apply_z(Sz.T, np.ascontiguousarray(a.imag))  # z (c2r)
 
 
+def idft3_point(uh, i, j, l):
+    """u at the mesh point (x_i, y_j, z_l) of the inverse transform idft3(uh),
+    evaluated by the definition for that one point (spot checks of inverse
+    transforms too large to evaluate whole):
+      a(kz) = N^-2 sum_{kx, ky} u_hat[kx, ky, kz] exp(+i (kx x_i + ky y_j)),
+      u = N^-1 [Re a(0) + (-1)^l Re a(N/2) + 2 sum_{0 < kz < N/2} Re(a(kz) exp(+i kz z_l))],
+    which keeps numpy irfftn's treatment of the kz = 0 and N/2 coefficients
+    (their imaginary parts after the x and y sums do not enter).  Angles are
+    reduced modulo N in integers.  uh: (..., N, N, N/2+1)."""
+    uh = np.asarray(uh, dtype=np.complex128)
+    N = uh.shape[-3]
+    roots = np.conj(_unit_root_table(N))            # exp(+2 pi i r / N)
+    n = np.arange(N, dtype=np.int64)
+    ex = roots[(n * i) % N]                          # over storage index ix (kx = ix mod N)
+    ey = roots[(n * j) % N]
+    a = np.tensordot(np.tensordot(uh, ex, axes=([-3], [0])), ey, axes=([-2], [0])) / float(N) ** 2
+    M = N // 2
+    ez = roots[(np.arange(M + 1, dtype=np.int64) * l) % N]
+    t = np.real(a * ez)
+    w = np.full(M + 1, 2.0)
+    w[0] = 1.0
+    w[M] = 1.0
+    t[..., 0] = np.real(a[..., 0])
+    t[..., M] = np.real(a[..., M]) * (1.0 if l % 2 == 0 else -1.0)
+    return np.sum(w * t, axis=-1) / N
+
+
 def dft3_mode(u, ix, iy, iz):
     """One coefficient of dft3(u) by the definition, for spot checks of
     transforms too large to evaluate whole: u_hat[ix, iy, iz] =
@@ -227,47 +253,51 @@ def cross(a, b):
     return c
 
 
-def rhs(uh, nu, mesh, mask):
-    """d u_hat / dt of eq. NSfinal, in the order of the computeRHS listing.
+def project(n, K, K2):
+    """Divergence-free part of n at every mode (eqs. mod_pressure, NSfinal):
+    the pressure gradient removes the component along k,
+      P(n) = n - k (k . n) / |k|^2,
+    and leaves the k = 0 mode unchanged (it has no pressure)."""
+    kn = K[0] * n[0] + K[1] * n[1] + K[2] * n[2]
+    along = np.where(K2 > 0, kn / np.where(K2 > 0, K2, 1), 0.0)
+    return n - K * along
 
-    u = F^-1(u_hat); omega = F^-1(i k x u_hat); N_hat = F(u x omega);
-    N_hat *= dealias; P_hat = sum_i N_hat_i k_i/|k|^2; N_hat -= P_hat k;
-    return N_hat - nu |k|^2 u_hat.
-    The velocity is recomputed from u_hat at every stage.
-    """
-    K, K2, K_over_K2 = mesh
+
+def nonlinear_hat(uh, K, mask):
+    """The dealiased convection term of eq. NSfinal: F(u x omega) with
+    u = F^-1(u_hat), omega = F^-1(i k x u_hat) (eq. curl_convection), set to
+    zero outside the 2/3-rule mask (Sec. 3.1)."""
     u = idft3(uh)
-    w = idft3(curl_hat(uh, K))
-    nh = dft3(cross(u, w))
-    nh *= mask
-    p_hat = np.sum(nh * K_over_K2, axis=0)
-    nh -= p_hat * K
-    nh -= nu * K2 * uh
-    return nh
+    omega = idft3(curl_hat(uh, K))
+    return mask * dft3(cross(u, omega))
+
+
+def rhs(uh, nu, mesh, mask):
+    """d u_hat / dt of eq. NSfinal: the projected dealiased convection term
+    minus the viscous term nu |k|^2 u_hat.  The velocity is obtained from
+    u_hat at every evaluation."""
+    K, K2 = mesh
+    return project(nonlinear_hat(uh, K, mask), K, K2) - nu * K2 * uh
 
 
 def rk4_step(uh, nu, dt, mesh, mask):
-    """One classic RK4 step as in the Appendix solver.
-
-    U0 = U1 = u_hat; for stage s = 0..3: R = rhs(u_hat); if s < 3:
-    u_hat = U0 + b_s dt R; U1 += a_s dt R.  The new state is U1.
-    a = (1/6, 1/3, 1/3, 1/6), b = (1/2, 1/2, 1).
-    """
-    U0 = uh.copy()
-    U1 = uh.copy()
-    cur = uh
-    for s in range(4):
-        R = rhs(cur, nu, mesh, mask)
-        if s < 3:
-            cur = U0 + RK4_B[s] * dt * R
-        U1 += RK4_A[s] * dt * R
-    return U1
+    """One step of the classical fourth-order Runge-Kutta method, the
+    integrator of the Appendix solver:
+      k1 = f(u), k2 = f(u + dt/2 k1), k3 = f(u + dt/2 k2), k4 = f(u + dt k3),
+      u_new = u + dt/6 (k1 + 2 k2 + 2 k3 + k4),  f = rhs."""
+    def f(v):
+        return rhs(v, nu, mesh, mask)
+    k1 = f(uh)
+    k2 = f(uh + (dt / 2) * k1)
+    k3 = f(uh + (dt / 2) * k2)
+    k4 = f(uh + dt * k3)
+    return uh + (dt / 6) * (k1 + 2 * k2 + 2 * k3 + k4)
 
 
 def euler_step(uh, nu, dt, mesh, mask):
-    """One forward Euler step as in the main loop of the Sec. 3.1 listing:
-    u_hat += computeRHS * dt."""
-    return uh + rhs(uh, nu, mesh, mask) * dt
+    """One forward Euler step, the time loop of the Sec. 3.1 listing:
+    u_new = u + dt f(u), f = rhs."""
+    return uh + dt * rhs(uh, nu, mesh, mask)
 
 
 # ----------------------------------------------------------------------------
@@ -293,7 +323,7 @@ def energy(uh):
 def enstrophy(uh):
     """Omega = mean over the mesh of |omega|^2 / 2 = (1/2N^6) sum_k w |k x u_hat|^2."""
     N = uh.shape[-3]
-    K, _, _ = wavenumber_mesh(N)
+    K, _ = wavenumber_mesh(N)
     return energy(curl_hat(uh, K))
 
 
@@ -304,11 +334,13 @@ def energy_physical(u):
 
 
 def divergence_max(uh):
-    """max |k . u_hat| / (max |k| * max |u_hat|): 0 for a solenoidal field."""
+    """Relative size of the divergence, max_k |k . u_hat(k)| / (max |k| *
+    max |u_hat|), over the stored modes: 0 for a solenoidal field (the
+    spectral form of div u = 0, Sec. 2)."""
     N = uh.shape[-3]
-    K, _, _ = wavenumber_mesh(N)
-    div = np.abs(np.sum(K * uh, axis=0))
-    scale = np.sqrt(np.max(np.sum(K * K, axis=0))) * np.max(np.abs(uh))
+    K, K2 = wavenumber_mesh(N)
+    div = np.abs(K[0] * uh[0] + K[1] * uh[1] + K[2] * uh[2])
+    scale = np.sqrt(float(np.max(K2))) * np.max(np.abs(uh))
     return float(np.max(div) / scale) if scale > 0 else 0.0
 
 

@@ -33,6 +33,8 @@ TOL = {
     "euler_decay": 1e-14,
     "masked_linear": 1e-14,
     "divergence": 1e-13,
+    "divergence_closed_form": 1e-14,
+    "point_inverse": 1e-14,
     "energy_budget": 1e-7,
     "appendix": 5e-13,
     "rk4_order_lo": 14.0,
@@ -109,15 +111,14 @@ def mesh_listing_error():
     (N = 8: kx = ky = 0,1,2,3,-4,-3,-2,-1 and kz = 0,1,2,3,+4)."""
     kxy = np.array([0, 1, 2, 3, -4, -3, -2, -1])
     kz = np.array([0, 1, 2, 3, 4])
-    K, K2, K_over_K2 = spectral.wavenumber_mesh(8)
+    K, K2 = spectral.wavenumber_mesh(8)
     err = 0.0
     for a in range(8):
         for b in range(8):
             for c in range(5):
                 k = np.array([kxy[a], kxy[b], kz[c]])
                 k2 = int(k @ k)
-                err = max(err, float(np.max(np.abs(K[:, a, b, c] - k))), abs(int(K2[a, b, c]) - k2),
-                          float(np.max(np.abs(K_over_K2[:, a, b, c] - (k / k2 if k2 else 0 * k)))))
+                err = max(err, float(np.max(np.abs(K[:, a, b, c] - k))), abs(int(K2[a, b, c]) - k2))
     return err
 
 
@@ -144,7 +145,7 @@ def dealias_table_error():
 def abc_curl_error(N=16):
     """The ABC flow is a Beltrami field: its vorticity equals the velocity."""
     u = workloads.abc_flow(N, 1.0, 0.7, 0.4)
-    K, _, _ = spectral.wavenumber_mesh(N)
+    K, _ = spectral.wavenumber_mesh(N)
     w = spectral.idft3(spectral.curl_hat(spectral.dft3(u), K))
     return _rel(w, u)
 
@@ -241,7 +242,7 @@ def masked_linear_error(N=16, nu=0.02, seed=3):
     uh = ic.random_isotropic(N, seed, k0=3.0)
     uh = uh + 0.05 * np.abs(uh).max() * spectral.dft3(workloads.random_physical(N, seed))
     mesh = spectral.wavenumber_mesh(N)
-    K, K2, _ = mesh
+    K, K2 = mesh
     mask = spectral.dealias_mask(N)
     r = spectral.rhs(uh, nu, mesh, mask)
     nonlin = r + nu * K2 * uh
@@ -256,6 +257,55 @@ def divergence_error(N=16, nu=0.01, dt=0.01, steps=3, seed=5):
     s = spectral.Solver(N, nu, dt).set_spectral(ic.random_isotropic(N, seed, k0=3.0))
     s.step(steps)
     return spectral.divergence_max(s.uh)
+
+
+def divergence_closed_form_error(N=16):
+    """divergence_max of fields with a known divergence.  u = (sin x, 0, 0):
+    u_hat_x = -+ i N^3/2 at kx = +-1, so max |k . u_hat| = N^3/2 = max |u_hat|,
+    and the largest |k| on the stored mesh is sqrt(3) N/2 (kx = ky = -N/2,
+    kz = +N/2): the value is 2 / (sqrt(3) N).  u = (0, 0, cos 2z): u_hat_z =
+    N^3/2 at kz = 2 gives 4 / (sqrt(3) N).  u = (0, sin 3y, 0) + a solenoidal
+    Taylor-Green field of larger amplitude: 6 / (sqrt(3) N) times N^3/2 over
+    the largest coefficient.  A solenoidal field gives 0."""
+    x = workloads.mesh_1d(N)
+    X, Y, Z = x[:, None, None], x[None, :, None], x[None, None, :]
+    zero = 0 * X + 0 * Y + 0 * Z
+    errs = []
+    u = np.stack([np.sin(X) + zero, zero, zero])
+    errs.append(abs(spectral.divergence_max(spectral.dft3(u)) - 2 / (np.sqrt(3) * N)) / (2 / (np.sqrt(3) * N)))
+    u = np.stack([zero, zero, np.cos(2 * Z) + zero])
+    errs.append(abs(spectral.divergence_max(spectral.dft3(u)) - 4 / (np.sqrt(3) * N)) / (4 / (np.sqrt(3) * N)))
+    tg = workloads.taylor_green(N)
+    u = 4.0 * tg + np.stack([zero, np.sin(3 * Y) + zero, zero])
+    uh = spectral.dft3(u)
+    want = 3 * (N ** 3 / 2) / (np.sqrt(3) * N / 2 * np.max(np.abs(uh)))
+    errs.append(abs(spectral.divergence_max(uh) - want) / want)
+    errs.append(spectral.divergence_max(spectral.dft3(tg)))
+    return max(errs)
+
+
+def point_inverse_error(N=8, seed=21):
+    """idft3_point at every mesh point against numpy.fft.irfftn (the routine
+    the paper's serial code calls) of a random, not Hermitian, half
+    spectrum, and against the closed form of a plane wave a cos(k . x + phi)
+    whose transform is N^3 a e^{i phi} / 2 at k."""
+    h = workloads.random_half_spectrum(N, seed)
+    ref = np.fft.irfftn(h, s=(N, N, N), axes=(1, 2, 3))
+    got = np.empty_like(ref)
+    for i in range(N):
+        for j in range(N):
+            for l in range(N):
+                got[:, i, j, l] = spectral.idft3_point(h, i, j, l)
+    err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    M = 16
+    kx, ky, kz, a, phi = 3, -5, 2, 0.75, 0.4
+    wave = np.zeros((1, M, M, M // 2 + 1), dtype=np.complex128)
+    wave[0, kx % M, ky % M, kz] = M ** 3 * a * np.exp(1j * phi) / 2
+    for i, j, l in ((0, 0, 0), (1, 2, 3), (15, 7, 9), (4, 11, 15)):
+        x = 2 * np.pi * np.array([i, j, l]) / M
+        want = a * np.cos(kx * x[0] + ky * x[1] + kz * x[2] + phi)
+        err = max(err, abs(float(spectral.idft3_point(wave, i, j, l)[0]) - want))
+    return err
 
 
 def energy_budget_error(N=32, nu=0.01, dt=0.01, steps=10):
@@ -314,6 +364,8 @@ FAST_PINS = {
     "euler_decay": euler_decay_error,
     "masked_linear": masked_linear_error,
     "divergence": divergence_error,
+    "divergence_closed_form": divergence_closed_form_error,
+    "point_inverse": point_inverse_error,
     "energy_budget": energy_budget_error,
 }
 

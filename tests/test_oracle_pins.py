@@ -110,7 +110,7 @@ def test_random_isotropic_shell_spectrum():
     energy over the shell-summed model is flat across shells."""
     N = 64
     uh = ic.random_isotropic(N, seed=7)
-    K, K2, _ = spectral.wavenumber_mesh(N)
+    K, K2 = spectral.wavenumber_mesh(N)
     w = np.full(N // 2 + 1, 2.0)
     w[0] = w[-1] = 1.0
     e_mode = 0.5 * w * np.sum(np.abs(uh) ** 2, axis=0)
