@@ -91,6 +91,17 @@ typedef struct dns_opts {
                          N >= 64 only (DNS_E_UNSUPPORTED otherwise); results
                          differ from the plain FP32 path at the 1e-6 level.
                          Default 0. */
+    /* Schedule of the step (see dns_set_schedule; every choice gives
+     * bitwise identical results).  0 / -1 / -1 = the defaults for N. */
+    int y_elems;      /* complex values per thread in the y passes: 8, 16, 32
+                         (0 = default: 8 below 1024, 16 in the FP32 forward
+                         y pass at 512; 16 FP64, 32 FP32 at 1024) */
+    int curl_in_y;    /* 1 = the inverse y pass forms the vorticity from five
+                         x-pass fields, 0 = the x pass writes all six fields;
+                         -1 = default (1 below 1024, 0 at 1024) */
+    int xcd_pair;     /* 1 = x passes whose row segments are shorter than
+                         128 bytes hand the tiles of each 128-byte line to
+                         one XCD; 0 = not; -1 = default (1 at 1024) */
 } dns_opts;
 
 typedef struct dns_ctx dns_t;
@@ -243,18 +254,65 @@ int dns_inverse(dns_t* ctx, const void* uhat_dev, void* u_dev);
  * matrix-core kernel, which has a single shape; their widths then only
  * matter for a later context without the option.
  *
- * Tuned plans are cached for the life of the process, keyed by (HIP device,
- * N, dtype, simulations per launch): dns_autotune stores its choice, and a
- * context or ensemble created with opts.autotune = 1 takes the cached plan
- * when one exists instead of timing again.  dns_plan_cache_entries returns
- * the number of cached plans; dns_plan_cache_clear empties the cache
- * (both thread-safe). */
+ * Tuned plans are cached for the life of the process, keyed by (device
+ * identity: architecture, name and compute units; N, dtype, simulations per
+ * launch), each as the descriptors of its variants (see dns_variant below):
+ * dns_autotune stores its choice, and a context or ensemble created with
+ * opts.autotune = 1 takes the cached plan when one exists instead of timing
+ * again.  dns_plan_cache_entries returns the number of cached plans;
+ * dns_plan_cache_clear empties the cache.  Persistence across processes:
+ * dns_plan_cache_save writes the cache to a file (JSON, one plan per line),
+ * dns_plan_cache_load adds a file's plans to the cache and returns how many
+ * it read (DNS_E_INVAL if the file cannot be read); with the environment
+ * variable DNS_PLAN_CACHE set to a path, the cache is loaded from it on
+ * first use and saved to it after every autotune.  A stored plan whose
+ * variants this build does not have is ignored.  All thread-safe. */
 int dns_autotune(dns_t* ctx, int reps);
 int dns_get_plan(const dns_t* ctx, int* widths, int max, int* count);
 int dns_set_plan(dns_t* ctx, const int* widths, int n);
 int dns_plan_variants(const dns_t* ctx, int pass, int* widths, int max, int* count);
 int dns_plan_cache_entries(void);
 int dns_plan_cache_clear(void);
+int dns_plan_cache_save(const char* path);
+int dns_plan_cache_load(const char* path);
+
+/* Schedule of a step.  Besides the width, a pass variant fixes three choices
+ * that change where work is done, never the arithmetic (results stay
+ * bitwise identical):
+ *  - y_elems: complex values per thread in the y passes (8, 16 or 32): the
+ *    forward y pass, and the inverse one where the x pass forms the
+ *    vorticity (the combining inverse y pass always holds 8);
+ *  - curl_in_y: where the vorticity i k x u_hat of the Curl listing (Sec. 3.1)
+ *    is combined.  Its components with ky and kz commute with the x
+ *    transform, so the inverse x pass need transform only u_hat and the kx
+ *    products; 1 = the inverse y pass combines them from the x pass's five
+ *    fields, 0 = the x pass writes all six;
+ *  - xcd_pair: the device dispatches workgroup b to XCD b mod 8, each XCD
+ *    with its own L2.  Where an x-pass tile's row segments are 64 bytes,
+ *    1 = the two tiles of each 128-byte line go to workgroups b and b + 8
+ *    (one XCD), 0 = to consecutive workgroups.
+ * dns_set_schedule selects, for every pass, the variant of the current width
+ * (else the nearest width) that runs the given schedule; y_elems 0,
+ * curl_in_y -1 and xcd_pair -1 take the defaults for N.  DNS_E_INVAL for an
+ * invalid value, DNS_E_UNSUPPORTED for a schedule this N and dtype (or the
+ * matrix-core option) do not provide.  Waits for the stream.
+ *
+ * dns_plan_variants_ex lists every variant of one pass (index order of
+ * dns_get_plan) with its descriptor (y_elems 0 for passes other than the y
+ * passes; curl_in_y -1 for passes that do not depend on it).
+ * dns_get_plan_ex / dns_set_plan_ex read and install a plan as one variant
+ * index per pass; DNS_E_INVAL if an index is out of range or the inverse x,
+ * inverse y and stage passes disagree on curl_in_y. */
+typedef struct dns_variant {
+    int width;
+    int xcd_pair;
+    int y_elems;
+    int curl_in_y;
+} dns_variant;
+int dns_set_schedule(dns_t* ctx, int y_elems, int curl_in_y, int xcd_pair);
+int dns_plan_variants_ex(const dns_t* ctx, int pass, dns_variant* out, int max, int* count);
+int dns_get_plan_ex(const dns_t* ctx, int* variants, int max, int* count);
+int dns_set_plan_ex(dns_t* ctx, const int* variants, int n);
 
 /* dns_strerror: a static description of a status code.  dns_last_error:
  * the message of the context's last failure ("" if none).
@@ -278,8 +336,13 @@ const char* dns_last_error(const dns_t* ctx);
  * ------------------------------------------------------------------------- */
 typedef struct dns_ens dns_ens_t;
 enum {
-    DNS_ENS_BATCHED = 0,   /* one captured graph per step covering every class */
-    DNS_ENS_PER_SIM = 1    /* every member's kernels launched separately (baseline) */
+    DNS_ENS_BATCHED = 0,   /* one captured graph per step covering every class,
+                              replayed once per step */
+    DNS_ENS_PER_SIM = 1,   /* every member's kernels launched separately (baseline) */
+    DNS_ENS_ONE_GRAPH = 2  /* all nsteps steps of every class captured into one
+                              graph and launched once (captured on the first
+                              call with that nsteps; the four most recent step
+                              counts are kept) */
 };
 int dns_ens_create(int count, const int* N, const double* nu, const double* dt, int dtype,
                    const dns_opts* opts, void* stream, dns_ens_t** out);
@@ -289,8 +352,10 @@ int dns_ens_set_velocity(dns_ens_t* ens, int i, const void* u_dev);
 int dns_ens_set_spectral(dns_ens_t* ens, int i, const void* uhat_dev);
 int dns_ens_init_random(dns_ens_t* ens, int i, unsigned long long seed, double k0, double energy);
 int dns_ens_get_spectral(dns_ens_t* ens, int i, void* uhat_dev);
-/* Advance every member nsteps time steps; mode DNS_ENS_BATCHED or
- * DNS_ENS_PER_SIM (bitwise identical results). */
+/* Advance every member nsteps time steps; mode DNS_ENS_BATCHED,
+ * DNS_ENS_PER_SIM or DNS_ENS_ONE_GRAPH (bitwise identical results).  With
+ * per-step diagnostics (opts.diag_every) or opts.use_graph = 0 the batched
+ * modes launch kernel by kernel. */
 int dns_ens_step(dns_ens_t* ens, int nsteps, int mode);
 /* E[i], Omega[i] for every member (either pointer may be NULL). Synchronous. */
 int dns_ens_diagnostics(dns_ens_t* ens, double* E, double* Omega);

@@ -39,7 +39,13 @@ class DnsError(RuntimeError):
 class dns_opts(ctypes.Structure):
     _fields_ = [("dealias", ctypes.c_int), ("diag_every", ctypes.c_int),
                 ("history_cap", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("fuse", ctypes.c_int), ("integrator", ctypes.c_int), ("mfma_dft", ctypes.c_int)]
+                ("fuse", ctypes.c_int), ("integrator", ctypes.c_int), ("mfma_dft", ctypes.c_int),
+                ("y_elems", ctypes.c_int), ("curl_in_y", ctypes.c_int), ("xcd_pair", ctypes.c_int)]
+
+
+class dns_variant(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int), ("xcd_pair", ctypes.c_int), ("y_elems", ctypes.c_int),
+                ("curl_in_y", ctypes.c_int)]
 
 
 _lib = None
@@ -92,6 +98,12 @@ def load_library(path=LIB_PATH):
         "dns_set_plan": (I, [P, ctypes.POINTER(I), I]),
         "dns_plan_variants": (I, [P, I, ctypes.POINTER(I), I, ctypes.POINTER(I)]),
         "dns_plan_cache_entries": (I, []),
+        "dns_plan_cache_save": (I, [ctypes.c_char_p]),
+        "dns_plan_cache_load": (I, [ctypes.c_char_p]),
+        "dns_set_schedule": (I, [P, I, I, I]),
+        "dns_plan_variants_ex": (I, [P, I, ctypes.POINTER(dns_variant), I, ctypes.POINTER(I)]),
+        "dns_get_plan_ex": (I, [P, ctypes.POINTER(I), I, ctypes.POINTER(I)]),
+        "dns_set_plan_ex": (I, [P, ctypes.POINTER(I), I]),
         "dns_plan_cache_clear": (I, []),
         "dns_ens_create": (I, [I, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D), I,
                                ctypes.POINTER(dns_opts), P, PP]),
@@ -162,11 +174,26 @@ def plan_cache_clear():
     load_library().dns_plan_cache_clear()
 
 
+def plan_cache_save(path):
+    """Write the tuned-plan cache to a JSON file (dns_plan_cache_save)."""
+    _check(load_library().dns_plan_cache_save(os.fsencode(path)), None, "dns_plan_cache_save")
+
+
+def plan_cache_load(path):
+    """Add the plans of a cache file to the cache; returns how many it read."""
+    n = load_library().dns_plan_cache_load(os.fsencode(path))
+    if n < 0:
+        _check(n, None, "dns_plan_cache_load")
+    return n
+
+
 class Solver:
     """One pseudo-spectral DNS context on the current GPU (see include/dns.h).
 
     dtype: "f64" or "f32"; integrator: "rk4" (default) or "euler"; mfma_dft:
     y passes with the radix-16 stage on FP16 matrix cores (FP32, N >= 64);
+    y_elems / curl_in_y / xcd_pair: schedule of the step (dns_set_schedule;
+    None = the default for N);
     workspace: None (the library allocates), "torch" (a uint8 tensor from
     torch's allocator) or a contiguous CUDA tensor of at least
     dns_workspace_bytes bytes, 256-byte aligned, kept alive by the Solver.
@@ -178,7 +205,7 @@ class Solver:
 
     def __init__(self, N, nu, dt, dtype="f64", dealias="text", diag_every=0, use_graph=True,
                  history_cap=4096, stream=None, autotune=False, fuse=True, integrator="rk4", mfma_dft=False,
-                 workspace=None):
+                 workspace=None, y_elems=None, curl_in_y=None, xcd_pair=None):
         import torch
         self._torch = torch
         lib = load_library()
@@ -196,6 +223,9 @@ class Solver:
         o.fuse = 1 if fuse else 0
         o.integrator = INTEGRATORS[integrator]
         o.mfma_dft = 1 if mfma_dft else 0
+        o.y_elems = 0 if y_elems is None else int(y_elems)
+        o.curl_in_y = -1 if curl_in_y is None else int(bool(curl_in_y))
+        o.xcd_pair = -1 if xcd_pair is None else int(bool(xcd_pair))
         self.history_cap = int(history_cap)
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -364,6 +394,66 @@ class Solver:
         _check(load_library().dns_set_plan(self.handle, w, len(self.PASSES)), self.handle, "dns_set_plan")
         return self
 
+    def set_schedule(self, y_elems=None, curl_in_y=None, xcd_pair=None):
+        """dns_set_schedule; None keeps the default for N."""
+        _check(load_library().dns_set_schedule(self.handle, 0 if y_elems is None else int(y_elems),
+                                                -1 if curl_in_y is None else int(bool(curl_in_y)),
+                                                -1 if xcd_pair is None else int(bool(xcd_pair))),
+               self.handle, "dns_set_schedule")
+        return self
+
+    def plan_variants_ex(self):
+        """Every variant of every pass: {pass: [dict(width, xcd_pair, y_elems, curl_in_y)]}."""
+        out = {}
+        for i, name in enumerate(self.PASSES):
+            arr = (dns_variant * 32)()
+            n = ctypes.c_int()
+            _check(load_library().dns_plan_variants_ex(self.handle, i, arr, 32, ctypes.byref(n)), self.handle,
+                   "dns_plan_variants_ex")
+            out[name] = [dict(width=v.width, xcd_pair=v.xcd_pair, y_elems=v.y_elems, curl_in_y=v.curl_in_y)
+                         for v in arr[: n.value]]
+        return out
+
+    def plan_ex(self):
+        """Variant index of every pass."""
+        w = (ctypes.c_int * len(self.PASSES))()
+        n = ctypes.c_int()
+        _check(load_library().dns_get_plan_ex(self.handle, w, len(self.PASSES), ctypes.byref(n)), self.handle,
+               "dns_get_plan_ex")
+        return dict(zip(self.PASSES, list(w)))
+
+    def set_plan_ex(self, variants):
+        if isinstance(variants, dict):
+            variants = [variants[p] for p in self.PASSES]
+        w = (ctypes.c_int * len(self.PASSES))(*[int(x) for x in variants])
+        _check(load_library().dns_set_plan_ex(self.handle, w, len(self.PASSES)), self.handle, "dns_set_plan_ex")
+        return self
+
+    COUPLED = ("xinv_curl", "yinv6", "xstage")   # passes whose fields depend on the curl placement
+
+    def plan_with(self, p, v, base=None):
+        """Variant indices of `base` (default: the current plan) with variant v
+        for pass p; where v changes the curl placement, the other coupled
+        passes take a variant of that placement (same width when there is
+        one), so that the plan is consistent."""
+        base = dict(self.plan_ex() if base is None else base)
+        var = self.plan_variants_ex()
+        base[p] = v
+        cy = var[p][v]["curl_in_y"]
+        if p in self.COUPLED:
+            for q in self.COUPLED:
+                if q == p or var[q][base[q]]["curl_in_y"] == cy:
+                    continue
+                cands = [i for i, d in enumerate(var[q]) if d["curl_in_y"] == cy]
+                same = [i for i in cands if var[q][i]["width"] == var[q][base[q]]["width"]]
+                base[q] = (same or cands)[0]
+        return base
+
+    def schedule(self):
+        """The current plan's descriptors: {pass: dict(width, xcd_pair, y_elems, curl_in_y)}."""
+        var = self.plan_variants_ex()
+        return {p: var[p][i] for p, i in self.plan_ex().items()}
+
     def plan_variants(self):
         out = {}
         for i, name in enumerate(self.PASSES):
@@ -395,6 +485,7 @@ class Solver:
 
 DNS_ENS_BATCHED = 0
 DNS_ENS_PER_SIM = 1
+DNS_ENS_ONE_GRAPH = 2
 
 
 def _check_ens(status, ens, what):
@@ -489,9 +580,12 @@ class Ensemble:
                    "dns_ens_get_spectral")
         return out
 
-    def step(self, n=1, batched=True):
-        _check_ens(load_library().dns_ens_step(self.handle, int(n), DNS_ENS_BATCHED if batched else DNS_ENS_PER_SIM),
-                   self.handle, "dns_ens_step")
+    def step(self, n=1, batched=True, one_graph=False):
+        """Advance every member n steps: batched launches replayed as one graph
+        per step (default), all n steps in one graph launch (one_graph), or
+        per-simulation launches (batched=False)."""
+        mode = DNS_ENS_ONE_GRAPH if one_graph else (DNS_ENS_BATCHED if batched else DNS_ENS_PER_SIM)
+        _check_ens(load_library().dns_ens_step(self.handle, int(n), mode), self.handle, "dns_ens_step")
         return self
 
     def diagnostics(self):

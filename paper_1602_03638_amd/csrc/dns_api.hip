@@ -217,6 +217,10 @@ int diag_groups(const dns_t* c) {
 // The N/16-point twiddle table that follows the N unit roots in mfma_tw.
 const void* mfma_tw2(const dns_t* c) { return (const char*)c->mfma_tw + (size_t)c->N * c->cbytes; }
 
+// Curl placement of the context's plan: 1 = the inverse y pass forms the
+// vorticity from the x pass's five fields, 0 = the x pass writes six.
+int plan_cy(const dns_t* c) { return c->ops->var[dns::P_XSTAGE][c->sel[dns::P_XSTAGE]].cy; }
+
 // Launch one pass of stage `stage` for all members (member < 0, one batched
 // launch) or for one member only.  diag: fused diagnostic partials of
 // member 0; member m's sit 2 * groups * m doubles further.
@@ -235,7 +239,7 @@ void launch_pass(dns_t* c, int pass, int variant, int stage, double* diag, hipSt
         }
         case dns::P_YINV6:
             if (c->opts.mfma_dft)
-                o->ymfma_inv6(c->W(m), c->tw, c->mfma_tw, mfma_tw2(c), b, s);
+                o->ymfma_inv6[plan_cy(c)](c->W(m), c->tw, c->mfma_tw, mfma_tw2(c), b, s);
             else
                 o->yinv6[variant](c->W(m), c->tw, b, s);
             break;
@@ -347,33 +351,132 @@ void release(dns_t* c) {
     if (c->s && c->own_stream) (void)hipStreamDestroy(c->s);
 }
 
-// Process-wide cache of autotuned plans: the variant chosen for each pass,
-// keyed by (device, N, dtype, members per launch).  dns_autotune stores its
-// result; a context created with opts.autotune takes a cached plan instead of
-// timing again.
-using PlanKey = std::tuple<int, int, int, int>;
-using Plan = std::array<int, dns::P_COUNT>;
+// Process-wide cache of autotuned plans, keyed by (device identity, N,
+// dtype, simulations per launch).  A plan is stored as the descriptor
+// (width, XCD grouping, y elements, curl placement) of the chosen variant of
+// every pass, so that a plan read back from a file written by another build
+// is used only where those variants still exist.  dns_autotune stores its
+// result; a context created with opts.autotune takes a cached plan instead
+// of timing again.  With DNS_PLAN_CACHE set to a file path, the cache is
+// read from that file on first use and written back after every autotune;
+// dns_plan_cache_save / dns_plan_cache_load do the same explicitly.
+using PlanKey = std::tuple<std::string, int, int, int>;
+using Plan = std::array<dns::Variant, dns::P_COUNT>;
 std::mutex g_plan_mu;
 std::map<PlanKey, Plan> g_plans;
+bool g_plan_env_loaded = false;
 
-PlanKey plan_key(const dns_t* c) {
+// "arch|name|compute units" of the current device ('"' and '|' removed).
+std::string device_identity() {
     int dev = 0;
     (void)hipGetDevice(&dev);
-    return PlanKey{dev, c->N, c->dtype, c->members};
+    hipDeviceProp_t p{};
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "device" + std::to_string(dev);
+    std::string id = std::string(p.gcnArchName) + "|" + p.name + "|" + std::to_string(p.multiProcessorCount);
+    for (char& ch : id)
+        if (ch == '"' || ch == '\\' || ch < 32) ch = ' ';
+    return id;
 }
+
+PlanKey plan_key(const dns_t* c) { return PlanKey{device_identity(), c->N, c->dtype, c->members}; }
+
+// Cache file: valid JSON, one plan per line.
+int plan_cache_write(const char* path) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return DNS_E_INVAL;
+    std::fprintf(f, "{\"format\": \"dns-plan-cache-1\", \"plans\": [\n");
+    size_t i = 0;
+    for (const auto& kv : g_plans) {
+        std::fprintf(f, "{\"device\": \"%s\", \"N\": %d, \"dtype\": %d, \"members\": %d, \"variants\": [",
+                     std::get<0>(kv.first).c_str(), std::get<1>(kv.first), std::get<2>(kv.first),
+                     std::get<3>(kv.first));
+        for (int p = 0; p < dns::P_COUNT; ++p) {
+            const dns::Variant& v = kv.second[p];
+            std::fprintf(f, "%s[%d, %d, %d, %d]", p ? ", " : "", v.width, v.pair, v.ye, v.cy);
+        }
+        std::fprintf(f, "]}%s\n", ++i < g_plans.size() ? "," : "");
+    }
+    std::fprintf(f, "]}\n");
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) return DNS_E_INVAL;
+    return DNS_OK;
+}
+
+// Read the plans of a cache file into the cache; the number read, or -1.
+int plan_cache_read(const char* path) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return -1;
+    int n = 0;
+    char line[4096];
+    while (std::fgets(line, sizeof line, f)) {
+        const char* d = std::strstr(line, "{\"device\": \"");
+        if (!d) continue;
+        d += 12;
+        const char* q = std::strchr(d, '"');
+        if (!q) continue;
+        const std::string dev(d, q);
+        long v[3 + 4 * dns::P_COUNT];
+        int k = 0;
+        for (const char* t = q + 1; *t && k < (int)(sizeof v / sizeof v[0]);) {
+            if (*t == '-' || (*t >= '0' && *t <= '9')) {
+                char* end = nullptr;
+                v[k++] = std::strtol(t, &end, 10);
+                t = end;
+            } else {
+                ++t;
+            }
+        }
+        if (k != 3 + 4 * dns::P_COUNT) continue;
+        Plan p;
+        for (int i = 0; i < dns::P_COUNT; ++i)
+            p[i] = dns::Variant{(int)v[3 + 4 * i], (int)v[4 + 4 * i], (int)v[5 + 4 * i], (int)v[6 + 4 * i]};
+        g_plans[PlanKey{dev, (int)v[0], (int)v[1], (int)v[2]}] = p;
+        ++n;
+    }
+    std::fclose(f);
+    return n;
+}
+
+// Load DNS_PLAN_CACHE once (caller holds g_plan_mu).
+void plan_env_load() {
+    if (g_plan_env_loaded) return;
+    g_plan_env_loaded = true;
+    const char* path = std::getenv("DNS_PLAN_CACHE");
+    if (path && *path) (void)plan_cache_read(path);
+}
+
+bool plan_consistent(const dns_t* c, const int* sel);
 
 void store_plan(const dns_t* c) {
     Plan p;
-    for (int k = 0; k < dns::P_COUNT; ++k) p[k] = c->sel[k];
+    for (int k = 0; k < dns::P_COUNT; ++k) p[k] = c->ops->var[k][c->sel[k]];
+    const PlanKey key = plan_key(c);
     std::lock_guard<std::mutex> lock(g_plan_mu);
-    g_plans[plan_key(c)] = p;
+    plan_env_load();
+    g_plans[key] = p;
+    const char* path = std::getenv("DNS_PLAN_CACHE");
+    if (path && *path) (void)plan_cache_write(path);
 }
 
 bool load_plan(dns_t* c) {
+    const PlanKey key = plan_key(c);
     std::lock_guard<std::mutex> lock(g_plan_mu);
-    auto it = g_plans.find(plan_key(c));
+    plan_env_load();
+    auto it = g_plans.find(key);
     if (it == g_plans.end()) return false;
-    for (int k = 0; k < dns::P_COUNT; ++k) c->sel[k] = it->second[k];
+    int sel[dns::P_COUNT];
+    for (int k = 0; k < dns::P_COUNT; ++k) {
+        sel[k] = -1;
+        const dns::Variant& want = it->second[k];
+        for (int v = 0; v < c->ops->nvar[k]; ++v) {
+            const dns::Variant& d = c->ops->var[k][v];
+            if (d.width == want.width && d.pair == want.pair && d.ye == want.ye && d.cy == want.cy) sel[k] = v;
+        }
+        if (sel[k] < 0) return false;   // a variant of another build
+    }
+    if (!plan_consistent(c, sel)) return false;
+    for (int k = 0; k < dns::P_COUNT; ++k) c->sel[k] = sel[k];
     return true;
 }
 
@@ -381,6 +484,59 @@ bool load_plan(dns_t* c) {
 int tune_new(dns_t* c) {
     if (load_plan(c)) return DNS_OK;
     return dns_autotune(c, 3);
+}
+
+// A plan is consistent when the passes whose fields depend on the curl
+// placement (inverse x, inverse y, fused stage) agree on it, and, with the
+// matrix-core option, that y kernel exists for it.
+bool plan_consistent(const dns_t* c, const int* sel) {
+    const dns::Ops& o = *c->ops;
+    const int a = o.var[dns::P_XINV][sel[dns::P_XINV]].cy;
+    const int b = o.var[dns::P_YINV6][sel[dns::P_YINV6]].cy;
+    const int d = o.var[dns::P_XSTAGE][sel[dns::P_XSTAGE]].cy;
+    if (a != b || b != d) return false;
+    return !c->opts.mfma_dft || o.ymfma_inv6[a] != nullptr;
+}
+
+// Variant of pass p that matches the schedule (curl placement cy, y elements
+// ye for the y passes, XCD pairing pair where a paired variant exists), of
+// width w if there is one, else the widest narrower, else the narrowest
+// wider; -1 if no variant matches the schedule.
+int find_variant(const dns::Ops& o, int p, int w, int cy, int ye, int pair) {
+    int best = -1;
+    auto rank = [&](const dns::Variant& d) {   // larger is better
+        const int wr = d.width == w ? 3 * 4096 : (d.width < w ? 2 * 4096 + d.width : 4096 - d.width);
+        return 2 * wr + (d.pair == pair ? 1 : 0);
+    };
+    for (int v = 0; v < o.nvar[p]; ++v) {
+        const dns::Variant& d = o.var[p][v];
+        if (d.cy >= 0 && d.cy != cy) continue;
+        if (d.ye > 0 && d.ye != ye && !(p == dns::P_YINV6 && cy == 1)) continue;
+        if (best < 0 || rank(d) > rank(o.var[p][best])) best = v;
+    }
+    return best;
+}
+
+// Select, for every pass, the variant of the current width that runs the
+// schedule (y_elems 0, curl_in_y -1 and xcd_pair -1 keep the defaults).
+int apply_schedule(dns_t* c, int y_elems, int curl_in_y, int xcd_pair) {
+    const dns::Ops& o = *c->ops;
+    const int cy = curl_in_y >= 0 ? curl_in_y : o.var[dns::P_XSTAGE][o.def[dns::P_XSTAGE]].cy;
+    const int ye = y_elems > 0 ? y_elems : o.var[dns::P_YFWD3][o.def[dns::P_YFWD3]].ye;
+    const int pair = xcd_pair >= 0 ? xcd_pair : o.var[dns::P_XSTAGE][o.def[dns::P_XSTAGE]].pair;
+    int sel[dns::P_COUNT];
+    for (int p = 0; p < dns::P_COUNT; ++p) {
+        sel[p] = find_variant(o, p, o.var[p][c->sel[p]].width, cy, ye, pair);
+        if (sel[p] < 0) return fail(c, DNS_E_UNSUPPORTED, "schedule not provided for this N and dtype");
+    }
+    if (pair == 1) {
+        bool any = false;
+        for (int p : {dns::P_XINV, dns::P_XRHS, dns::P_XSTAGE}) any = any || o.var[p][sel[p]].pair == 1;
+        if (!any) return fail(c, DNS_E_UNSUPPORTED, "no XCD-paired x pass for this N and dtype");
+    }
+    if (!plan_consistent(c, sel)) return fail(c, DNS_E_UNSUPPORTED, "schedule not provided with these options");
+    for (int p = 0; p < dns::P_COUNT; ++p) c->sel[p] = sel[p];
+    return DNS_OK;
 }
 
 int check_args(int N, double nu, double dt, int dtype, const dns_opts& o) {
@@ -392,6 +548,9 @@ int check_args(int N, double nu, double dt, int dtype, const dns_opts& o) {
         (o.integrator != DNS_RK4 && o.integrator != DNS_EULER) || (o.mfma_dft != 0 && o.mfma_dft != 1))
         return DNS_E_INVAL;
     if (o.mfma_dft && (dtype != DNS_FP32 || N < 64)) return DNS_E_UNSUPPORTED;
+    if ((o.y_elems != 0 && o.y_elems != 8 && o.y_elems != 16 && o.y_elems != 32) || o.curl_in_y < -1 ||
+        o.curl_in_y > 1 || o.xcd_pair < -1 || o.xcd_pair > 1)
+        return DNS_E_INVAL;
     return DNS_OK;
 }
 
@@ -490,7 +649,24 @@ int create_ctx(int N, double nu, double dt, int dtype, const dns_opts& o, hipStr
     c->tw = c->mem + k.tw;
     c->mfma_tw = o.mfma_dft ? (void*)(c->mem + k.mfma_tw) : nullptr;
     c->npart_cap = k.npart_cap;
-    for (int p = 0; p < dns::P_COUNT; ++p) c->sel[p] = c->ops->def[p];
+    for (int p = 0; p < dns::P_COUNT; ++p) {
+        c->sel[p] = c->ops->def[p];
+        if (c->sel[p] < 0 || c->sel[p] >= c->ops->nvar[p]) {
+            std::fprintf(stderr, "dns_create: no default variant of pass %d for N = %d\n", p, N);
+            release(c);
+            delete c;
+            return DNS_E_UNSUPPORTED;
+        }
+    }
+    if (o.y_elems != 0 || o.curl_in_y >= 0 || o.xcd_pair >= 0 || o.mfma_dft) {
+        const int r = apply_schedule(c, o.y_elems, o.curl_in_y, o.xcd_pair);
+        if (r != DNS_OK) {
+            std::fprintf(stderr, "dns_create: %s\n", c->err.c_str());
+            release(c);
+            delete c;
+            return r;
+        }
+    }
 
     // twiddles: long-double accurate, rounded to the context's precision
     const int ntw = c->ops->tw_count;
@@ -650,6 +826,9 @@ void dns_default_opts(dns_opts* o) {
     o->fuse = 1;
     o->integrator = DNS_RK4;
     o->mfma_dft = 0;
+    o->y_elems = 0;
+    o->curl_in_y = -1;
+    o->xcd_pair = -1;
 }
 
 size_t dns_state_bytes(int N, int dtype) {
@@ -899,31 +1078,64 @@ int dns_profile_step(dns_t* c, int nsteps, float* ms, const char** names, int ma
     return leave(c);
 }
 
-// Time every tile-shape variant of every pass on the context's buffers and
-// keep the fastest.  The RHS passes are timed in their stage-1 form, which
-// reads U0 but writes only U1, Us and W, so the current state is preserved.
+// Time every variant of every pass on the context's buffers and keep the
+// fastest plan.  The RHS passes are timed in their stage-1 form, which reads
+// U0 but writes only U1, Us and W, so the current state is preserved.  The
+// passes whose fields depend on the curl placement are chosen together: for
+// each placement the fastest variants of the inverse x, inverse y and stage
+// passes are summed with the weights of one step, and the cheaper placement
+// wins; the other passes take their fastest variant.
 int dns_autotune(dns_t* c, int reps) {
     if (!c || reps < 0) return fail(c, DNS_E_INVAL, "bad argument");
     if (reps == 0) reps = 3;
     int r = enter(c);
     if (r) return r;
     drop_graphs(c);
+    const dns::Ops& o = *c->ops;
+    std::vector<std::vector<float>> t(dns::P_COUNT);
     for (int p = 0; p < dns::P_COUNT; ++p) {
-        float best = 1e30f;
-        int bestv = c->sel[p];
-        for (int v = 0; v < c->ops->nvar[p]; ++v) {
+        t[p].assign(o.nvar[p], 1e30f);
+        for (int v = 0; v < o.nvar[p]; ++v) {
             launch_pass(c, p, v, 1, nullptr, c->s);                  // warm-up
             DNS_TRY(c, hipEventRecord(c->ev_prof[0], c->s));
             for (int i = 0; i < reps; ++i) launch_pass(c, p, v, 1, nullptr, c->s);
             if ((r = launched(c, kPassNames[p]))) return r;
             DNS_TRY(c, hipEventRecord(c->ev_prof[1], c->s));
             DNS_TRY(c, hipEventSynchronize(c->ev_prof[1]));
-            float t = 0.f;
-            DNS_TRY(c, hipEventElapsedTime(&t, c->ev_prof[0], c->ev_prof[1]));
-            if (t < best) { best = t; bestv = v; }
+            float ms = 0.f;
+            DNS_TRY(c, hipEventElapsedTime(&ms, c->ev_prof[0], c->ev_prof[1]));
+            t[p][v] = ms;
         }
-        c->sel[p] = bestv;
     }
+    // fastest variant of pass p usable with curl placement cy (-1: any)
+    auto fastest = [&](int p, int cy) {
+        int best = -1;
+        for (int v = 0; v < o.nvar[p]; ++v) {
+            const int vc = o.var[p][v].cy;
+            if (cy >= 0 && vc >= 0 && vc != cy) continue;
+            if (best < 0 || t[p][v] < t[p][best]) best = v;
+        }
+        return best;
+    };
+    int best_cy = plan_cy(c);
+    float best_cost = 1e30f;
+    for (int cy = 0; cy <= 1; ++cy) {
+        const int vx = fastest(dns::P_XINV, cy), vy = fastest(dns::P_YINV6, cy), vs = fastest(dns::P_XSTAGE, cy);
+        if (vx < 0 || vy < 0 || vs < 0 || o.var[dns::P_XINV][vx].cy != cy || o.var[dns::P_YINV6][vy].cy != cy ||
+            o.var[dns::P_XSTAGE][vs].cy != cy)
+            continue;
+        if (c->opts.mfma_dft && !o.ymfma_inv6[cy]) continue;
+        const float cost = c->opts.fuse ? 4.f * (t[dns::P_YINV6][vy] + t[dns::P_XSTAGE][vs])
+                                        : 4.f * (t[dns::P_YINV6][vy] + t[dns::P_XINV][vx]);
+        if (cost < best_cost) { best_cost = cost; best_cy = cy; }
+    }
+    int sel[dns::P_COUNT];
+    for (int p = 0; p < dns::P_COUNT; ++p) {
+        const int cy = (p == dns::P_XINV || p == dns::P_YINV6 || p == dns::P_XSTAGE) ? best_cy : -1;
+        sel[p] = fastest(p, cy);
+    }
+    if (plan_consistent(c, sel))
+        for (int p = 0; p < dns::P_COUNT; ++p) c->sel[p] = sel[p];
     c->w_ready = false;
     store_plan(c);
     return leave(c);
@@ -931,11 +1143,28 @@ int dns_autotune(dns_t* c, int reps) {
 
 int dns_plan_cache_entries(void) {
     std::lock_guard<std::mutex> lock(g_plan_mu);
+    plan_env_load();
     return (int)g_plans.size();
+}
+
+int dns_plan_cache_save(const char* path) {
+    if (!path || !*path) return DNS_E_INVAL;
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    plan_env_load();
+    return plan_cache_write(path);
+}
+
+int dns_plan_cache_load(const char* path) {
+    if (!path || !*path) return DNS_E_INVAL;
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    plan_env_load();
+    const int n = plan_cache_read(path);
+    return n < 0 ? DNS_E_INVAL : n;
 }
 
 int dns_plan_cache_clear(void) {
     std::lock_guard<std::mutex> lock(g_plan_mu);
+    g_plan_env_loaded = true;   // a cleared cache is not refilled from DNS_PLAN_CACHE
     g_plans.clear();
     return DNS_OK;
 }
@@ -943,20 +1172,14 @@ int dns_plan_cache_clear(void) {
 int dns_get_plan(const dns_t* c, int* widths, int max, int* count) {
     if (!c || !count || max < 0 || (max > 0 && !widths)) return DNS_E_INVAL;
     const int m = max < dns::P_COUNT ? max : dns::P_COUNT;
-    for (int p = 0; p < m; ++p) widths[p] = c->ops->width[p][c->sel[p]];
+    for (int p = 0; p < m; ++p) widths[p] = c->ops->var[p][c->sel[p]].width;
     *count = dns::P_COUNT;
     return DNS_OK;
 }
 
-int dns_set_plan(dns_t* c, const int* widths, int n) {
-    if (!c || !widths || n != dns::P_COUNT) return fail(c, DNS_E_INVAL, "bad argument");
-    int sel[dns::P_COUNT];
-    for (int p = 0; p < dns::P_COUNT; ++p) {
-        sel[p] = -1;
-        for (int v = 0; v < c->ops->nvar[p]; ++v)
-            if (c->ops->width[p][v] == widths[p]) sel[p] = v;
-        if (sel[p] < 0) return fail(c, DNS_E_INVAL, "no variant of that width for this N and dtype");
-    }
+// Install plan `sel` (variant indices): waits for the stream and drops the
+// captured graphs, whose kernels it changes.
+int install_plan(dns_t* c, const int* sel) {
     DNS_TRY(c, hipStreamSynchronize(c->s));
     drop_graphs(c);
     for (int p = 0; p < dns::P_COUNT; ++p) c->sel[p] = sel[p];
@@ -964,12 +1187,91 @@ int dns_set_plan(dns_t* c, const int* widths, int n) {
     return DNS_OK;
 }
 
+int dns_set_plan(dns_t* c, const int* widths, int n) {
+    if (!c || !widths || n != dns::P_COUNT) return fail(c, DNS_E_INVAL, "bad argument");
+    const dns::Ops& o = *c->ops;
+    const int cy = plan_cy(c);
+    int sel[dns::P_COUNT];
+    for (int p = 0; p < dns::P_COUNT; ++p) {
+        // the variant of that width with the current schedule
+        const dns::Variant& cur = o.var[p][c->sel[p]];
+        sel[p] = -1;
+        for (int v = 0; v < o.nvar[p]; ++v) {
+            const dns::Variant& d = o.var[p][v];
+            if (d.width != widths[p] || (d.cy >= 0 && d.cy != cy) || (d.ye > 0 && d.ye != cur.ye)) continue;
+            if (sel[p] < 0 || (d.pair == cur.pair && o.var[p][sel[p]].pair != cur.pair)) sel[p] = v;
+        }
+        if (sel[p] < 0) return fail(c, DNS_E_INVAL, "no variant of that width for this N, dtype and schedule");
+    }
+    return install_plan(c, sel);
+}
+
 int dns_plan_variants(const dns_t* c, int pass, int* widths, int max, int* count) {
     if (!c || !count || pass < 0 || pass >= dns::P_COUNT || max < 0 || (max > 0 && !widths)) return DNS_E_INVAL;
-    const int n = c->ops->nvar[pass];
-    for (int v = 0; v < n && v < max; ++v) widths[v] = c->ops->width[pass][v];
+    // distinct widths of the variants that run the current schedule
+    const dns::Ops& o = *c->ops;
+    const int cy = plan_cy(c);
+    const dns::Variant& cur = o.var[pass][c->sel[pass]];
+    int n = 0;
+    for (int v = 0; v < o.nvar[pass]; ++v) {
+        const dns::Variant& d = o.var[pass][v];
+        if ((d.cy >= 0 && d.cy != cy) || (d.ye > 0 && d.ye != cur.ye)) continue;
+        bool seen = false;
+        for (int u = 0; u < v; ++u) {
+            const dns::Variant& e = o.var[pass][u];
+            seen = seen || (e.width == d.width && (e.cy < 0 || e.cy == cy) && (e.ye <= 0 || e.ye == cur.ye));
+        }
+        if (seen) continue;
+        if (n < max) widths[n] = d.width;
+        ++n;
+    }
     *count = n;
     return DNS_OK;
+}
+
+int dns_plan_variants_ex(const dns_t* c, int pass, dns_variant* out, int max, int* count) {
+    if (!c || !count || pass < 0 || pass >= dns::P_COUNT || max < 0 || (max > 0 && !out)) return DNS_E_INVAL;
+    const dns::Ops& o = *c->ops;
+    for (int v = 0; v < o.nvar[pass] && v < max; ++v) {
+        out[v].width = o.var[pass][v].width;
+        out[v].xcd_pair = o.var[pass][v].pair;
+        out[v].y_elems = o.var[pass][v].ye;
+        out[v].curl_in_y = o.var[pass][v].cy;
+    }
+    *count = o.nvar[pass];
+    return DNS_OK;
+}
+
+int dns_get_plan_ex(const dns_t* c, int* variants, int max, int* count) {
+    if (!c || !count || max < 0 || (max > 0 && !variants)) return DNS_E_INVAL;
+    for (int p = 0; p < dns::P_COUNT && p < max; ++p) variants[p] = c->sel[p];
+    *count = dns::P_COUNT;
+    return DNS_OK;
+}
+
+int dns_set_plan_ex(dns_t* c, const int* variants, int n) {
+    if (!c || !variants || n != dns::P_COUNT) return fail(c, DNS_E_INVAL, "bad argument");
+    for (int p = 0; p < dns::P_COUNT; ++p)
+        if (variants[p] < 0 || variants[p] >= c->ops->nvar[p]) return fail(c, DNS_E_INVAL, "variant index out of range");
+    if (!plan_consistent(c, variants))
+        return fail(c, DNS_E_INVAL, "inverse x, inverse y and stage passes disagree on the curl placement");
+    return install_plan(c, variants);
+}
+
+int dns_set_schedule(dns_t* c, int y_elems, int curl_in_y, int xcd_pair) {
+    if (!c || (y_elems != 0 && y_elems != 8 && y_elems != 16 && y_elems != 32) || curl_in_y < -1 ||
+        curl_in_y > 1 || xcd_pair < -1 || xcd_pair > 1)
+        return fail(c, DNS_E_INVAL, "bad argument");
+    int keep[dns::P_COUNT];
+    for (int p = 0; p < dns::P_COUNT; ++p) keep[p] = c->sel[p];
+    int r = apply_schedule(c, y_elems, curl_in_y, xcd_pair);
+    if (r != DNS_OK) return r;
+    int sel[dns::P_COUNT];
+    for (int p = 0; p < dns::P_COUNT; ++p) {
+        sel[p] = c->sel[p];
+        c->sel[p] = keep[p];
+    }
+    return install_plan(c, sel);
 }
 
 const char* dns_strerror(int s) {
@@ -1000,6 +1302,8 @@ struct dns_ens {
     std::vector<int> cls_of, idx_of;      // member i -> (class, index in class)
     std::vector<char> ready;              // member i has a velocity field
     hipGraphExec_t gexec = nullptr;       // one step of every class
+    // DNS_ENS_ONE_GRAPH: graphs of whole multi-step calls, by step count
+    std::vector<std::pair<int, hipGraphExec_t>> multi;
     std::string err;
 };
 
@@ -1029,6 +1333,8 @@ int ens_cls_error(dns_ens_t* e, dns_t* c, int r) {
 
 void ens_release(dns_ens_t* e) {
     if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+    for (auto& m : e->multi) (void)hipGraphExecDestroy(m.second);
+    e->multi.clear();
     for (dns_t* c : e->cls) {
         release(c);
         delete c;
@@ -1161,8 +1467,27 @@ int dns_ens_get_spectral(dns_ens_t* e, int i, void* uh) {
     return ens_leave(e);
 }
 
+// Capture `steps` steps of every class (in class order) into one graph.
+int ens_capture(dns_ens_t* e, int steps, hipGraphExec_t* out) {
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(e->s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return ens_fail(e, DNS_E_HIP, "hipStreamBeginCapture");
+    for (int i = 0; i < steps; ++i)
+        for (dns_t* c : e->cls) enqueue_step(c, false, e->s);
+    hipError_t le = hipGetLastError();
+    hipError_t ee = hipStreamEndCapture(e->s, &g);
+    if (le != hipSuccess || ee != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return ens_fail(e, DNS_E_HIP, "ensemble graph capture");
+    }
+    hipError_t ie = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return ens_fail(e, DNS_E_HIP, "hipGraphInstantiate");
+    return DNS_OK;
+}
+
 int dns_ens_step(dns_ens_t* e, int nsteps, int mode) {
-    if (!e || nsteps < 0 || (mode != DNS_ENS_BATCHED && mode != DNS_ENS_PER_SIM))
+    if (!e || nsteps < 0 || (mode != DNS_ENS_BATCHED && mode != DNS_ENS_PER_SIM && mode != DNS_ENS_ONE_GRAPH))
         return ens_fail(e, DNS_E_INVAL, "bad argument");
     for (char ok : e->ready)
         if (!ok) return ens_fail(e, DNS_E_STATE, "a member has no velocity set");
@@ -1178,26 +1503,29 @@ int dns_ens_step(dns_ens_t* e, int nsteps, int mode) {
             if ((r = ens_cls_error(e, c, step_all(c, nsteps, mode == DNS_ENS_PER_SIM)))) return r;
         return ens_leave(e);
     }
-    // batched: one captured graph advances every class by one step
     for (dns_t* c : e->cls)
         if ((r = ens_cls_error(e, c, prepare_w(c)))) return r;
-    if (!e->gexec) {
-        hipGraph_t g = nullptr;
-        if (hipStreamBeginCapture(e->s, hipStreamCaptureModeThreadLocal) != hipSuccess)
-            return ens_fail(e, DNS_E_HIP, "hipStreamBeginCapture");
-        for (dns_t* c : e->cls) enqueue_step(c, false, e->s);
-        hipError_t le = hipGetLastError();
-        hipError_t ee = hipStreamEndCapture(e->s, &g);
-        if (le != hipSuccess || ee != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return ens_fail(e, DNS_E_HIP, "ensemble graph capture");
+    if (mode == DNS_ENS_ONE_GRAPH) {
+        // all nsteps steps of every class in one captured graph (one launch);
+        // graphs are kept per step count (the four most recent)
+        hipGraphExec_t g = nullptr;
+        for (auto& m : e->multi)
+            if (m.first == nsteps) g = m.second;
+        if (!g) {
+            if ((r = ens_capture(e, nsteps, &g))) return r;
+            if (e->multi.size() >= 4) {
+                (void)hipGraphExecDestroy(e->multi.front().second);
+                e->multi.erase(e->multi.begin());
+            }
+            e->multi.emplace_back(nsteps, g);
         }
-        hipError_t ie = hipGraphInstantiate(&e->gexec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (ie != hipSuccess) return ens_fail(e, DNS_E_HIP, "hipGraphInstantiate");
+        if (hipGraphLaunch(g, e->s) != hipSuccess) return ens_fail(e, DNS_E_HIP, "hipGraphLaunch");
+    } else {
+        // batched: one captured graph advances every class by one step
+        if (!e->gexec && (r = ens_capture(e, 1, &e->gexec))) return r;
+        for (int i = 0; i < nsteps; ++i)
+            if (hipGraphLaunch(e->gexec, e->s) != hipSuccess) return ens_fail(e, DNS_E_HIP, "hipGraphLaunch");
     }
-    for (int i = 0; i < nsteps; ++i)
-        if (hipGraphLaunch(e->gexec, e->s) != hipSuccess) return ens_fail(e, DNS_E_HIP, "hipGraphLaunch");
     for (dns_t* c : e->cls) {
         c->steps += nsteps;
         c->w_ready = c->opts.fuse != 0;

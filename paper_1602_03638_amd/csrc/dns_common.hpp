@@ -141,30 +141,55 @@ template <typename R, int N, typename P> __device__ __forceinline__ P* field_el(
         return F + at;
 }
 
-// Elements per thread of the y-pass line transforms.  Lines of 1024 take
-// 16 (FP64) or 32 (FP32) complex values per thread, so that a workgroup of
-// 128-byte row segments (8 FP64 or 16 FP32 columns) has 512 threads, each
+// Elements per thread of the y-pass line transforms (a plan choice, see
+// dns_impl.hpp; every choice runs the same butterflies with the same
+// twiddles, so the results are bitwise identical).  Default: lines of 1024
+// take 16 (FP64) or 32 (FP32) complex values per thread, so that a workgroup
+// of 128-byte row segments (8 FP64 or 16 FP32 columns) has 512 threads, each
 // holding one 256-byte line slice; shorter lines take 8.
-template <typename R> constexpr int y_elems(int N) { return N >= 1024 ? (sizeof(R) == 8 ? 16 : 32) : 8; }
+template <typename R> constexpr int default_y_elems(int N) { return N >= 1024 ? (sizeof(R) == 8 ? 16 : 32) : 8; }
 // With more than 8 elements per thread the y pass reads its twiddles from
 // shared memory at every stage (kept in registers they would crowd out the
 // line).
-template <typename R> constexpr bool y_twiddles_in_lds(int N) { return y_elems<R>(N) > 8; }
+constexpr bool y_twiddles_in_lds(int E) { return E > 8; }
 
 // Where the vorticity combinations i (ky w - kz v), i (kz u - kx w),
-// i (kx v - ky u) are formed.  With 8 elements per y-line thread the inverse
-// y pass forms them as it loads (the x pass writes U, V, W, F(kx v_hat) and
-// F(kx w_hat): five fields instead of six, 8 of 180 fields per step less);
-// with longer y slices (N = 1024) three live lines per thread would spill,
-// so there the x pass writes the six fields u, v, w, omega and the y pass
-// transforms them as they are.
-template <typename R> constexpr bool curl_in_y(int N) { return y_elems<R>(N) == 8; }
+// i (kx v - ky u) are formed (a plan choice, bitwise neutral: the same
+// operations in another kernel).  With 8 elements per y-line thread the
+// inverse y pass can form them as it loads (the x pass writes U, V, W,
+// F(kx v_hat) and F(kx w_hat): five fields instead of six, 8 of 180 fields
+// per step less); with longer y slices three live lines per thread would
+// spill, so there the x pass writes the six fields u, v, w, omega and the y
+// pass transforms them as they are.  Default: in the y pass below 1024.
+template <typename R> constexpr bool default_curl_in_y(int N) { return default_y_elems<R>(N) == 8; }
 
 // Elements per thread of the x-pass line transforms.  8 for every size: the
 // fused stage kernel holds three lines per thread, and 16 per thread (which
 // would fit 128-byte FP32 rows of 1024-lines into fewer threads) spilled and
 // measured slower at 1024^3 (24.7 vs 22.1 ms per launch on MI355X).
 template <typename R> constexpr int x_elems(int) { return 8; }
+
+// Tile handled by workgroup b of an x pass.  Workgroups are dispatched to
+// the 8 XCDs in turn (workgroup b to XCD b mod 8), each with its own L2.
+// Where an x tile's row segments are shorter than 128 bytes, GRP
+// consecutive tiles share every 128-byte line; with GRP > 1 they go to
+// workgroups b, b + 8, ..., b + 8 (GRP - 1) of one XCD, which start together
+// and share its L2, instead of to GRP XCDs that each fetch the whole line.
+// Tiles are permuted within the main block and within the Nyquist-plane
+// block separately (both counts multiples of 8 GRP).
+template <int GRP> __device__ __forceinline__ int x_tile(int b, int main_tiles) {
+    if constexpr (GRP == 1) {
+        return b;
+    } else {
+        const int base = b < main_tiles ? 0 : main_tiles;
+        const int r = b - base, xcd = r & 7, k = r >> 3;
+        return base + GRP * (8 * (k / GRP) + xcd) + (k % GRP);
+    }
+}
+// Tiles of width T (columns of type R) sharing one 128-byte line.
+template <typename R, int T> constexpr int line_group() {
+    return T * 2 * (int)sizeof(R) >= 128 ? 1 : 128 / (T * 2 * (int)sizeof(R));
+}
 
 // Workgroups of the standalone diagnostic reduction (fixed, so the summation
 // order and hence the result are reproducible).

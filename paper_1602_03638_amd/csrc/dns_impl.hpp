@@ -21,6 +21,11 @@ template <typename R, int N> struct Impl {
     static constexpr int GX = N / x_elems<R>(N);   // threads per x line
     static constexpr size_t CB = sizeof(C);
     static constexpr int XCOLS = N * (N / 2);
+    static constexpr int YE0 = default_y_elems<R>(N);
+    static constexpr bool CY0 = default_curl_in_y<R>(N);
+    // FP64 lines of 8 complex doubles per thread need more than the 128
+    // registers a 1024-thread workgroup leaves each thread: at most 512.
+    static constexpr int MAXT = sizeof(R) == 8 ? 512 : 1024;
 
     // Feasibility of a workgroup shape: at most 1024 threads and the LDS limit.
     // (lines of more than 8 elements per thread need more than the 128
@@ -34,11 +39,19 @@ template <typename R, int N> struct Impl {
         return x_ok<T>() && (sizeof(R) == 4 || GX * T <= 512) &&
                (size_t)T * N * CB + 2 * 8 * (size_t)GX * T <= LDS_LIMIT;
     }
-    static constexpr int GY = N / y_elems<R>(N);   // threads per y line
-    template <int T> static constexpr bool y_ok() {
-        return T <= N / 2 && GY * T <= 1024 &&
-               ((size_t)T * N + (y_twiddles_in_lds<R>(N) || curl_in_y<R>(N) ? (size_t)tw_size(N) : 0)) * CB <=
-                   LDS_LIMIT;
+    // XCD-grouped tile order (x_tile): where an x tile's row segment is 32
+    // or 64 bytes, from 256^3 up, with both tile counts multiples of 8 times
+    // the number of tiles per 128-byte line.
+    template <int T> static constexpr bool pair_ok() {
+        constexpr int grp = line_group<R, T>();
+        return N >= 256 && (T * CB == 64 || T * CB == 32) && (XCOLS / T) % (8 * grp) == 0 &&
+               (N / T) % (8 * grp) == 0;
+    }
+    // y shapes with YE elements per thread; CURL: the vorticity-forming
+    // inverse pass (twiddles in shared memory)
+    template <int T, int YE, bool CURL> static constexpr bool y_ok() {
+        return YE >= 8 && N % YE == 0 && T <= N / 2 && (N / YE) * T <= 1024 &&
+               ((size_t)T * N + (y_twiddles_in_lds(YE) || CURL ? (size_t)tw_size(N) : 0)) * CB <= LDS_LIMIT;
     }
     // z shapes: at least 16 threads, and up to 128 threads for small N
     template <int L> static constexpr bool z_ok() {
@@ -47,82 +60,104 @@ template <typename R, int N> struct Impl {
     }
     template <int T> static constexpr int x_groups() { return XCOLS / T + N / T; }
 
+    // Default widths: 128-byte row segments, and for small N at least one
+    // full 64-lane wave per workgroup.
+    static constexpr int want_width(int threads_per_line) {
+        const int w = (int)(128 / CB), wave = 64 / threads_per_line;
+        return w > wave ? w : (wave > 0 ? wave : 1);
+    }
+    // Widest power-of-two width <= want whose x stage shape is feasible.
+    static constexpr int x_default_width() {
+        int best = 4;
+        const int want = want_width(N / 8);
+        if (xr_ok<4>() && GX * 4 <= MAXT && 4 <= want) best = 4;
+        if (xr_ok<8>() && GX * 8 <= MAXT && 8 <= want) best = 8;
+        if (N <= 64 && xr_ok<16>() && GX * 16 <= MAXT && 16 <= want) best = 16;
+        if (N <= 64 && xr_ok<32>() && GX * 32 <= MAXT && 32 <= want) best = 32;
+        if (N > 64 && xr_ok<16>() && GX * 16 <= MAXT && 16 <= want) best = 16;
+        return best;
+    }
+    template <int YE> static constexpr int y_default_width() {
+        if (N % YE != 0) return 0;
+        int best = 0;
+        const int want = want_width(N / 8) > want_width(N / YE) ? want_width(N / 8) : want_width(N / YE);
+        if (y_ok<4, YE, false>() && (N / YE) * 4 <= MAXT && 4 <= want) best = 4;
+        if (y_ok<8, YE, false>() && (N / YE) * 8 <= MAXT && 8 <= want) best = 8;
+        if (y_ok<16, YE, false>() && (N / YE) * 16 <= MAXT && 16 <= want) best = 16;
+        if (y_ok<32, YE, false>() && (N / YE) * 32 <= MAXT && 32 <= want) best = 32;
+        return best;
+    }
+    static constexpr int XD = x_default_width();
+
     // ---- pass launchers ----------------------------------------------------
-    template <int T> static void xinv(const void* U, void* W, const void* tw, const Batch& b, hipStream_t s) {
-        hipLaunchKernelGGL((k_xinv_curl<R, N, T>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0, s,
+    template <int T, bool CY, bool PAIR>
+    static void xinv(const void* U, void* W, const void* tw, const Batch& b, hipStream_t s) {
+        hipLaunchKernelGGL((k_xinv_curl<R, N, T, CY, PAIR>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0, s,
                            (const C*)U, (C*)W, (const C*)tw, b.sst, b.wst);
     }
-    template <int T, int DIR, int NF> static void ypass(void* W, const void* tw, const Batch& b, hipStream_t s) {
-        hipLaunchKernelGGL((k_yline<R, N, T, DIR, NF>), dim3(y_tiles<R, N, T>(), b.members), dim3(GY * T), 0, s,
-                           (C*)W, (const C*)tw, b.wst);
+    template <int T, int DIR, int NF, int YE>
+    static void ypass(void* W, const void* tw, const Batch& b, hipStream_t s) {
+        hipLaunchKernelGGL((k_yline<R, N, T, DIR, NF, YE>), dim3(y_tiles<R, N, T>(), b.members), dim3((N / YE) * T),
+                           0, s, (C*)W, (const C*)tw, b.wst);
     }
-    template <int DIR, int NF>
+    template <int DIR, int NF, bool CURL>
     static void ymfma(void* W, const void* tw, const void* roots, const void* tw2, const Batch& b, hipStream_t s) {
         if constexpr (std::is_same_v<R, float> && N >= 64) {
-            hipLaunchKernelGGL((k_yline_mfma<N, DIR, NF>), dim3(MfmaY<N>::TILES, b.members), dim3(MfmaY<N>::NT), 0, s,
-                               (C*)W, (const C*)tw, (const C*)roots, (const C*)tw2, b.wst);
+            hipLaunchKernelGGL((k_yline_mfma<N, DIR, NF, CURL>), dim3(MfmaY<N>::TILES, b.members),
+                               dim3(MfmaY<N>::NT), 0, s, (C*)W, (const C*)tw, (const C*)roots, (const C*)tw2, b.wst);
         }
     }
-    // inverse y pass of a stage: the six fields for the z pass, with the
-    // vorticity combinations formed from the x pass's five outputs
-    template <int T> static void yinv6(void* W, const void* tw, const Batch& b, hipStream_t s) {
-        if constexpr (curl_in_y<R>(N))
-            hipLaunchKernelGGL((k_yinv_curl<R, N, T>), dim3(y_tiles<R, N, T>(), b.members), dim3(GY * T), 0, s,
-                               (C*)W, (const C*)tw, b.wst);
-        else
-            ypass<T, +1, 6>(W, tw, b, s);
-    }
-    template <int T> static void yfwd3(void* W, const void* tw, const Batch& b, hipStream_t s) {
-        ypass<T, -1, 3>(W, tw, b, s);
+    // inverse y pass of a stage with the vorticity combinations formed from
+    // the x pass's five outputs
+    template <int T> static void yinv_curl(void* W, const void* tw, const Batch& b, hipStream_t s) {
+        hipLaunchKernelGGL((k_yinv_curl<R, N, T>), dim3(y_tiles<R, N, T>(), b.members), dim3((N / 8) * T), 0, s,
+                           (C*)W, (const C*)tw, b.wst);
     }
     template <int L> static void zcross(void* W, const void* tw, const Batch& b, hipStream_t s) {
         const R scale = (R)std::ldexp(1.0, -6 * ilog2(N));
         hipLaunchKernelGGL((k_zcross<R, N, L>), dim3((N * N) / L, b.members), dim3(G * L), 0, s, (C*)W,
                            (const C*)tw, scale, b.wst);
     }
-    template <int T, int ST>
+    template <int T, bool PAIR, int ST>
     static void xrhs_st(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
                         const Batch& b, hipStream_t s) {
-        hipLaunchKernelGGL((k_xrhs<R, N, T, ST>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0, s,
+        hipLaunchKernelGGL((k_xrhs<R, N, T, ST, PAIR>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0, s,
                            (const C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a, b.sst, b.wst);
     }
-    template <int T>
+    template <int T, bool PAIR>
     static void xrhs(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
                      const Batch& b, hipStream_t s) {
         switch (a.stage) {
-            case 0: xrhs_st<T, 0>(W, U0, U1, Us, tw, a, b, s); break;
-            case 1: xrhs_st<T, 1>(W, U0, U1, Us, tw, a, b, s); break;
-            case 2: xrhs_st<T, 2>(W, U0, U1, Us, tw, a, b, s); break;
-            case 3: xrhs_st<T, 3>(W, U0, U1, Us, tw, a, b, s); break;
-            case 4: xrhs_st<T, 4>(W, U0, U1, Us, tw, a, b, s); break;
-            default: xrhs_st<T, -1>(W, U0, U1, Us, tw, a, b, s); break;
+            case 0: xrhs_st<T, PAIR, 0>(W, U0, U1, Us, tw, a, b, s); break;
+            case 1: xrhs_st<T, PAIR, 1>(W, U0, U1, Us, tw, a, b, s); break;
+            case 2: xrhs_st<T, PAIR, 2>(W, U0, U1, Us, tw, a, b, s); break;
+            case 3: xrhs_st<T, PAIR, 3>(W, U0, U1, Us, tw, a, b, s); break;
+            case 4: xrhs_st<T, PAIR, 4>(W, U0, U1, Us, tw, a, b, s); break;
+            default: xrhs_st<T, PAIR, -1>(W, U0, U1, Us, tw, a, b, s); break;
         }
     }
 
-    template <int T, int ST>
+    template <int T, bool CY, bool PAIR, int ST>
     static void xstage_st(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
                           const Batch& b, hipStream_t s) {
-        hipLaunchKernelGGL((k_xstage<R, N, T, ST>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0, s,
+        hipLaunchKernelGGL((k_xstage<R, N, T, ST, CY, PAIR>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0, s,
                            (C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a, b.sst, b.wst);
     }
-    template <int T>
+    template <int T, bool CY, bool PAIR>
     static void xstage(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
                        const Batch& b, hipStream_t s) {
         switch (a.stage) {
-            case 0: xstage_st<T, 0>(W, U0, U1, Us, tw, a, b, s); break;
-            case 1: xstage_st<T, 1>(W, U0, U1, Us, tw, a, b, s); break;
-            case 2: xstage_st<T, 2>(W, U0, U1, Us, tw, a, b, s); break;
-            case 3: xstage_st<T, 3>(W, U0, U1, Us, tw, a, b, s); break;
-            default: xstage_st<T, 4>(W, U0, U1, Us, tw, a, b, s); break;
+            case 0: xstage_st<T, CY, PAIR, 0>(W, U0, U1, Us, tw, a, b, s); break;
+            case 1: xstage_st<T, CY, PAIR, 1>(W, U0, U1, Us, tw, a, b, s); break;
+            case 2: xstage_st<T, CY, PAIR, 2>(W, U0, U1, Us, tw, a, b, s); break;
+            case 3: xstage_st<T, CY, PAIR, 3>(W, U0, U1, Us, tw, a, b, s); break;
+            default: xstage_st<T, CY, PAIR, 4>(W, U0, U1, Us, tw, a, b, s); break;
         }
     }
 
     // ---- standalone transforms (fixed shapes) -------------------------------
-    // FP64 lines of 8 complex doubles per thread need more than the 128
-    // registers a 1024-thread workgroup leaves each thread: at most 512.
-    static constexpr int MAXT = sizeof(R) == 8 ? 512 : 1024;
     template <int T> static constexpr bool xs_ok() { return x_ok<T>() && GX * T <= MAXT; }
-    template <int T> static constexpr bool ys_ok() { return y_ok<T>() && GY * T <= MAXT; }
+    template <int T> static constexpr bool ys_ok() { return y_ok<T, YE0, false>() && (N / YE0) * T <= MAXT; }
     static constexpr int TS = xs_ok<8>() ? 8 : (xs_ok<4>() ? 4 : (xs_ok<2>() ? 2 : 1));
     static constexpr int YS = ys_ok<8>() ? 8 : (ys_ok<4>() ? 4 : (ys_ok<2>() ? 2 : 1));
     static constexpr int LS = N >= 128 ? 4 : 512 / N;
@@ -134,8 +169,8 @@ template <typename R, int N> struct Impl {
         hipLaunchKernelGGL((k_xplain<R, N, TS, -1, 3>), dim3(x_groups<TS>()), dim3(GX * TS), 0, s,
                            (const C*)W, (C*)U, (const C*)tw);
     }
-    static void yinv3(void* W, const void* tw, hipStream_t s) { ypass<YS, +1, 3>(W, tw, Batch{1, 0, 0}, s); }
-    static void yfwd3s(void* W, const void* tw, hipStream_t s) { ypass<YS, -1, 3>(W, tw, Batch{1, 0, 0}, s); }
+    static void yinv3(void* W, const void* tw, hipStream_t s) { ypass<YS, +1, 3, YE0>(W, tw, Batch{1, 0, 0}, s); }
+    static void yfwd3s(void* W, const void* tw, hipStream_t s) { ypass<YS, -1, 3, YE0>(W, tw, Batch{1, 0, 0}, s); }
     static void zr2c(const void* u, void* W, const void* tw, hipStream_t s) {
         hipLaunchKernelGGL((k_zr2c<R, N, LS>), dim3((N * N) / LS), dim3(G * LS), 0, s,
                            (const R*)u, (C*)W, (const C*)tw);
@@ -175,49 +210,80 @@ template <typename R, int N> struct Impl {
     }
 
     // ---- variant tables ------------------------------------------------------
-    template <int T> static void add_x(Ops& o) {
+    static int& push(Ops& o, int p, Variant d) {
+        int& n = o.nvar[p];
+        o.var[p][n] = d;
+        return n;
+    }
+    // x passes of width T with curl placement CY and XCD pairing PAIR
+    template <int T, bool CY, bool PAIR> static void add_x(Ops& o) {
         if constexpr (T > 16 && N > 64) return;    // wide tiles only for small N
+        if constexpr (PAIR && !pair_ok<T>()) return;
         if constexpr (x_ok<T>()) {
-            int& n = o.nvar[P_XINV];
-            o.xinv[n] = &xinv<T>;
-            o.width[P_XINV][n++] = T;
+            int& n = push(o, P_XINV, Variant{T, PAIR, 0, CY});
+            o.xinv[n++] = &xinv<T, CY, PAIR>;
         }
         if constexpr (xr_ok<T>()) {
-            int& n = o.nvar[P_XRHS];
-            o.xrhs[n] = &xrhs<T>;
-            o.xrhs_groups[n] = x_groups<T>();
-            o.width[P_XRHS][n++] = T;
-            int& k = o.nvar[P_XSTAGE];
-            o.xstage[k] = &xstage<T>;
-            o.xstage_groups[k] = x_groups<T>();
-            o.width[P_XSTAGE][k++] = T;
+            int& k = push(o, P_XSTAGE, Variant{T, PAIR, 0, CY});
+            o.xstage[k] = &xstage<T, CY, PAIR>;
+            o.xstage_groups[k++] = x_groups<T>();
         }
     }
-    template <int T> static void add_y(Ops& o) {
-        if constexpr (y_ok<T>()) {
-            int& n = o.nvar[P_YINV6];
-            o.yinv6[n] = &yinv6<T>;
-            o.yfwd3[n] = &yfwd3<T>;
-            o.width[P_YINV6][n] = T;
-            o.width[P_YFWD3][n] = T;
-            ++n;
-            o.nvar[P_YFWD3] = n;
+    // the RHS pass alone (independent of the curl placement)
+    template <int T, bool PAIR> static void add_xr(Ops& o) {
+        if constexpr (T > 16 && N > 64) return;
+        if constexpr (PAIR && !pair_ok<T>()) return;
+        if constexpr (xr_ok<T>()) {
+            int& n = push(o, P_XRHS, Variant{T, PAIR, 0, -1});
+            o.xrhs[n] = &xrhs<T, PAIR>;
+            o.xrhs_groups[n++] = x_groups<T>();
+        }
+    }
+    // inverse y pass forming the vorticity (curl in y, 8 per thread)
+    template <int T> static void add_ycurl(Ops& o) {
+        if constexpr (y_ok<T, 8, true>()) {
+            int& n = push(o, P_YINV6, Variant{T, 0, 8, 1});
+            o.yinv6[n++] = &yinv_curl<T>;
+        }
+    }
+    // inverse y pass of the six fields the x pass wrote (curl in x)
+    template <int T, int YE> static void add_yinv(Ops& o) {
+        if constexpr (T > 0 && y_ok<T, YE, false>()) {
+            int& n = push(o, P_YINV6, Variant{T, 0, YE, 0});
+            o.yinv6[n++] = &ypass<T, +1, 6, YE>;
+        }
+    }
+    template <int T, int YE> static void add_yfwd(Ops& o) {
+        if constexpr (T > 0 && y_ok<T, YE, false>()) {
+            int& n = push(o, P_YFWD3, Variant{T, 0, YE, -1});
+            o.yfwd3[n++] = &ypass<T, -1, 3, YE>;
         }
     }
     template <int L> static void add_z(Ops& o) {
         if constexpr (z_ok<L>()) {
-            int& n = o.nvar[P_ZCROSS];
-            o.zcross[n] = &zcross<L>;
-            o.width[P_ZCROSS][n++] = L;
+            int& n = push(o, P_ZCROSS, Variant{L, 0, 0, -1});
+            o.zcross[n++] = &zcross<L>;
         }
     }
+    static int threads_per_line(int p, const Variant& d) {
+        if (p == P_YINV6 || p == P_YFWD3) return N / d.ye;
+        return p == P_ZCROSS ? G : GX;
+    }
     // index of the widest variant of pass p not wider than w whose
-    // workgroup has at most MAXT threads
-    static int pick(const Ops& o, int p, int w) {
-        const int per_line = (p == P_YINV6 || p == P_YFWD3) ? GY : (p == P_ZCROSS ? G : GX);
-        int best = 0;
-        for (int v = 0; v < o.nvar[p]; ++v)
-            if (o.width[p][v] <= w && per_line * o.width[p][v] <= MAXT) best = v;
+    // workgroup has at most MAXT threads and that matches the schedule
+    // (curl placement cy, y elements ye, XCD pairing preferred as `pair`);
+    // -1 if none
+    static int pick(const Ops& o, int p, int w, int cy, int ye, int pair) {
+        int best = -1;
+        for (int v = 0; v < o.nvar[p]; ++v) {
+            const Variant& d = o.var[p][v];
+            if (d.width > w || threads_per_line(p, d) * d.width > MAXT) continue;
+            if (d.cy >= 0 && d.cy != cy) continue;
+            if (d.ye > 0 && !(p == P_YINV6 && cy == 1) && d.ye != ye) continue;
+            if (best < 0) { best = v; continue; }
+            const Variant& b = o.var[p][best];
+            if (d.width > b.width || (d.width == b.width && d.pair == pair && b.pair != pair)) best = v;
+        }
         return best;
     }
     static Ops make() {
@@ -226,22 +292,47 @@ template <typename R, int N> struct Impl {
         o.real_size = sizeof(R);
         o.fs = Lay<R, N>::FS;
         o.tw_count = tw_size(N) > 0 ? tw_size(N) : 1;
-        add_x<4>(o); add_x<8>(o); add_x<16>(o); add_x<32>(o);
-        add_y<4>(o); add_y<8>(o); add_y<16>(o); add_y<32>(o);
+        if constexpr (CY0) {
+            // below 1024: the vorticity in the y pass at every width; the
+            // six-field x pass (curl in x) at the default width, with the
+            // plain inverse y pass at 8, 16 and 32 elements per thread
+            add_x<4, true, false>(o); add_x<8, true, false>(o); add_x<16, true, false>(o); add_x<32, true, false>(o);
+            add_x<4, true, true>(o); add_x<8, true, true>(o);
+            add_x<XD, false, false>(o);
+            add_ycurl<4>(o); add_ycurl<8>(o); add_ycurl<16>(o); add_ycurl<32>(o);
+            add_yinv<y_default_width<8>(), 8>(o);
+            add_yinv<y_default_width<16>(), 16>(o);
+            add_yinv<y_default_width<32>(), 32>(o);
+            add_yfwd<4, 8>(o); add_yfwd<8, 8>(o); add_yfwd<16, 8>(o); add_yfwd<32, 8>(o);
+            add_yfwd<y_default_width<16>(), 16>(o);
+            add_yfwd<y_default_width<32>(), 32>(o);
+        } else {
+            // 1024: six-field x pass, long y slices
+            add_x<4, false, false>(o); add_x<8, false, false>(o); add_x<16, false, false>(o);
+            add_x<4, false, true>(o); add_x<8, false, true>(o);
+            add_yinv<4, YE0>(o); add_yinv<8, YE0>(o); add_yinv<16, YE0>(o); add_yinv<32, YE0>(o);
+            add_yfwd<4, YE0>(o); add_yfwd<8, YE0>(o); add_yfwd<16, YE0>(o); add_yfwd<32, YE0>(o);
+        }
+        add_xr<4, false>(o); add_xr<8, false>(o); add_xr<16, false>(o); add_xr<32, false>(o);
+        add_xr<4, true>(o); add_xr<8, true>(o);
         add_z<1>(o); add_z<2>(o); add_z<4>(o); add_z<8>(o);
         add_z<16>(o); add_z<32>(o); add_z<64>(o); add_z<128>(o);
-        // defaults: 128-byte row segments in the x and y passes, four z lines
-        // per workgroup (eight for N = 256, two for N = 1024), the fastest
-        // measured on MI355X at 256^3, 512^3 and 1024^3; for small N, at
-        // least one full 64-lane wave per workgroup
-        const int wave = 64 / G;
-        const int xw = std::max((int)(128 / CB), wave), yw = xw;
-        o.def[P_XINV] = pick(o, P_XINV, xw);
-        o.def[P_XRHS] = pick(o, P_XRHS, xw);
-        o.def[P_XSTAGE] = pick(o, P_XSTAGE, xw);
-        o.def[P_YINV6] = pick(o, P_YINV6, yw);
-        o.def[P_YFWD3] = pick(o, P_YFWD3, yw);
-        o.def[P_ZCROSS] = pick(o, P_ZCROSS, std::max(N >= 1024 ? 2 : (N == 256 ? 8 : 4), wave));
+        // defaults, the fastest measured on MI355X at 256^3, 512^3 and
+        // 1024^3: 128-byte row segments in the x and y passes, four z lines
+        // per workgroup (eight for N = 256, two for N = 1024); for small N,
+        // at least one full 64-lane wave per workgroup.  At 1024 the x
+        // passes (64-byte rows) take the XCD-grouped tile order (stage pass
+        // 41.2 -> 38.1 ms FP64, 24.4 -> 22.3 ms FP32); the FP32 forward y
+        // pass at 512 holds 16 values per thread (0.638 -> 0.583 ms).
+        const int xw = want_width(G), yw = want_width(G);
+        const int cy = CY0 ? 1 : 0, pair = N >= 1024 ? 1 : 0;
+        const int ye = (std::is_same_v<R, float> && N == 512) ? 16 : YE0;
+        o.def[P_XINV] = pick(o, P_XINV, xw, cy, ye, pair);
+        o.def[P_XRHS] = pick(o, P_XRHS, xw, cy, ye, pair);
+        o.def[P_XSTAGE] = pick(o, P_XSTAGE, xw, cy, ye, pair);
+        o.def[P_YINV6] = pick(o, P_YINV6, yw, cy, ye, pair);
+        o.def[P_YFWD3] = pick(o, P_YFWD3, yw, cy, ye, pair);
+        o.def[P_ZCROSS] = pick(o, P_ZCROSS, std::max(N >= 1024 ? 2 : (N == 256 ? 8 : 4), 64 / G), cy, ye, pair);
         o.xinv3 = &xinv3;
         o.yinv3 = &yinv3;
         o.yfwd3s = &yfwd3s;
@@ -254,8 +345,9 @@ template <typename R, int N> struct Impl {
         o.ic_random = &ic_random;
         o.scale = &scale;
         if constexpr (std::is_same_v<R, float> && N >= 64) {
-            o.ymfma_inv6 = &ymfma<+1, 6>;
-            o.ymfma_fwd3 = &ymfma<-1, 3>;
+            o.ymfma_inv6[0] = &ymfma<+1, 6, false>;
+            if constexpr (CY0) o.ymfma_inv6[1] = &ymfma<+1, 6, true>;
+            o.ymfma_fwd3 = &ymfma<-1, 3, false>;
         }
         return o;
     }

@@ -101,17 +101,18 @@ template <int N, int T> constexpr int x_main_tiles() { return (N * (N / 2)) / T;
 //               (k_yinv_curl) forms the combinations with ky and kz;
 //   otherwise:  U, V, W, omega_x = i (ky W - kz V),
 //               omega_y = i (kz U - F(kx w_hat)), omega_z = i (F(kx v_hat) - ky U).
-// T lines (consecutive columns) per workgroup.
+// T lines (consecutive columns) per workgroup.  CY selects where the
+// vorticity combinations are formed (curl in y: five fields; else six).
 // ---------------------------------------------------------------------------
-// Five inverse x transforms of the velocity held in v[3] (x-spectral), written
-// to W as above.  Shared by the first stage's pass and the fused stage pass.
-template <typename R, int N, int T, bool NYQ>
+// Inverse x transforms of the velocity held in v[3] (x-spectral), written to
+// W as above.  Shared by the first stage's pass and the fused stage pass.
+template <typename R, int N, int T, bool NYQ, bool CY>
 __device__ __forceinline__ void xinv_curl_store(cx<R> (&v)[3][x_elems<R>(N)],
                                                 cx<R>* __restrict__ W, const XAddr<R, N, NYQ>& A, cx<R>* lt,
                                                 const cx<R>* twl, int g, int iky, int ikz) {
     constexpr int E = x_elems<R>(N), G = N / E;
     constexpr size_t FS = Lay<R, N>::FS;
-    if constexpr (!curl_in_y<R>(N)) {
+    if constexpr (!CY) {
         // the six fields u, v, w, omega (combinations formed here)
         const R ky = (R)iky, kz = (R)ikz;
         cx<R> b[E];
@@ -167,23 +168,23 @@ __device__ __forceinline__ void xinv_curl_store(cx<R> (&v)[3][x_elems<R>(N)],
     for (int m = 0; m < E; ++m) A(W + 2 * FS, m) = v[2][m];
 }
 
-template <typename R, int N, int T, bool NYQ>
+template <typename R, int N, int T, bool NYQ, bool CY>
 __device__ __forceinline__ void xinv_curl_tile(const cx<R>* __restrict__ U, cx<R>* __restrict__ W,
-                                               cx<R>* lds, const cx<R>* twl) {
+                                               cx<R>* lds, const cx<R>* twl, int tile) {
     constexpr int E = x_elems<R>(N), G = N / E;
     constexpr size_t FS = Lay<R, N>::FS;
     const int t = threadIdx.x % T, g = threadIdx.x / T;
-    const XCol<R, N, NYQ> col(blockIdx.x * T + t);
+    const XCol<R, N, NYQ> col(tile * T + t);
     const XAddr<R, N, NYQ> A(col, g);
     cx<R> v[3][E];
 #pragma unroll
     for (int f = 0; f < 3; ++f)
 #pragma unroll
         for (int m = 0; m < E; ++m) v[f][m] = A(U + f * FS, m);
-    xinv_curl_store<R, N, T, NYQ>(v, W, A, lds + t, twl, g, col.ky, col.kz);
+    xinv_curl_store<R, N, T, NYQ, CY>(v, W, A, lds + t, twl, g, col.ky, col.kz);
 }
 
-template <typename R, int N, int T>
+template <typename R, int N, int T, bool CY, bool PAIR>
 __global__ __launch_bounds__(N / x_elems<R>(N) * T)
 void k_xinv_curl(const cx<R>* __restrict__ U, cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t sst,
                  size_t wst) {
@@ -192,8 +193,9 @@ void k_xinv_curl(const cx<R>* __restrict__ U, cx<R>* __restrict__ W, const cx<R>
     __shared__ cx<R> lds[T * N];
     __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
     load_twiddles<R, N>(twl, tw);
-    if ((int)blockIdx.x < x_main_tiles<N, T>()) xinv_curl_tile<R, N, T, false>(U, W, lds, twl);
-    else xinv_curl_tile<R, N, T, true>(U, W, lds, twl);
+    const int tile = x_tile<PAIR ? line_group<R, T>() : 1>((int)blockIdx.x, x_main_tiles<N, T>());
+    if (tile < x_main_tiles<N, T>()) xinv_curl_tile<R, N, T, false, CY>(U, W, lds, twl, tile);
+    else xinv_curl_tile<R, N, T, true, CY>(U, W, lds, twl, tile);
 }
 
 // Plain inverse (DIR = +1) or forward (DIR = -1) x transform of NF fields
@@ -235,44 +237,64 @@ void k_xplain(const cx<R>* __restrict__ S, cx<R>* __restrict__ D, const cx<R>* _
 // consecutive ix, whose lines are contiguous; thread (l, g) holds elements
 // g + m G of line l, so consecutive threads read consecutive elements.
 // ---------------------------------------------------------------------------
-// Tile geometry of the y pass: the row offset of element m of this thread's
-// line, the line's place in shared memory, and the kz of the line.
-template <typename R, int N, int T, bool NYQ> struct YTile {
+// Tile geometry of the y pass (YE elements per thread): the place of
+// element m of this thread's line, the line's place in shared memory, and
+// the kz of the line.  Element m of a field F sits at F plus a byte offset
+// (shared by every field) of the tile's block blk plus this thread's column
+// and row off plus m G rows.  Where a field spans less than 4 GiB the whole
+// offset is one 32-bit value per element; above (N = 1024), F + blk is
+// formed as a uniform 64-bit base (scalar registers) and only off + m G RS
+// sizeof(C), below the plane size, is a 32-bit per-thread offset.
+template <typename R, int N, int T, bool NYQ, int YE> struct YTile {
     using L = Lay<R, N>;
-    static constexpr int E = y_elems<R>(N), G = N / E;
+    using C = cx<R>;
+    static constexpr int E = YE, G = N / E;
     static constexpr int ZT = (N / 2) / T;                 // main tiles per ix
     static constexpr unsigned RS = NYQ ? 1u : L::ZP;      // offset between rows iy
     static constexpr int PS = NYQ ? 1 : T;                 // shared-memory stride of a line
     int g, lo, kz;
-    unsigned base;
+    size_t blk;        // element offset of the tile's block (uniform)
+    unsigned off;      // byte offset of (line, row g) within the block
     __device__ __forceinline__ explicit YTile(int tile) {
         if constexpr (NYQ) {
             g = threadIdx.x % G;
             const int l = threadIdx.x / G;
-            base = (unsigned)L::MAIN + (unsigned)(tile * T + l) * N;
+            blk = L::MAIN + (size_t)tile * T * N;
+            off = ((unsigned)l * N + (unsigned)g) * (unsigned)sizeof(C);
             lo = l * N;
             kz = N / 2;
         } else {
             const int t = threadIdx.x % T;
             g = threadIdx.x / T;
             kz = (tile % ZT) * T + t;
-            base = (unsigned)(tile / ZT) * L::XP + (unsigned)kz;
+            blk = (size_t)(tile / ZT) * L::XP + (size_t)(tile % ZT) * T;
+            off = ((unsigned)t + (unsigned)g * RS) * (unsigned)sizeof(C);
             lo = t;
         }
     }
-    __device__ __forceinline__ unsigned at(int m) const { return base + (unsigned)(g + m * G) * RS; }
+    static constexpr bool WIDE = L::FS * sizeof(C) >= (size_t(1) << 32);
+    __device__ __forceinline__ C* ptr(C* F, int m) const {
+        const unsigned step = (unsigned)(G * RS * sizeof(C));
+        if constexpr (WIDE)
+            return reinterpret_cast<C*>(reinterpret_cast<char*>(F + blk) + (off + (unsigned)m * step));
+        else
+            return reinterpret_cast<C*>(reinterpret_cast<char*>(F) +
+                                        ((unsigned)blk * (unsigned)sizeof(C) + off + (unsigned)m * step));
+    }
     // element m of the line in the field starting at F
     template <bool NT = stream_io<R>(N)>
-    __device__ __forceinline__ GRef<cx<R>, NT> el(cx<R>* F, int m) const { return {field_el<R, N>(F, at(m))}; }
+    __device__ __forceinline__ GRef<C, NT> el(C* F, int m) const { return {ptr(F, m)}; }
 };
+static_assert((size_t)Lay<double, 1024>::XP * sizeof(double2) < (size_t(1) << 32),
+              "y-tile byte offsets within a plane must fit 32 bits");
 
-template <typename R, int N, int T, int DIR, int NF, bool NYQ>
+template <typename R, int N, int T, int DIR, int NF, bool NYQ, int YE>
 __device__ __forceinline__ void yline_tile(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, cx<R>* lds,
                                            int tile) {
-    using Y = YTile<R, N, T, NYQ>;
+    using Y = YTile<R, N, T, NYQ, YE>;
     constexpr int E = Y::E;
     constexpr size_t FS = Lay<R, N>::FS;
-    constexpr bool TWL = y_twiddles_in_lds<R>(N);
+    constexpr bool TWL = y_twiddles_in_lds(YE);
     // plain accesses: the forward pass, and the inverse pass of the
     // standalone transform (stage passes below 1024 use k_yinv_curl), whose
     // 64-byte FP32 rows measured 763 -> 1079 us per 512^3 launch streaming
@@ -302,7 +324,7 @@ __device__ __forceinline__ void yline_tile(cx<R>* __restrict__ W, const cx<R>* _
 // elements).
 template <typename R, int N, int T, bool NYQ>
 __device__ __forceinline__ void yinv_curl_tile(cx<R>* __restrict__ W, const cx<R>* twl, cx<R>* lds, int tile) {
-    using Y = YTile<R, N, T, NYQ>;
+    using Y = YTile<R, N, T, NYQ, 8>;
     constexpr int E = Y::E, G = Y::G;
     constexpr size_t FS = Lay<R, N>::FS;
     constexpr bool TWL = true;          // twiddles from shared memory: three lines live
@@ -354,12 +376,12 @@ __device__ __forceinline__ void yinv_curl_tile(cx<R>* __restrict__ W, const cx<R
 template <typename R, int N, int T> constexpr int y_main_tiles() { return N * ((N / 2) / T); }
 template <typename R, int N, int T> constexpr int y_tiles() { return y_main_tiles<R, N, T>() + N / T; }
 
-template <typename R, int N, int T, int DIR, int NF>
-__global__ __launch_bounds__(N / y_elems<R>(N) * T)
+template <typename R, int N, int T, int DIR, int NF, int YE>
+__global__ __launch_bounds__(N / YE * T)
 void k_yline(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
     W += blockIdx.y * wst;
     __shared__ cx<R> lds[T * N];
-    constexpr bool TWL = y_twiddles_in_lds<R>(N);
+    constexpr bool TWL = y_twiddles_in_lds(YE);
     __shared__ cx<R> twl[TWL ? tw_size(N) : 1];
     const cx<R>* t = tw;
     if constexpr (TWL) {
@@ -367,12 +389,12 @@ void k_yline(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
         t = twl;
     }
     const int b = blockIdx.x;
-    if (b < y_main_tiles<R, N, T>()) yline_tile<R, N, T, DIR, NF, false>(W, t, lds, b);
-    else yline_tile<R, N, T, DIR, NF, true>(W, t, lds, b - y_main_tiles<R, N, T>());
+    if (b < y_main_tiles<R, N, T>()) yline_tile<R, N, T, DIR, NF, false, YE>(W, t, lds, b);
+    else yline_tile<R, N, T, DIR, NF, true, YE>(W, t, lds, b - y_main_tiles<R, N, T>());
 }
 
 template <typename R, int N, int T>
-__global__ __launch_bounds__(N / y_elems<R>(N) * T)
+__global__ __launch_bounds__(N / 8 * T)
 void k_yinv_curl(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
     W += blockIdx.y * wst;
     __shared__ cx<R> lds[T * N];
@@ -829,9 +851,12 @@ __device__ __forceinline__ void rk_apply_stage(cx<R> (&nh)[3][E], const XCol<R, 
 }
 
 // Fixed-order tree reduction of the two diagnostic partial sums over a
-// workgroup of NT threads; thread 0 writes them to diag[2 blockIdx + {0, 1}].
+// workgroup of NT threads; thread 0 writes them to diag[2 slot + {0, 1}]
+// (slot = the tile, so that the partials do not depend on which workgroup
+// took which tile).
 template <int NT>
-__device__ __forceinline__ void diag_reduce(double (&red)[2][NT], double e_acc, double w_acc, double* diag) {
+__device__ __forceinline__ void diag_reduce(double (&red)[2][NT], double e_acc, double w_acc, double* diag,
+                                            int slot) {
     red[0][threadIdx.x] = e_acc;
     red[1][threadIdx.x] = w_acc;
     __syncthreads();
@@ -844,20 +869,20 @@ __device__ __forceinline__ void diag_reduce(double (&red)[2][NT], double e_acc, 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        diag[2 * blockIdx.x] = red[0][0];
-        diag[2 * blockIdx.x + 1] = red[1][0];
+        diag[2 * slot] = red[0][0];
+        diag[2 * slot + 1] = red[1][0];
     }
 }
 
 template <typename R, int N, int T, int STAGE, bool NYQ>
 __device__ __forceinline__ void xrhs_tile(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
                                           cx<R>* __restrict__ Us, const StageArgs& sa, cx<R>* lds, const cx<R>* twl,
-                                          double (&red)[2][N / x_elems<R>(N) * T]) {
+                                          double (&red)[2][N / x_elems<R>(N) * T], int tile) {
     constexpr int E = x_elems<R>(N), G = N / E;
     constexpr int NT = G * T;
     constexpr size_t FS = Lay<R, N>::FS;
     const int t = threadIdx.x % T, g = threadIdx.x / T;
-    const XCol<R, N, NYQ> col(blockIdx.x * T + t);
+    const XCol<R, N, NYQ> col(tile * T + t);
     cx<R> nh[3][E];
 #pragma unroll
     for (int f = 0; f < 3; ++f)
@@ -867,12 +892,12 @@ __device__ __forceinline__ void xrhs_tile(const cx<R>* __restrict__ W, cx<R>* __
     for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true>(nh[f], lds + t, T, twl, g);
     double e_acc = 0.0, w_acc = 0.0;
     rk_apply_stage<R, N, E, STAGE, NYQ, NT>(nh, col, g, U0, U1, Us, sa, e_acc, w_acc);
-    if (STAGE >= 3 && sa.diag) diag_reduce<NT>(red, e_acc, w_acc, sa.diag);
+    if (STAGE >= 3 && sa.diag) diag_reduce<NT>(red, e_acc, w_acc, sa.diag, tile);
 }
 
 // The RK stage is a template parameter: one kernel per stage gives each
 // its own straight-line code and register allocation.
-template <typename R, int N, int T, int STAGE>
+template <typename R, int N, int T, int STAGE, bool PAIR>
 __global__ __launch_bounds__(N / x_elems<R>(N) * T)
 void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
             cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa, size_t sst, size_t wst) {
@@ -885,8 +910,9 @@ void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restri
     __shared__ double red[2][N / x_elems<R>(N) * T];
     __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
     load_twiddles<R, N>(twl, tw);
-    if ((int)blockIdx.x < x_main_tiles<N, T>()) xrhs_tile<R, N, T, STAGE, false>(W, U0, U1, Us, sa, lds, twl, red);
-    else xrhs_tile<R, N, T, STAGE, true>(W, U0, U1, Us, sa, lds, twl, red);
+    const int tile = x_tile<PAIR ? line_group<R, T>() : 1>((int)blockIdx.x, x_main_tiles<N, T>());
+    if (tile < x_main_tiles<N, T>()) xrhs_tile<R, N, T, STAGE, false>(W, U0, U1, Us, sa, lds, twl, red, tile);
+    else xrhs_tile<R, N, T, STAGE, true>(W, U0, U1, Us, sa, lds, twl, red, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -898,15 +924,15 @@ void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restri
 // before fields 0..4 are written; a workgroup owns its columns, so this is
 // safe in place.
 // ---------------------------------------------------------------------------
-template <typename R, int N, int T, int STAGE, bool NYQ>
+template <typename R, int N, int T, int STAGE, bool NYQ, bool CY>
 __device__ __forceinline__ void xstage_tile(cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
                                             cx<R>* __restrict__ Us, const StageArgs& sa, cx<R>* lds,
-                                            const cx<R>* twl, double (&red)[2][N / x_elems<R>(N) * T]) {
+                                            const cx<R>* twl, double (&red)[2][N / x_elems<R>(N) * T], int tile) {
     constexpr int E = x_elems<R>(N), G = N / E;
     constexpr int NT = G * T;
     constexpr size_t FS = Lay<R, N>::FS;
     const int t = threadIdx.x % T, g = threadIdx.x / T;
-    const XCol<R, N, NYQ> col(blockIdx.x * T + t);
+    const XCol<R, N, NYQ> col(tile * T + t);
     const XAddr<R, N, NYQ> A(col, g);
 
     cx<R> u[3][E];
@@ -919,13 +945,13 @@ __device__ __forceinline__ void xstage_tile(cx<R>* __restrict__ W, cx<R>* __rest
     for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true>(u[f], lt, T, twl, g);
     double e_acc = 0.0, w_acc = 0.0;
     rk_apply_stage<R, N, E, STAGE, NYQ, NT>(u, col, g, U0, U1, Us, sa, e_acc, w_acc);
-    if (STAGE >= 3 && sa.diag) diag_reduce<NT>(red, e_acc, w_acc, sa.diag);
+    if (STAGE >= 3 && sa.diag) diag_reduce<NT>(red, e_acc, w_acc, sa.diag, tile);
 
     // inverse x transforms for the next stage's velocity and vorticity
-    xinv_curl_store<R, N, T, NYQ>(u, W, A, lt, twl, g, col.ky, col.kz);
+    xinv_curl_store<R, N, T, NYQ, CY>(u, W, A, lt, twl, g, col.ky, col.kz);
 }
 
-template <typename R, int N, int T, int STAGE>
+template <typename R, int N, int T, int STAGE, bool CY, bool PAIR>
 __global__ __launch_bounds__(N / x_elems<R>(N) * T)
 void k_xstage(cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
               cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa, size_t sst, size_t wst) {
@@ -938,8 +964,11 @@ void k_xstage(cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__
     __shared__ double red[2][N / x_elems<R>(N) * T];
     __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
     load_twiddles<R, N>(twl, tw);
-    if ((int)blockIdx.x < x_main_tiles<N, T>()) xstage_tile<R, N, T, STAGE, false>(W, U0, U1, Us, sa, lds, twl, red);
-    else xstage_tile<R, N, T, STAGE, true>(W, U0, U1, Us, sa, lds, twl, red);
+    const int tile = x_tile<PAIR ? line_group<R, T>() : 1>((int)blockIdx.x, x_main_tiles<N, T>());
+    if (tile < x_main_tiles<N, T>())
+        xstage_tile<R, N, T, STAGE, false, CY>(W, U0, U1, Us, sa, lds, twl, red, tile);
+    else
+        xstage_tile<R, N, T, STAGE, true, CY>(W, U0, U1, Us, sa, lds, twl, red, tile);
 }
 
 // ---------------------------------------------------------------------------

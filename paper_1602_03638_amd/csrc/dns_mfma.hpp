@@ -16,9 +16,9 @@
 // Fl xh + Fh xl + Fh xh are accumulated in FP32 (the Fl xl term, 2^-22
 // relative, is dropped).  The remaining stages run in FP32 as in the plain
 // y pass.  Lines of the kz = N/2 plane take the plain FP32 y transform.
-// Where the y pass forms the vorticity combinations (curl_in_y), the inverse
-// pass of a stage (CURL) forms those of k_yinv_curl as it stages each
-// output's tile, in the same field order.
+// Where the y pass forms the vorticity combinations (the plan's curl
+// placement), the inverse pass of a stage (CURL) forms those of k_yinv_curl
+// as it stages each output's tile, in the same field order.
 #pragma once
 
 #include "dns_kernels.hpp"
@@ -39,7 +39,8 @@ template <int N> struct MfmaY {
     static constexpr int G2 = N2 / E2;                      // threads per sub-transform
     static constexpr int ROUNDS = 16 * MFMA_T * G2 / NT;    // rounds of sub-transforms per field
     static constexpr int RPT = NT / MFMA_T;                 // rows per pass of the tile load
-    static constexpr int GY = N / y_elems<float>(N);        // threads per line, plain y transform
+    static constexpr int YE = default_y_elems<float>(N);     // elements per thread, plain y transform
+    static constexpr int GY = N / YE;                        // threads per line, plain y transform
     static constexpr int TN = NT / GY;                      // Nyquist-plane lines per workgroup
     static constexpr int MAIN_TILES = N * ((N / 2) / MFMA_T);
     static constexpr int TILES = MAIN_TILES + N / TN;
@@ -227,7 +228,7 @@ __device__ __forceinline__ void ymfma_tile(cx<float>* __restrict__ W, const cx<f
     }
 }
 
-template <int N, int DIR, int NF>
+template <int N, int DIR, int NF, bool CURL>
 __global__ __launch_bounds__(MfmaY<N>::NT)
 void k_yline_mfma(cx<float>* __restrict__ W, const cx<float>* __restrict__ tw, const cx<float>* __restrict__ roots,
                   const cx<float>* __restrict__ tw2, size_t wst) {
@@ -236,9 +237,10 @@ void k_yline_mfma(cx<float>* __restrict__ W, const cx<float>* __restrict__ tw, c
     __shared__ cx<float> xs[M::LDS];
     __shared__ cx<float> tw2l[tw_size(M::N2) > 0 ? tw_size(M::N2) : 1];
     __shared__ float red[M::WAVES];
-    constexpr bool TWL = y_twiddles_in_lds<float>(N);
+    constexpr bool TWL = y_twiddles_in_lds(M::YE);
     __shared__ cx<float> twl[TWL ? tw_size(N) : 1];
-    constexpr bool CURL = curl_in_y<float>(N) && DIR > 0 && NF == 6;   // inverse pass of a stage
+    // CURL: the inverse pass of a stage forms the vorticity (five input fields)
+    static_assert(!CURL || (DIR > 0 && NF == 6 && M::YE == 8), "vorticity in the y pass: inverse, 6 fields, 8 per thread");
     const int b = blockIdx.x;
     if (b < M::MAIN_TILES) {
         load_twiddles<float, M::N2>(tw2l, tw2);
@@ -250,7 +252,7 @@ void k_yline_mfma(cx<float>* __restrict__ W, const cx<float>* __restrict__ tw, c
             t = twl;
         }
         if constexpr (CURL) yinv_curl_tile<float, N, M::TN, true>(W, t, xs, b - M::MAIN_TILES);
-        else yline_tile<float, N, M::TN, DIR, NF, true>(W, t, xs, b - M::MAIN_TILES);
+        else yline_tile<float, N, M::TN, DIR, NF, true, M::YE>(W, t, xs, b - M::MAIN_TILES);
     }
 }
 

@@ -1,14 +1,25 @@
 // Host-side launch table of the kernels for one (real type, N) pair, with
-// the tile-shape variants the autotuner chooses between.  Every variant of a
-// pass runs the same per-line arithmetic, so all variants give bitwise
-// identical results; they differ only in how many lines share a workgroup.
+// the variants the autotuner chooses between.  Every variant of a pass runs
+// the same per-line arithmetic, so all variants give bitwise identical
+// results; they differ in how many lines share a workgroup (width), in the
+// order in which workgroups take tiles (XCD pairing), in how many elements a
+// y-pass thread holds, and in which kernel forms the vorticity combinations.
 #pragma once
 
 #include "dns_common.hpp"
 
 namespace dns {
 
-constexpr int MAXV = 4;   // variants per pass
+constexpr int MAXV = 16;   // variants per pass
+
+// Descriptor of one variant of a pass.
+struct Variant {
+    int width;   // lines (columns) per workgroup
+    int pair;    // 1: x tiles sharing 128-byte lines go to one XCD (x passes); else 0
+    int ye;      // y passes: complex values per thread (8, 16, 32); 0 for other passes
+    int cy;      // 1: vorticity formed in the inverse y pass (five x-pass fields), 0: in the
+                 // x pass (six fields); -1 for passes that do not depend on it
+};
 
 // The kernels of a stage: the inverse x pass with the curl (first stage
 // only when fused), the inverse y pass, the fused z pass, the forward y
@@ -31,10 +42,10 @@ struct Ops {
     size_t real_size;      // bytes of one real value
     size_t fs;             // complex values of one field in the internal layout
     int tw_count;          // complex entries of the twiddle table
-    // variants of the five passes of one RK4 stage; width[p][v] is the
-    // number of lines per workgroup of variant v of pass p
+    // variants of the passes of one RK4 stage; var[p][v] describes variant v
+    // of pass p
     int nvar[P_COUNT];
-    int width[P_COUNT][MAXV];
+    Variant var[P_COUNT][MAXV];
     int def[P_COUNT];      // default variant (before tuning)
     XinvFn xinv[MAXV];
     YFn yinv6[MAXV];
@@ -44,8 +55,9 @@ struct Ops {
     XrhsFn xstage[MAXV];
     int xrhs_groups[MAXV]; // workgroups of each xrhs variant (= fused diagnostic partials)
     int xstage_groups[MAXV];
-    // y passes with the matrix-core DFT stage (FP32, N >= 64; else nullptr)
-    YMfmaFn ymfma_inv6;
+    // y passes with the matrix-core DFT stage (FP32, N >= 64; else nullptr);
+    // the inverse one per curl placement ([0]: six input fields, [1]: five)
+    YMfmaFn ymfma_inv6[2];
     YMfmaFn ymfma_fwd3;
     // standalone transforms and utilities (default shapes)
     void (*xinv3)(const void* U, void* W, const void* tw, hipStream_t s);

@@ -114,3 +114,34 @@ def test_workspace_bytes_and_validation(lib):
     h = ctypes.c_void_p()
     assert lib.dns_create_ws(64, 0.01, 0.01, dns.DNS_FP64, None, None, 1 << 30, None, ctypes.byref(h)) == \
         dns.DNS_E_INVAL
+
+
+def test_plan_cache_file_round_trip(tmp_path):
+    """The tuned-plan cache file (dns_plan_cache_save / _load, no GPU needed):
+    plans read from a file are counted, written back as valid JSON with the
+    same descriptors, and cleared."""
+    import json
+    import paper_1602_03638_amd as dns
+    lib = dns.load_library()
+    lib.dns_plan_cache_clear()
+    src = tmp_path / "plans.json"
+    src.write_text(
+        '{"format": "dns-plan-cache-1", "plans": [\n'
+        '{"device": "gfx950|MI355X|256", "N": 512, "dtype": 0, "members": 1, "variants": '
+        '[[8, 0, 0, 1], [8, 0, 8, 1], [4, 0, 0, -1], [8, 0, 8, -1], [8, 0, 0, -1], [8, 0, 0, 1]]},\n'
+        '{"device": "gfx950|MI355X|256", "N": 1024, "dtype": 1, "members": 1, "variants": '
+        '[[8, 1, 0, 0], [16, 0, 32, 0], [2, 0, 0, -1], [16, 0, 32, -1], [8, 1, 0, -1], [8, 1, 0, 0]]}\n'
+        ']}\n')
+    assert dns.plan_cache_load(str(src)) == 2
+    assert dns.plan_cache_entries() == 2
+    out = tmp_path / "out.json"
+    dns.plan_cache_save(str(out))
+    rec = json.loads(out.read_text())
+    assert rec["format"] == "dns-plan-cache-1" and len(rec["plans"]) == 2
+    by_n = {p["N"]: p for p in rec["plans"]}
+    assert by_n[1024]["variants"][0] == [8, 1, 0, 0] and by_n[1024]["dtype"] == 1
+    assert by_n[512]["variants"][1] == [8, 0, 8, 1] and by_n[512]["device"] == "gfx950|MI355X|256"
+    with pytest.raises(dns.DnsError):
+        dns.plan_cache_load(str(tmp_path / "missing.json"))
+    dns.plan_cache_clear()
+    assert dns.plan_cache_entries() == 0

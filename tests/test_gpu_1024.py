@@ -2,10 +2,15 @@
 nu = 1e-3, dt = 5e-4, seed 1, k0 = 4, E = 0.5).
 
 The oracle cannot hold a 1024^3 field, so the checks use results fixed by
-the mathematics at any size:
+the mathematics at any size, and the oracle at a size it can evaluate:
+  * the right-hand side of a band-limited broadband field (|k_i| <= 21) is
+    the same at every N >= 128 up to the scale (N/128)^3, so the default
+    1024^3 schedule (six-field x pass, long y slices, 64-bit addressing) is
+    compared element by element with the oracle at 128^3;
   * the forward transform of a sum of plane waves a cos(k . x + phi) is
     N^3 a e^{i phi} / 2 at k and zero at every other stored mode (closed form
-    of the DFT, which pins axis order, sign and normalisation);
+    of the DFT, which pins axis order, sign and normalisation), and the
+    inverse transform of that spectrum is the sum of cosines;
   * the random initial field has E = 0.5 and the semi-discrete energy budget
     dE/dt = -2 nu Omega holds over RK4 steps (trapezoid rule);
   * FP32 and FP64 runs from the same spectrum agree in energy to 1e-5.
@@ -16,6 +21,7 @@ import numpy as np
 import pytest
 
 from gpu_util import note, torch_mod
+from test_gpu_fullsize import band_rhs, check_band_rhs  # noqa: F401  (fixture)
 
 pytestmark = pytest.mark.gpu
 
@@ -109,3 +115,68 @@ def test_random_isotropic_1024_budget_and_precision():
     assert abs(e32 - E[2]) / E[2] <= 1e-5
     assert abs(w32 - W[2]) / W[2] <= 1e-5
     assert np.isfinite(e32) and np.isfinite(w32)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 5e-6), ("f64", 1e-12)])
+def test_rhs_1024_band_limited_matches_oracle_128(dtype, tol, band_rhs):
+    """1024^3 right-hand side of a broadband band-limited field against the
+    oracle at 128^3, element by element over |k_i| <= 42 and zero elsewhere:
+    the paths only the 1024^3 default runs (vorticity formed in the x pass,
+    16/32 values per y-pass thread, fields beyond 4 GiB)."""
+    note(f"band rhs 1024 {dtype}")
+    check_band_rhs(N, dtype, band_rhs, tol)
+    torch_mod().cuda.empty_cache()
+
+
+def test_rhs_1024_xcd_grouped_tiles_bitwise(band_rhs):
+    """The XCD-grouped x passes (both tiles of a 128-byte line on one XCD)
+    compute the same bits as the plain tile order: the right-hand side and
+    one RK4 step at 1024^3 FP32."""
+    note("1024 fp32 xcd grouping bitwise")
+    torch = torch_mod()
+    from gpu_util import embed_on_device
+    from paper_1602_03638_amd import Solver
+    uh, _, nu = band_rhs
+    outs = []
+    for pair in (False, True):
+        s = Solver(N, nu, DT, dtype="f32", xcd_pair=pair)
+        sched = s.schedule()
+        assert sched["xstage"]["xcd_pair"] == int(pair) and sched["xrhs_rk4"]["xcd_pair"] == int(pair)
+        dev = embed_on_device(uh.astype(np.complex64), N, "f32", 21)
+        s.set_spectral(dev)
+        r = s.rhs()
+        s.set_spectral(dev).step(1)
+        del dev
+        outs.append((r.cpu(), s.get_spectral().cpu()))
+        del r
+        s.close()
+        torch.cuda.empty_cache()
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 2e-6)])
+def test_inverse_1024_plane_waves(dtype, tol):
+    """dns_inverse of the plane-wave spectrum (N^3 a e^{i phi} / 2 at each k)
+    is the sum of cosines a cos(k . x + phi) at every mesh point."""
+    note(f"inverse 1024 {dtype} plane waves")
+    torch = torch_mod()
+    from paper_1602_03638_amd import Solver
+    cdt = torch.complex128 if dtype == "f64" else torch.complex64
+    uh = torch.zeros((3, N, N, N // 2 + 1), dtype=cdt, device="cuda")
+    for c, waves in enumerate(WAVES):
+        for kx, ky, kz, a, phi in waves:
+            uh[c, kx % N, ky % N, kz] = float(N) ** 3 * a * complex(math.cos(phi), math.sin(phi)) / 2
+    torch.cuda.empty_cache()
+    s = Solver(N, NU, DT, dtype=dtype)
+    u = s.inverse(uh)
+    s.close()
+    del uh
+    torch.cuda.empty_cache()
+    want = _plane_waves(torch, dtype)
+    amp = sum(abs(w[3]) for w in WAVES[0])
+    err = float((u - want).abs().max().item()) / amp
+    note(f"  max error {err:.2e}")
+    assert err <= tol
+    del u, want
+    torch.cuda.empty_cache()

@@ -183,3 +183,61 @@ def test_ensemble_errors():
         ens.set_spectral(0, to_dev(workloads.random_half_spectrum(8, 1), "f64"))
     with pytest.raises(DnsError):
         _ensemble([16, 12], [0.01, 0.01], [0.01, 0.01])
+
+
+def test_ensemble_configured_classes_fp32():
+    """The classes of the benchmark's ensemble (32^3, 64^3 and 128^3, FP32,
+    nu = 0.01, dt = 0.005, seeds 1000 + j, k0 = 4, E = 0.5): after 3 steps
+    every member is bitwise the standalone run, batched and in one graph
+    launch alike; a 64^3 member against the FP64 oracle from the same (FP32
+    rounded) start (relative L2 <= 2e-5, energy <= 1e-5)."""
+    note("ensemble 32/64/128 fp32 vs standalone and oracle")
+    Ns = [32, 64, 128, 32, 64, 128, 64]
+    nu, dt = 0.01, 0.005
+    ens = _ensemble(Ns, [nu] * len(Ns), [dt] * len(Ns), dtype="f32")
+    assert ens.classes() == 3
+    for j in range(len(Ns)):
+        ens.init_random(j, 1000 + j, k0=4.0, energy=0.5)
+    init = [ens.get_spectral(j).clone() for j in range(len(Ns))]
+    ens.step(3)
+    batched = [to_host(ens.get_spectral(j)) for j in range(len(Ns))]
+    for j, h in enumerate(init):
+        ens.set_spectral(j, h)
+    ens.step(3, one_graph=True)
+    one = [to_host(ens.get_spectral(j)) for j in range(len(Ns))]
+    for j, N in enumerate(Ns):
+        alone = _solver(N, nu, dt, dtype="f32").set_spectral(init[j]).step(3)
+        ref = to_host(alone.get_spectral())
+        assert np.array_equal(batched[j], ref), j
+        assert np.array_equal(one[j], ref), j
+        alone.close()
+    j = 4
+    orc = spectral.Solver(64, nu, dt).set_spectral(to_host(init[j])).step(3)
+    assert spectral_rel_l2(batched[j], orc.uh) <= 2e-5
+    E, _ = ens.diagnostics()
+    assert abs(E[j] - orc.energy()) <= 1e-5 * orc.energy()
+    ens.close()
+
+
+def test_ensemble_one_graph_launch_equals_replays():
+    """100 steps of a mixed ensemble captured into one graph give the bits of
+    100 one-step graph replays; a second call with the same step count reuses
+    the graph, another count captures anew."""
+    note("ensemble one-graph 100 steps")
+    Ns = [32, 64, 32, 16]
+    nu, dt = 0.01, 0.005
+    a = _ensemble(Ns, [nu] * 4, [dt] * 4, dtype="f32")
+    b = _ensemble(Ns, [nu] * 4, [dt] * 4, dtype="f32")
+    for j in range(4):
+        a.init_random(j, 1100 + j)
+        b.init_random(j, 1100 + j)
+    a.step(100, one_graph=True)
+    b.step(100)
+    for j in range(4):
+        assert np.array_equal(to_host(a.get_spectral(j)), to_host(b.get_spectral(j))), j
+    a.step(7, one_graph=True).step(100, one_graph=True)
+    b.step(107)
+    for j in range(4):
+        assert np.array_equal(to_host(a.get_spectral(j)), to_host(b.get_spectral(j))), j
+    a.close()
+    b.close()

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import workloads
-from gpu_util import embed_low_modes, note, to_dev, to_host
+from gpu_util import band_limited_spectrum, box_index, embed_low_modes, embed_on_device, note, to_dev, to_host
 from oracle import spectral
 
 pytestmark = pytest.mark.gpu
@@ -93,3 +93,90 @@ def test_forward_512_sampled_modes(dtype, tol):
         want = spectral.dft3_mode(u, ix, iy, iz)
         assert np.max(np.abs(got - want)) / scale <= tol, (ix, iy, iz)
     s.close()
+
+
+# Band-limited broadband field: |k_i| <= KB, so u x omega has |k_i| <= 2 KB = 42,
+# inside the 2/3-rule mask of 128^3 (3 * 42 < 128) and free of aliasing there.
+KB, N_ORACLE = 21, 128
+
+
+@pytest.fixture(scope="module")
+def band_rhs():
+    """A band-limited random solenoidal field and its right-hand side from the
+    oracle at 128^3 (nu = 0.0137)."""
+    uh = band_limited_spectrum(N_ORACLE, seed=421, kb=KB)
+    nu = 0.0137
+    r = spectral.rhs(uh, nu, spectral.wavenumber_mesh(N_ORACLE), spectral.dealias_mask(N_ORACLE))
+    return uh, r, nu
+
+
+def check_band_rhs(N, dtype, band_rhs, tol, **sched):
+    """dns_rhs at N^3 of the band-limited field against the oracle's 128^3
+    right-hand side: every mode of the box |k_i| <= 2 KB element by element
+    (scaled by (N/128)^3), and every mode outside the box (the zero high
+    modes, the masked modes and the Nyquist planes) zero to rounding.
+    Returns the relative L2 error over all stored modes."""
+    torch = __import__("torch")
+    uh, ref, nu = band_rhs
+    src = uh if dtype == "f64" else uh.astype(np.complex64).astype(np.complex128)
+    if dtype == "f32":
+        ref = spectral.rhs(src, nu, spectral.wavenumber_mesh(N_ORACLE), spectral.dealias_mask(N_ORACLE))
+    from paper_1602_03638_amd import Solver
+    s = Solver(N, nu, 1e-3, dtype=dtype, **sched)
+    dev = embed_on_device(src, N, dtype, KB)
+    s.set_spectral(dev)
+    del dev
+    out = s.rhs()
+    s.close()
+    scale = (float(N) / N_ORACLE) ** 3
+    kb2 = 2 * KB
+    bi = box_index(N, kb2, torch)
+    got = np.stack([to_host(out[c][bi]) for c in range(3)]) / scale
+    want = ref[(slice(None),) + box_index(N_ORACLE, kb2)]
+    for c in range(3):
+        out[c][bi] = 0
+    w_out = float(torch.linalg.vector_norm(out).item()) / scale    # everything outside the box
+    del out
+    torch.cuda.empty_cache()
+    wz = np.full(kb2 + 1, 2.0)
+    wz[0] = 1.0
+    num = np.sqrt(np.sum(wz * np.abs(got - want) ** 2) + 2 * w_out ** 2)
+    den = np.sqrt(np.sum(wz * np.abs(want) ** 2))
+    err = float(num / den)
+    note(f"  band rhs N={N} {dtype}: rel L2 {err:.2e} (outside box {w_out / den:.1e})")
+    assert err <= tol
+    return err
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 2e-5)])
+def test_rhs_512_band_limited_matches_oracle_128(dtype, tol, band_rhs):
+    """512^3 right-hand side of a broadband band-limited field, element by
+    element against the oracle evaluated at 128^3 (the launch configuration
+    of the benchmark: default plan)."""
+    note(f"band rhs 512 {dtype}")
+    check_band_rhs(512, dtype, band_rhs, tol)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 5e-6)])
+def test_inverse_512_sampled_points(dtype, tol):
+    """dns_inverse of a random (not Hermitian) 512^3 half spectrum: sampled
+    physical values against the oracle's point evaluation of the definition
+    (which keeps numpy irfftn's treatment of the kz = 0 and N/2 bins),
+    relative to the field's rms."""
+    note(f"inverse 512 {dtype} sampled points")
+    N = 512
+    h = workloads.random_half_spectrum(N, seed=5120)
+    if dtype == "f32":
+        h = h.astype(np.complex64).astype(np.complex128)
+    s = _solver(N, dtype)
+    u = s.inverse(to_dev(h, dtype))
+    s.close()
+    rms = float(u.double().pow(2).mean().sqrt().item())
+    rng = np.random.default_rng(3)
+    pts = [(0, 0, 0), (N - 1, N - 1, N - 1), (1, 2, 3), (N // 2, 7, N // 2 + 1)] + \
+          [tuple(int(v) for v in rng.integers(0, N, 3)) for _ in range(4)]
+    for i, j, l in pts:
+        want = spectral.idft3_point(h, i, j, l)
+        got = to_host(u[:, i, j, l])
+        assert np.max(np.abs(got - want)) / rms <= tol, (i, j, l, got, want)
+    del u

@@ -232,23 +232,90 @@ def test_nonfinite_energy_reported():
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("N", [8, 16, 32, 64])
 def test_every_plan_variant_is_bitwise_identical(N, dtype):
-    """Tile-shape variants change only how lines share a workgroup, never the
-    arithmetic: every variant of every pass gives identical bits."""
+    """Variants change how lines share a workgroup, which workgroup takes a
+    tile, how many values a y-pass thread holds and which kernel combines
+    the vorticity, never the arithmetic: every variant of every pass gives
+    identical bits, and so does the autotuner's choice."""
     note(f"plan variants N={N} {dtype}")
     uh0 = ic.random_isotropic(N, seed=77)
     s = _solver(N, 0.01, 0.005, dtype=dtype)
-    base = s.plan()
+    base = s.plan_ex()
+    var = s.plan_variants_ex()
     ref = to_host(s.set_spectral(to_dev(uh0, dtype)).step(2).get_spectral())
-    for p, widths in s.plan_variants().items():
-        for w in widths:
-            plan = dict(base)
-            plan[p] = w
-            s.set_plan(plan)
+    for p, vs in var.items():
+        for v in range(len(vs)):
+            s.set_plan_ex(s.plan_with(p, v, base))
             got = to_host(s.set_spectral(to_dev(uh0, dtype)).step(2).get_spectral())
-            assert np.array_equal(got, ref), (p, w)
+            assert np.array_equal(got, ref), (p, vs[v])
     tuned = s.autotune()
     got = to_host(s.set_spectral(to_dev(uh0, dtype)).step(2).get_spectral())
     assert np.array_equal(got, ref), tuned
+
+
+def _long_y(dtype):
+    """The schedule of the 1024^3 default: six-field x pass (vorticity formed
+    in the x pass) and 16 (FP64) / 32 (FP32) values per y-pass thread."""
+    return dict(y_elems=16 if dtype == "f64" else 32, curl_in_y=False)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("N", [64, 128])
+def test_rhs_with_1024_schedule_matches_oracle(N, dtype):
+    """The code the 1024^3 default runs (six-field x pass with the curl
+    combinations of the Sec. 3.1 Curl listing formed there; long y slices with
+    twiddles in shared memory), selected at a size the oracle evaluates:
+    broadband right-hand side element by element, then two fused RK4 steps
+    bitwise equal to the default schedule."""
+    note(f"rhs 1024-schedule N={N} {dtype}")
+    nu = 0.0137
+    uh = _rhs_input(N, seed=60 + N)
+    s = _solver(N, nu=nu, dtype=dtype, **_long_y(dtype))
+    sched = s.schedule()
+    assert sched["xinv_curl"]["curl_in_y"] == 0 and sched["xstage"]["curl_in_y"] == 0
+    assert sched["yinv6"]["y_elems"] == _long_y(dtype)["y_elems"]
+    assert sched["yfwd3"]["y_elems"] == _long_y(dtype)["y_elems"]
+    got = to_host(s.set_spectral(to_dev(uh, dtype)).rhs())
+    src = uh if dtype == "f64" else uh.astype(np.complex64).astype(np.complex128)
+    ref = spectral.rhs(src, nu, spectral.wavenumber_mesh(N), spectral.dealias_mask(N))
+    err = spectral_rel_l2(got, ref)
+    note(f"  rel L2 {err:.2e}")
+    assert err <= (TOL_F64 if dtype == "f64" else 2e-5)
+    a = to_host(s.set_spectral(to_dev(uh, dtype)).step(2).get_spectral())
+    d = _solver(N, nu=nu, dtype=dtype)
+    b = to_host(d.set_spectral(to_dev(uh, dtype)).step(2).get_spectral())
+    assert np.array_equal(a, b)
+    for x in (s, d):
+        x.close()
+
+
+def test_schedule_errors():
+    """Schedules the library does not provide are refused, the plan is left
+    as it was, and inconsistent explicit plans are rejected."""
+    from paper_1602_03638_amd import DNS_E_INVAL, DNS_E_UNSUPPORTED, DnsError
+    note("schedule errors")
+    s = _solver(32)
+    before = s.plan_ex()
+    small = _solver(16)
+    with pytest.raises(DnsError) as e:
+        small.set_schedule(y_elems=32, curl_in_y=False)  # 32 values per thread: lines of at least 32
+    assert e.value.status == DNS_E_UNSUPPORTED
+    small.close()
+    with pytest.raises(DnsError) as e:
+        s.set_schedule(xcd_pair=True)                    # no 64-byte rows at 32^3
+    assert e.value.status == DNS_E_UNSUPPORTED
+    assert s.plan_ex() == before
+    var = s.plan_variants_ex()
+    plan = dict(before)
+    plan["xinv_curl"] = [i for i, d in enumerate(var["xinv_curl"]) if d["curl_in_y"] == 0][0]
+    with pytest.raises(DnsError) as e:
+        s.set_plan_ex(plan)
+    assert e.value.status == DNS_E_INVAL
+    s.set_schedule(curl_in_y=False)
+    assert s.schedule()["yinv6"]["curl_in_y"] == 0
+    s.set_schedule(y_elems=16, curl_in_y=True)           # the combining inverse pass keeps 8
+    sched = s.schedule()
+    assert sched["yinv6"]["y_elems"] == 8 and sched["yfwd3"]["y_elems"] == 16
+    s.close()
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -328,6 +395,47 @@ def test_autotuned_plan_is_cached():
         s.close()
     dns.plan_cache_clear()
     assert dns.plan_cache_entries() == 0
+
+
+def test_plan_cache_persists_across_processes(tmp_path):
+    """A tuned plan saved to a file and read back is taken by a new context
+    (same variants, same bits); with DNS_PLAN_CACHE set, one process's
+    autotune is written to the file and a second process reuses it."""
+    import os
+    import subprocess
+    import sys
+    import paper_1602_03638_amd as dns
+    note("plan cache file")
+    dns.plan_cache_clear()
+    N = 64
+    a = _solver(N, dtype="f32", autotune=True)
+    plan = a.schedule()
+    path = str(tmp_path / "plans.json")
+    dns.plan_cache_save(path)
+    dns.plan_cache_clear()
+    assert dns.plan_cache_load(path) == 1
+    b = _solver(N, dtype="f32", autotune=True)
+    assert b.schedule() == plan and dns.plan_cache_entries() == 1
+    uh0 = ic.random_isotropic(N, seed=1009)
+    ra = to_host(a.set_spectral(to_dev(uh0, "f32")).step(2).get_spectral())
+    rb = to_host(b.set_spectral(to_dev(uh0, "f32")).step(2).get_spectral())
+    assert np.array_equal(ra, rb)
+    a.close()
+    b.close()
+    dns.plan_cache_clear()
+    env_path = str(tmp_path / "env_plans.json")
+    child = ("import json, sys; sys.path.insert(0, %r); import paper_1602_03638_amd as d; "
+             "s = d.Solver(32, 0.01, 0.005, autotune=True); n = d.plan_cache_entries(); "
+             "print(json.dumps([n, s.schedule()]))") % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))),)
+    env = dict(os.environ, DNS_PLAN_CACHE=env_path)
+    first = subprocess.run([sys.executable, "-c", child], env=env, capture_output=True, text=True, timeout=120)
+    assert first.returncode == 0, first.stderr[-2000:]
+    assert os.path.exists(env_path)
+    second = subprocess.run([sys.executable, "-c", child], env=env, capture_output=True, text=True, timeout=120)
+    assert second.returncode == 0, second.stderr[-2000:]
+    n1, s1 = json.loads(first.stdout.strip().splitlines()[-1])
+    n2, s2 = json.loads(second.stdout.strip().splitlines()[-1])
+    assert n1 == 1 and n2 == 1 and s1 == s2
 
 
 def test_caller_workspace_matches_library_allocation():
