@@ -30,21 +30,23 @@ N_DEFAULT, NU, DT = 512, 1.0 / 1600, 1e-3
 # next stage.  Below N = 1024 the inverse y pass forms the vorticity from
 # five x-pass fields (U, V, W, F(kx v), F(kx w)): xinv_curl 3C + 5C,
 # yinv6 5C + 6C, xstage 12C + 5C, fused step 4 * (11 + 9 + 6 + 17) C = 172 C.
-# At N = 1024 the x pass writes all six: 9C, 12C, 18C and 180 C per step.
+# Where the x pass writes all six (the default at N = 1024, or a plan with
+# the vorticity formed in the x pass): 9C, 12C, 18C and 180 C per step.
 # Unfused (either): 4 * (9 + 27) C + 48 C = 192 C.
-def curl_in_y(N):
-    """True where the inverse y pass combines the vorticity (N < 1024)."""
-    return N < 1024
+def curl_in_y(N, cy=None):
+    """True where the inverse y pass combines the vorticity: the plan's
+    choice cy when given, else the default (N < 1024)."""
+    return bool(cy) if cy is not None else N < 1024
 
 
-def fields_per_launch(N):
-    x = 5.0 if curl_in_y(N) else 6.0
+def fields_per_launch(N, cy=None):
+    x = 5.0 if curl_in_y(N, cy) else 6.0
     return {"xinv_curl": 3.0 + x, "yinv6": x + 6.0, "zcross": 9.0, "yfwd3": 6.0, "xrhs_rk4": 48.0 / 4,
             "xstage": 48.0 / 4 + x}
 
 
-def fields_per_step(N):
-    f = fields_per_launch(N)
+def fields_per_step(N, cy=None):
+    f = fields_per_launch(N, cy)
     return 4 * (f["yinv6"] + f["zcross"] + f["yfwd3"] + f["xstage"])
 
 
@@ -64,7 +66,7 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(N, dtype, kernel):
+def measured_traffic(N, dtype, kernel, cy=None):
     """HBM bytes per launch of `kernel` (averaged over its RK stages) from the
     committed rocprofv3 counter summary, calibrated against a plain copy;
     None when no summary exists for this size or the kernel sources changed
@@ -78,11 +80,14 @@ def measured_traffic(N, dtype, kernel):
         return None
     real = "double" if dtype == "f64" else "float"
     name = {"xstage": "k_xstage", "xrhs_rk4": "k_xrhs", "xinv_curl": "k_xinv_curl", "zcross": "k_zcross",
-            "yinv6": "k_yinv_curl" if curl_in_y(N) else "k_yline", "yfwd3": "k_yline"}[kernel]
+            "yinv6": "k_yinv_curl" if curl_in_y(N, cy) else "k_yline", "yfwd3": "k_yline"}[kernel]
+
+    def args(k):   # template arguments after <real, N, width
+        return [a.strip() for a in k[k.index("<") + 1:k.rindex(">")].split(",")][3:]
     vals = [v["traffic_bytes_calibrated"] for k, v in rec["kernels"].items()
             if k.startswith(f"{name}<{real}, {N},")
-            and (kernel != "yinv6" or curl_in_y(N) or k.endswith(", 1, 6>"))
-            and (kernel != "yfwd3" or k.endswith(", -1, 3>"))]
+            and (kernel != "yinv6" or curl_in_y(N, cy) or args(k)[:2] == ["1", "6"])
+            and (kernel != "yfwd3" or args(k)[:2] == ["-1", "3"])]
     return sum(vals) / len(vals) if vals else None
 
 
@@ -108,7 +113,48 @@ def field_bytes(N, dtype):
     return N * N * (N // 2 + 1) * (16 if dtype == "f64" else 8)
 
 
-def run_gpu(N, dtype, steps, warmup, prof_steps):
+ERROR_STEP = 50   # the Taylor-Green 512^3 case is stated after 50 steps
+
+
+def tg_velocity_error(s, n):
+    """Relative L2 (Hermitian-weighted, equal to the physical-space relative
+    L2 by Parseval) of the context's velocity after n steps of the Re = 1600
+    Taylor-Green run against the oracle's stored run: its coefficients
+    u_hat / N^3 of every mode with |k_i| <= kmax, and zero outside that box
+    (where the oracle's field holds a fraction outside_rel_l2 of the norm,
+    stored with it).  None when the run is not stored at step n."""
+    import numpy as np
+    import torch
+    path = os.path.join(ROOT, "tests", "golden", "tg_re1600_n64.npz")
+    g = np.load(path)
+    if f"modes_{n}" not in g.files:
+        return None
+    N = s.N
+    ref = g[f"modes_{n}"]
+    kxy, kz = g["kxy"], g["kz"]
+    uh = s.get_spectral()
+    ix = torch.as_tensor(np.where(kxy < 0, kxy + N, kxy), device="cuda")
+    iz = torch.as_tensor(kz, device="cuda")
+    sel = (slice(None), ix[:, None, None], ix[None, :, None], iz[None, None, :])
+    box = uh[sel].cpu().numpy().astype(np.complex128) / float(N) ** 3
+    uh[sel] = 0
+    w = torch.full((N // 2 + 1,), 2.0, dtype=torch.float64, device="cuda")
+    w[0] = w[-1] = 1.0
+    out2 = float((uh.abs().double() ** 2 * w).sum().item()) / float(N) ** 6
+    del uh
+    torch.cuda.empty_cache()
+    wb = np.where(kz == 0, 1.0, 2.0)
+    num = np.sum(wb * np.abs(box - ref) ** 2) + out2
+    den = np.sum(wb * np.abs(ref) ** 2)
+    return {"velocity_rel_l2": float(np.sqrt(num / den)),
+            "velocity_rel_l2_outside_box": float(np.sqrt(out2 / den)),
+            "box_kmax": int(g["kmax"]), "oracle_outside_rel_l2": float(g[f"outside_rel_l2_{n}"])}
+
+
+def run_gpu(N, dtype, steps, warmup, prof_steps, error_step=ERROR_STEP):
+    """Time `steps` RK4 steps of the Taylor-Green field after `warmup`, then
+    continue (untimed) to step `error_step` and state the errors against the
+    CPU oracle there; mean kernel times from `prof_steps` profiled steps."""
     import torch
     import workloads
     from paper_1602_03638_amd import Solver
@@ -118,6 +164,7 @@ def run_gpu(N, dtype, steps, warmup, prof_steps):
     s = Solver(N, NU, DT, dtype=dtype)
     s.set_velocity(u0)
     del u0
+    cy = s.schedule()["xstage"]["curl_in_y"]
     s.step(warmup)
     s.synchronize()
     torch.cuda.synchronize()
@@ -126,16 +173,24 @@ def run_gpu(N, dtype, steps, warmup, prof_steps):
     s.synchronize()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+    done = warmup + steps
+    if done < error_step:
+        s.step(error_step - done)
+        done = error_step
     E, W = s.diagnostics()
-    err = oracle_tg_error(N, warmup + steps, E, W)
+    err = oracle_tg_error(N, done, E, W)
+    if err is not None:
+        v = tg_velocity_error(s, done)
+        if v is not None:
+            err.update(v)
     kern = s.profile_step(prof_steps) if prof_steps > 0 else {}
     s.close()
     torch.cuda.empty_cache()
     C = field_bytes(N, dtype)
-    out = {"ms_per_step": ms, "model_GBps": fields_per_step(N) * C / (ms * 1e-3) / 1e9,
-           "energy": E, "enstrophy": W, "error_vs_oracle": err, "kernels_ms": kern}
+    out = {"ms_per_step": ms, "model_GBps": fields_per_step(N, cy) * C / (ms * 1e-3) / 1e9,
+           "energy": E, "enstrophy": W, "error_vs_oracle": err, "kernels_ms": kern, "curl_in_y": cy}
     if kern:
-        achieved = {k: fields_per_launch(N)[k] * C / (v * 1e-3) / 1e9 for k, v in kern.items()}
+        achieved = {k: fields_per_launch(N, cy)[k] * C / (v * 1e-3) / 1e9 for k, v in kern.items()}
         out["kernels_GBps"] = achieved
     return out
 
@@ -147,9 +202,10 @@ ENS_NU, ENS_DT = 0.01, 0.005
 
 
 def run_ensemble(steps, warmup, per_sim_steps, autotune=True):
-    """Ensemble steps per second, batched (one captured graph per step whose
-    kernels each advance every member of one size) against per-simulation
-    launches of the same kernels."""
+    """Ensemble steps per second: batched kernels (each advances every member
+    of one size) replayed as one captured graph per step, all `steps` steps
+    captured into one graph launched once, and per-simulation launches of
+    the same kernels (the baseline)."""
     import torch
     from paper_1602_03638_amd import Ensemble
 
@@ -158,30 +214,32 @@ def run_ensemble(steps, warmup, per_sim_steps, autotune=True):
     for j in range(len(Ns)):
         ens.init_random(j, 1000 + j, k0=4.0, energy=0.5)
 
-    def timed(n, batched):
-        ens.step(warmup, batched=batched)
+    def timed(n, mode):
+        kw = {"batched": mode != "per_sim", "one_graph": mode == "one_graph"}
+        ens.step(n if mode == "one_graph" else warmup, **kw)   # one_graph: captures the n-step graph
         ens.synchronize()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ens.step(n, batched=batched)
+        ens.step(n, **kw)
         ens.synchronize()
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / n
 
-    ms_b = timed(steps, True)
-    ms_p = timed(per_sim_steps, False)
+    ms_b = timed(steps, "batched")
+    ms_o = timed(steps, "one_graph")
+    ms_p = timed(per_sim_steps, "per_sim")
     E, _ = ens.diagnostics()
     ens.close()
     traffic = sum(count * fields_per_step(N) * field_bytes(N, "f32") for N, count in ENSEMBLE)
+
+    def rec(n, ms):
+        return {"steps": n, "ms_per_step": round(ms, 4), "ens_steps_per_s": round(1e3 / ms, 1),
+                "sim_steps_per_s": round(len(Ns) * 1e3 / ms, 1), "model_GBps": round(traffic / (ms * 1e-3) / 1e9, 1)}
     return {"workload": "+".join(f"{count}x{N}^3" for N, count in ENSEMBLE) + " f32 random isotropic",
-            "members": len(Ns), "nu": ENS_NU, "dt": ENS_DT, "autotuned_tiles": autotune,
-            "batched": {"steps": steps, "ms_per_step": round(ms_b, 4), "ens_steps_per_s": round(1e3 / ms_b, 1),
-                        "sim_steps_per_s": round(len(Ns) * 1e3 / ms_b, 1),
-                        "model_GBps": round(traffic / (ms_b * 1e-3) / 1e9, 1)},
-            "per_sim": {"steps": per_sim_steps, "ms_per_step": round(ms_p, 4),
-                        "ens_steps_per_s": round(1e3 / ms_p, 1),
-                        "sim_steps_per_s": round(len(Ns) * 1e3 / ms_p, 1)},
-            "speedup": round(ms_p / ms_b, 2), "energy_mean": sum(E) / len(E)}
+            "members": len(Ns), "nu": ENS_NU, "dt": ENS_DT, "autotuned_plans": autotune,
+            "one_graph": rec(steps, ms_o), "batched": rec(steps, ms_b), "per_sim": rec(per_sim_steps, ms_p),
+            "speedup": round(ms_p / ms_o, 2), "speedup_per_step_replay": round(ms_p / ms_b, 2),
+            "energy_mean": sum(E) / len(E)}
 
 
 # Random isotropic field at 1024^3 (seed 1, k0 = 4, E = 0.5): FP32 path
@@ -353,24 +411,27 @@ def run_tg_long(N, dtype, steps, out_path, chunk=1000):
             "max_rel_budget_residual": max(res)}
 
 
-def cpu_baseline(N):
-    """Time the CPU oracle on a bounded sample of the workload: one inverse and
-    one forward 3D transform of one velocity component at N^3, scaled to one
-    RK4 step (4 stages x (6 inverse + 3 forward) transforms).  The
-    elementwise work of the RHS is excluded, so this is a lower bound on
-    the oracle's time per step."""
-    import numpy as np
-    import workloads
-    from oracle import spectral
-
-    u = workloads.taylor_green(N)[0]
-    t0 = time.perf_counter()
-    uh = spectral.dft3(u)
-    t_fwd = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    spectral.idft3(uh)
-    t_inv = time.perf_counter() - t0
-    ms = 4 * (6 * t_inv + 3 * t_fwd) * 1e3
+def host_info():
+    """The host's CPU model and core counts (from /proc/cpuinfo and the
+    scheduler affinity), and the threads the oracle's BLAS uses."""
+    model, cores = None, set()
+    try:
+        phys = core = None
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and model is None:
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                elif not k and phys is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+    except OSError:
+        pass
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     try:
         import threadpoolctl
@@ -378,16 +439,67 @@ def cpu_baseline(N):
         threads = max([i.get("num_threads", 1) for i in info] or [threads])
     except Exception:
         pass
-    del np
-    return {"value": ms, "unit": "ms/step", "cores": threads, "kind": "oracle",
-            "sample": f"one forward ({t_fwd:.2f} s) and one inverse ({t_inv:.2f} s) 3D DFT of one "
-                      f"component at {N}^3 on the host, scaled by 4 stages x (6 inverse + 3 forward); "
-                      "RHS elementwise work excluded"}
+    return {"cpu_model": model, "host_physical_cores": len(cores) or None, "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)), "blas_threads": threads}
+
+
+def cpu_baseline(N_metric, sizes=((128, 3), (256, 1))):
+    """Time the CPU oracle's full RK4 step (oracle.spectral.rk4_step: four
+    right-hand sides, each nine plain-DFT 3D transforms plus the elementwise
+    curl, cross product, mask, projection and viscous term) on the host, on
+    the Taylor-Green field of the benchmark: the median of the steps run at
+    each size.  The metric's size is reached from the largest size timed by
+    the growth factor measured between the two sizes (the DFT-matrix
+    transforms cost N^4)."""
+    import statistics
+
+    import workloads
+    from oracle import spectral
+
+    times = {}
+    for N, nsteps in sizes:
+        s = spectral.Solver(N, NU, DT).set_velocity(workloads.taylor_green(N))
+        t = []
+        for _ in range(nsteps):
+            t0 = time.perf_counter()
+            s.step(1)
+            t.append(time.perf_counter() - t0)
+        times[N] = statistics.median(t)
+        del s
+    (n0, _), (n1, _) = sizes[0], sizes[-1]
+    growth = times[n1] / times[n0]
+    per_doubling = growth ** (1.0 / max(1, (n1 // n0).bit_length() - 1))
+    steps_to_metric = max(0, (N_metric // n1).bit_length() - 1)
+    ms = times[n1] * per_doubling ** steps_to_metric * 1e3
+    h = host_info()
+    return {"value": ms, "unit": "ms/step", "cores": h["blas_threads"], "kind": "oracle_step",
+            "sample": f"full oracle RK4 steps of the Taylor-Green field: median of {sizes[0][1]} at {n0}^3 "
+                      f"({times[n0]:.2f} s), {sizes[-1][1]} at {n1}^3 ({times[n1]:.2f} s); {N_metric}^3 value = "
+                      f"the {n1}^3 step x {per_doubling:.1f} per doubling of N (measured {n0}->{n1})",
+            "measured_s_per_step": {str(k): v for k, v in times.items()}, "growth_per_doubling": per_doubling,
+            **h}
+
+
+def gpu_clocks():
+    """Current and enabled clock levels reported by rocm-smi (text lines), or
+    None when rocm-smi is not available."""
+    import shutil
+    import subprocess
+    exe = shutil.which("rocm-smi") or "/opt/rocm/bin/rocm-smi"
+    if not os.path.exists(exe):
+        return None
+    try:
+        r = subprocess.run([exe, "--showclocks"], capture_output=True, text=True, timeout=30)
+    except Exception:
+        return None
+    lines = [ln.strip() for ln in r.stdout.splitlines() if "clock level" in ln.lower() or "Mhz" in ln]
+    return lines[:12] or None
 
 
 def sweep(N, dtype, reps=2):
-    """Time every tile-shape variant of every pass (HIP events, mean of the
-    launches of `reps` steps) and the autotuner's choice."""
+    """Time every variant of every pass (HIP events, mean over the launches
+    of `reps` profiled steps) with the other passes at the default plan, and
+    the autotuner's choice; fused and unfused schedules."""
     import torch
     import workloads
     from paper_1602_03638_amd import Solver
@@ -397,25 +509,21 @@ def sweep(N, dtype, reps=2):
     out = {"N": N, "dtype": dtype, "passes": {}}
     for fuse in (True, False):
         s = Solver(N, NU, DT, dtype=dtype, fuse=fuse).set_velocity(u0)
-        base = s.plan()
-        out["default_plan"] = base
+        base = s.plan_ex()
+        var = s.plan_variants_ex()
+        out["default_schedule"] = s.schedule()
         mine = ("yinv6", "zcross", "yfwd3", "xstage") if fuse else ("xinv_curl", "xrhs_rk4")
-        for p, widths in s.plan_variants().items():
-            if p not in mine:
-                continue
-            res = {}
-            for w in widths:
-                plan = dict(base)
-                plan[p] = w
-                if p in ("yinv6", "yfwd3"):
-                    plan["yinv6"] = plan["yfwd3"] = w
-                s.set_plan(plan)
+        for p in mine:
+            res = []
+            for v, d in enumerate(var[p]):
+                s.set_plan_ex(s.plan_with(p, v, base))
                 s.profile_step(1)            # warm (rebuilds the fused work space)
-                res[w] = round(s.profile_step(reps)[p], 4)
+                res.append(dict(d, ms=round(s.profile_step(reps)[p], 4)))
             out["passes"][p] = res
-        s.set_plan(base)
+        s.set_plan_ex(base)
         key = "fused" if fuse else "unfused"
-        out[f"autotuned_plan_{key}"] = s.autotune()
+        s.autotune()
+        out[f"autotuned_{key}"] = s.schedule()
         s.profile_step(1)
         out[f"autotuned_ms_{key}"] = {k: round(v, 4) for k, v in s.profile_step(reps).items()}
         s.close()
@@ -498,24 +606,27 @@ def main(argv=None):
         f32 = run_gpu(a.N, "f32", a.steps, a.warmup, a.prof_steps)
         print(json.dumps({"fp32": f32, "N": a.N, "steps": a.steps}), flush=True)
         return 0
+    clocks_before = gpu_clocks()
     f64 = run_gpu(a.N, "f64", a.steps, a.warmup, a.prof_steps)
     f32 = None if a.no_fp32 else run_gpu(a.N, "f32", a.steps, a.warmup, a.prof_steps)
+    clocks_after = gpu_clocks()
 
     roof = None
     if f64["kernels_ms"]:
         dom = max(f64["kernels_ms"], key=f64["kernels_ms"].get)
         C = field_bytes(a.N, "f64")
         ach = f64["kernels_GBps"][dom]
-        tr = measured_traffic(a.N, "f64", dom)
+        tr = measured_traffic(a.N, "f64", dom, f64["curl_in_y"])
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
                 "traffic": None if tr is None else round(tr / 1e9, 3), "traffic_unit": "GB per launch",
-                "bytes_per_launch": fields_per_launch(a.N)[dom] * C,
+                "bytes_per_launch": fields_per_launch(a.N, f64["curl_in_y"])[dom] * C,
                 "mean_launch_ms": f64["kernels_ms"][dom]}
     ens = None if a.no_ensemble else run_ensemble(a.ens_steps, a.warmup, a.ens_per_sim_steps, not a.ens_default_tiles)
     iso = None if a.no_isotropic else run_isotropic(steps=a.iso_steps)
     fft = None if a.no_fft else run_fft()
     cpu = None if a.no_cpu_baseline else cpu_baseline(a.N)
+    line_clocks = {"before": clocks_before, "after": clocks_after}
     line = {
         "metric": METRIC, "value": round(f64["ms_per_step"], 4), "unit": "ms/step",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -530,6 +641,7 @@ def main(argv=None):
         "kernels_ms": f64["kernels_ms"],
         "roofline": roof,
         "cpu_baseline": cpu,
+        "gpu_clocks": line_clocks,
     }
     if f32 is not None:
         line["fp32"] = {"ms_per_step": round(f32["ms_per_step"], 4), "model_GBps": round(f32["model_GBps"], 1),

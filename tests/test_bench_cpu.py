@@ -32,6 +32,26 @@ def test_traffic_model_at_1024():
     assert bench.fields_per_step(1024) == 180
 
 
+def test_traffic_model_follows_the_plan():
+    """A plan with the vorticity formed in the x pass moves the six-field
+    figures at any N, and the five-field ones at 1024 when the y pass forms
+    it."""
+    assert bench.fields_per_step(512, cy=0) == 180
+    assert bench.fields_per_step(1024, cy=1) == 172
+    assert bench.fields_per_launch(128, cy=0)["yinv6"] == 12
+
+
+def test_cpu_baseline_times_full_oracle_steps():
+    """The CPU baseline times whole oracle RK4 steps and scales the larger
+    size by the measured growth per doubling of N."""
+    r = bench.cpu_baseline(32, sizes=((8, 1), (16, 1)))
+    assert r["kind"] == "oracle_step" and r["unit"] == "ms/step"
+    t8, t16 = r["measured_s_per_step"]["8"], r["measured_s_per_step"]["16"]
+    assert abs(r["growth_per_doubling"] - t16 / t8) < 1e-12
+    assert abs(r["value"] - t16 * (t16 / t8) * 1e3) < 1e-9 * r["value"]
+    assert r["cores"] >= 1 and r["nproc"] >= 1
+
+
 def test_rk4_state_traffic():
     """Regrouped RK4: the stages move 6, 12, 9 and 9 fields of state and read
     the 3 fields of N_hat each, 48C per step, 12C per stage on average."""
@@ -58,7 +78,7 @@ def test_measured_traffic_lookup(tmp_path, monkeypatch):
     sha = bench.kernel_source_hash()
     _summary(tmp_path, 512, sha, {
         "k_yinv_curl<double, 512, 8>": 11e9,
-        "k_yline<double, 512, 8, -1, 3>": 6e9,
+        "k_yline<double, 512, 8, -1, 3, 8>": 6e9,
         "k_zcross<double, 512, 4>": 9e9,
         "k_xstage<double, 512, 8, 0>": 15e9,
         "k_xstage<double, 512, 8, 1>": 21e9,
@@ -72,8 +92,8 @@ def test_measured_traffic_lookup(tmp_path, monkeypatch):
     assert bench.measured_traffic(512, "f32", "yinv6") is None
     # at 1024 the inverse y pass is the six-field k_yline<..., 1, 6>
     _summary(tmp_path, 1024, sha, {
-        "k_yline<double, 1024, 8, 1, 6>": 12e9,
-        "k_yline<double, 1024, 8, -1, 3>": 6e9,
+        "k_yline<double, 1024, 8, 1, 6, 16>": 12e9,
+        "k_yline<double, 1024, 8, -1, 3, 16>": 6e9,
     })
     assert bench.measured_traffic(1024, "f64", "yinv6") == 12e9
     assert bench.measured_traffic(1024, "f64", "yfwd3") == 6e9
