@@ -205,6 +205,27 @@ int dns_step(dns_t* ctx, int nsteps);
  * changed.  For verification of a single stage. */
 int dns_rhs(dns_t* ctx, void* rhs_dev);
 
+/* dns_rhs without a context, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the right-hand side of eq. NSfinal of the
+ * (3, N, N, N/2+1) spectrum uhat_dev, written to rhs_dev (same layout and
+ * dtype), for viscosity nu and the dealias rule `dealias`, enqueued on
+ * `stream` (a hipStream_t cast to void*, NULL = null stream); asynchronous.
+ * Same kernels and default plan as dns_rhs, hence the same bits.
+ *
+ * Allocates nothing: its work space (input and output in the internal
+ * layout and six work fields, 32.4 MB) is one array that the library holds
+ * on every GPU it runs on until the process ends, so N is limited to
+ * N <= 64 (DNS_E_INVAL beyond; the message is in dns_last_error(NULL)).
+ * Every call on a GPU uses that GPU's one array: calls that overlap in time
+ * on one GPU (different streams or threads) race and must be ordered by the
+ * caller.  Nothing in the array needs to start at zero (every value read is
+ * written earlier in the same call).  The first call on each device looks
+ * up the array's address and uploads the twiddle tables with a synchronous
+ * copy; make it before capturing a graph.  DNS_E_INVAL for invalid
+ * arguments, DNS_E_HIP if a launch fails. */
+int dns_rhs_noalloc(int N, int dtype, double nu, int dealias, const void* uhat_dev, void* rhs_dev, void* stream);
+
 /* E = mean over the mesh of |u|^2 / 2 (the Appendix's final energy) and
  * Omega = mean of |omega|^2 / 2, evaluated from the spectrum by Parseval
  * with FP64 accumulation in a fixed order.  Synchronous.  DNS_E_NONFINITE
@@ -315,7 +336,8 @@ int dns_get_plan_ex(const dns_t* ctx, int* variants, int max, int* count);
 int dns_set_plan_ex(dns_t* ctx, const int* variants, int n);
 
 /* dns_strerror: a static description of a status code.  dns_last_error:
- * the message of the context's last failure ("" if none).
+ * the message of the context's last failure ("" if none); with NULL, the
+ * message of the calling thread's last failed context-free call.
  *
  * Testing error paths: with the environment variable DNS_FAULT_INJECT set to
  * "launch" when a context is created, every launch check of that context

@@ -81,6 +81,7 @@ def load_library(path=LIB_PATH):
         "dns_get_velocity": (I, [P, P]),
         "dns_step": (I, [P, I]),
         "dns_rhs": (I, [P, P]),
+        "dns_rhs_noalloc": (I, [I, I, D, I, P, P, P]),
         "dns_energy": (I, [P, ctypes.POINTER(D)]),
         "dns_enstrophy": (I, [P, ctypes.POINTER(D)]),
         "dns_diagnostics": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D)]),
@@ -185,6 +186,33 @@ def plan_cache_load(path):
     if n < 0:
         _check(n, None, "dns_plan_cache_load")
     return n
+
+
+def rhs_noalloc(uh, nu, dealias="text", out=None, stream=None):
+    """dns_rhs_noalloc: right-hand side of the (3, N, N, N/2+1) CUDA spectrum
+    uh (complex128 -> FP64, complex64 -> FP32, N <= 64) with no context and
+    no device allocation by the library; `out` (same shape and dtype) is
+    allocated by torch when not given.  Enqueued on torch's current stream
+    (or `stream`)."""
+    import torch
+    N = uh.shape[1]
+    if (not uh.is_cuda or uh.dtype not in (torch.complex128, torch.complex64) or tuple(uh.shape) != (3, N, N, N // 2 + 1)
+            or not uh.is_contiguous()):
+        raise ValueError("expected a contiguous CUDA complex tensor of shape (3, N, N, N/2+1)")
+    out = torch.empty_like(uh) if out is None else out
+    if out.dtype != uh.dtype or out.shape != uh.shape or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError("out must match uh")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    dt = DNS_FP64 if uh.dtype == torch.complex128 else DNS_FP32
+    code = {"text": DNS_DEALIAS_TEXT, "appendix": DNS_DEALIAS_APPENDIX}[dealias]
+    lib = load_library()
+    st = lib.dns_rhs_noalloc(int(N), dt, float(nu), code, ctypes.c_void_p(uh.data_ptr()),
+                             ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream.cuda_stream))
+    if st != DNS_OK:
+        raise DnsError(st, "dns_rhs_noalloc: " + lib.dns_strerror(st).decode() + ": " +
+                       lib.dns_last_error(None).decode())
+    return out
 
 
 class Solver:

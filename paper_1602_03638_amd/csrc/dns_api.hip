@@ -812,9 +812,123 @@ int history_m(dns_t* c, int m, double* E, double* W, int max, int* count) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Context-free right-hand side (dns_rhs_noalloc): every device buffer it
+// needs beyond the caller's input and output lives in one file-scope array,
+// so a call allocates nothing.  Layout of the array (all offsets 256-byte
+// aligned): U0 (3 fields, the input in the internal layout), U1 (3 fields,
+// the right-hand side), W (6 work fields), each field of the largest grid
+// served (N = 64, FP64); then one twiddle-table slot per (precision, N).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int NA_MAX_N = 64;
+constexpr size_t NA_FIELD = (dns::Lay<double, NA_MAX_N>::FS * sizeof(double2) + 255) / 256 * 256;
+constexpr size_t NA_TW_SLOT = 4096;   // bytes per twiddle table (64-point FP64: 896)
+constexpr int NA_SIZES = 4;           // N = 8, 16, 32, 64
+constexpr size_t NA_TW = 12 * NA_FIELD;
+constexpr size_t NA_BYTES = NA_TW + 2 * NA_SIZES * NA_TW_SLOT;
+static_assert((size_t)dns::tw_size(NA_MAX_N) * sizeof(double2) <= NA_TW_SLOT, "twiddle slot");
+constexpr int NA_MAX_DEV = 64;
+
+thread_local std::string g_free_err;   // message of the last failed context-free call
+
+int free_fail(int code, const std::string& msg) {
+    g_free_err = msg;
+    return code;
+}
+
+size_t na_tw_offset(int dtype, int N) { return NA_TW + (size_t)(dtype * NA_SIZES + (dns::ilog2(N) - 3)) * NA_TW_SLOT; }
+}  // namespace
+
+// The scratch array: one copy per GPU, held until the process ends.  Host
+// code never uses this name as an address (on the host it is only a
+// stand-in); it uses the device address na_base() obtained for the current
+// device.
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+std::mutex g_na_mu;
+char* g_na_base[NA_MAX_DEV] = {};
+
+// Device address of the scratch array on the current device.  The first
+// call on a device (under g_na_mu, with that device current) looks the
+// address up and uploads the twiddle tables of every served (precision, N),
+// long-double accurate as for a context, with a synchronous copy.
+int na_base(char** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return free_fail(DNS_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= NA_MAX_DEV) return free_fail(DNS_E_UNSUPPORTED, "device ordinal beyond 63");
+    std::lock_guard<std::mutex> lock(g_na_mu);
+    if (g_na_base[dev] == nullptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return free_fail(DNS_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        double tw[2 * NA_TW_SLOT / sizeof(double2) * 2];
+        float twf[2 * NA_TW_SLOT / sizeof(double2) * 2];
+        for (int n = 8; n <= NA_MAX_N; n *= 2) {
+            const int cnt = dns::tw_size(n);
+            if (cnt == 0) continue;
+            dns::make_twiddles(n, tw);
+            for (int i = 0; i < 2 * cnt; ++i) twf[i] = (float)tw[i];
+            char* base = (char*)p;
+            if ((e = hipMemcpy(base + na_tw_offset(DNS_FP64, n), tw, (size_t)cnt * sizeof(double2),
+                               hipMemcpyHostToDevice)) != hipSuccess ||
+                (e = hipMemcpy(base + na_tw_offset(DNS_FP32, n), twf, (size_t)cnt * sizeof(float2),
+                               hipMemcpyHostToDevice)) != hipSuccess)
+                return free_fail(DNS_E_HIP, std::string("twiddle upload: ") + hipGetErrorString(e));
+        }
+        g_na_base[dev] = (char*)p;
+    }
+    *out = g_na_base[dev];
+    return DNS_OK;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C ABI: single simulation
 // ---------------------------------------------------------------------------
 extern "C" {
+
+int dns_rhs_noalloc(int N, int dtype, double nu, int dealias, const void* uhat_dev, void* rhs_dev, void* stream) {
+    if (!uhat_dev || !rhs_dev) return free_fail(DNS_E_INVAL, "null argument");
+    if (!valid_n(N) || (dtype != DNS_FP64 && dtype != DNS_FP32) || !(nu >= 0.0) || !std::isfinite(nu) ||
+        (dealias != DNS_DEALIAS_TEXT && dealias != DNS_DEALIAS_APPENDIX))
+        return free_fail(DNS_E_INVAL, "bad argument");
+    if (N > NA_MAX_N) return free_fail(DNS_E_INVAL, "dns_rhs_noalloc serves N <= 64 (its fixed scratch size)");
+    char* base = nullptr;
+    int r = na_base(&base);
+    if (r != DNS_OK) return r;
+    const dns::Ops* o = dtype == DNS_FP64 ? dns::ops_f64(N) : dns::ops_f32(N);
+    const size_t fb = o->fs * 2 * o->real_size;   // the kernels address the fields at this stride
+    char* U0 = base;
+    char* U1 = base + 3 * NA_FIELD;
+    char* W = base + 6 * NA_FIELD;
+    if (3 * fb > 3 * NA_FIELD) return free_fail(DNS_E_UNSUPPORTED, "field larger than its scratch slot");
+    const void* tw = base + na_tw_offset(dtype, N);
+    hipStream_t s = (hipStream_t)stream;
+    const dns::Batch b{1, 0, 0};
+    dns::StageArgs a;
+    a.nu = nu;
+    a.ca = 0.0;
+    a.cb = 0.0;
+    a.stage = -1;                     // right-hand side only: U1 = R
+    a.mask_lim = dealias == DNS_DEALIAS_TEXT ? N : N + 2;
+    a.diag = nullptr;
+    // the unfused stage of dns_rhs, default variants: inverse x (+curl),
+    // inverse y, z pass, forward y, forward x + RHS
+    o->layout(uhat_dev, U0, true, s);
+    o->xinv[o->def[dns::P_XINV]](U0, W, tw, b, s);
+    o->yinv6[o->def[dns::P_YINV6]](W, tw, b, s);
+    o->zcross[o->def[dns::P_ZCROSS]](W, tw, b, s);
+    o->yfwd3[o->def[dns::P_YFWD3]](W, tw, b, s);
+    o->xrhs[o->def[dns::P_XRHS]](W, U0, U1, U1, tw, a, b, s);
+    o->layout(U1, rhs_dev, false, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return free_fail(DNS_E_HIP, std::string("dns_rhs_noalloc launch: ") + hipGetErrorString(e));
+    return DNS_OK;
+}
+
 
 void dns_default_opts(dns_opts* o) {
     if (!o) return;
@@ -1287,7 +1401,7 @@ const char* dns_strerror(int s) {
     }
 }
 
-const char* dns_last_error(const dns_t* c) { return c ? c->err.c_str() : ""; }
+const char* dns_last_error(const dns_t* c) { return c ? c->err.c_str() : g_free_err.c_str(); }
 
 }  // extern "C"
 
