@@ -531,22 +531,197 @@ def sweep(N, dtype, reps=2):
     return 0
 
 
-def calibrate_copy(gib, reps=5):
-    """Plain device-to-device copy of a known size: its HBM counters and
-    bandwidth calibrate the per-kernel counter readings."""
+def calibrate_copy(gib, row_bytes=0, pitch=0, reps=5):
+    """A copy of known size for calibrating the per-kernel HBM byte counters:
+    row_bytes = 0 is a plain device copy (torch), else dns_copy_rows with rows
+    of row_bytes bytes (one request each) every `pitch` bytes (default: the
+    row length, i.e. contiguous).  Prints the bytes read and written."""
+    import ctypes
+
     import torch
+    from paper_1602_03638_amd import load_library
     n = int(gib * (1 << 30)) // 8
     src = torch.ones(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
+    if row_bytes <= 0:
+        def run():
+            dst.copy_(src)
+        moved = n * 8
+        desc = "plain device copy"
+    else:
+        pitch = pitch or row_bytes
+        nrows = (n * 8) // pitch
+        lib = load_library()
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+        def run():
+            st = lib.dns_copy_rows(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nrows,
+                                   int(row_bytes), int(pitch), stream)
+            if st != 0:
+                raise RuntimeError(f"dns_copy_rows: status {st}")
+        moved = nrows * row_bytes
+        desc = f"dns_copy_rows: {nrows} rows of {row_bytes} B, pitch {pitch} B"
+    run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        dst.copy_(src)
+        run()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / reps
-    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "ms": ms,
-                      "GBps_read_plus_write": 2 * n * 8 / (ms * 1e-3) / 1e9}), flush=True)
+    print(json.dumps({"copy": desc, "copy_bytes_read": moved, "copy_bytes_written": moved, "launches": reps + 1,
+                      "ms": ms, "GBps_read_plus_write": 2 * moved / (ms * 1e-3) / 1e9}), flush=True)
+    return 0
+
+
+# ---------------------------------------------------------------------------
+# Summaries of rocprofv3 output (kernel trace statistics and HBM counters),
+# written under profiles/ with the command that made them.
+# ---------------------------------------------------------------------------
+def kernel_short_name(name):
+    """'void dns::k_x<double, 512, 8>(...)' -> 'k_x<double, 512, 8>'."""
+    name = name.strip().strip('"')
+    if name.startswith("void "):
+        name = name[5:]
+    depth, cut = 0, len(name)
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            cut = i
+            break
+    return name[:cut].replace("dns::", "").strip()
+
+
+def algorithmic_bytes(short):
+    """Algorithmic HBM bytes (read + write) of one launch of a stage kernel,
+    from its template arguments (see the traffic model at the top of this
+    file); None for other kernels."""
+    import re
+    m = re.match(r"(k_\w+)<(.*)>$", short)
+    if not m:
+        return None
+    kind, args = m.group(1), [a.strip() for a in m.group(2).split(",")]
+    if kind == "k_yline_mfma":
+        N, DIR, NF = int(args[0]), int(args[1]), int(args[2])
+        return 2 * NF * field_bytes(N, "f32")
+    if len(args) < 2 or args[0] not in ("double", "float"):
+        return None
+    dt = "f64" if args[0] == "double" else "f32"
+    N = int(args[1])
+    C = field_bytes(N, dt)
+    state = {0: 6, 1: 12, 2: 9, 3: 9, 4: 6, -1: 6}
+    if kind == "k_xinv_curl":
+        return (3 + (5 if args[3] == "true" else 6)) * C
+    if kind == "k_yinv_curl":
+        return 11 * C
+    if kind == "k_yline":
+        return 2 * int(args[4]) * C
+    if kind == "k_zcross":
+        return 9 * C
+    if kind == "k_xrhs":
+        return (3 + state[int(args[3])]) * C
+    if kind == "k_xstage":
+        return (3 + state[int(args[3])] + (5 if args[4] == "true" else 6)) * C
+    return None
+
+
+def _csv_rows(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _find(d, suffix):
+    import glob
+    hits = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return hits
+
+
+def summarize_trace(stats_dir, out_md, command, title):
+    """Kernel trace statistics (rocprofv3 --kernel-trace --stats) as a table
+    of calls and durations per kernel instance, with the algorithmic bytes
+    and bandwidth at the mean duration for the stage kernels."""
+    rows = []
+    for path in _find(stats_dir, "kernel_stats.csv"):
+        rows += _csv_rows(path)
+    lines = [f"# {title}", "", "Command (repository root, on the MI355X machine):", "", "```", command, "```", "",
+             "| kernel | calls | avg us | min us | max us | alg. bytes / launch (GB) | GB/s at avg |",
+             "|---|---|---|---|---|---|---|"]
+    recs = []
+    for r in rows:
+        name = kernel_short_name(r["Name"])
+        avg = float(r["AverageNs"]) / 1e3
+        alg = algorithmic_bytes(name)
+        recs.append((float(r["TotalDurationNs"]), name, int(r["Calls"]), avg, float(r["MinNs"]) / 1e3,
+                     float(r["MaxNs"]) / 1e3, alg))
+    for _, name, calls, avg, mn, mx, alg in sorted(recs, reverse=True):
+        a = f"{alg / 1e9:.3f}" if alg else ""
+        bw = f"{alg / (avg * 1e-6) / 1e9:.0f}" if alg else ""
+        lines.append(f"| `{name}` | {calls} | {avg:.1f} | {mn:.1f} | {mx:.1f} | {a} | {bw} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return 0
+
+
+def _counter_means(d, counter):
+    """Mean value of `counter` per kernel instance over its dispatches."""
+    acc = {}
+    for path in _find(d, "counter_collection.csv"):
+        for r in _csv_rows(path):
+            if r.get("Counter_Name") != counter:
+                continue
+            name = kernel_short_name(r["Kernel_Name"])
+            v = float(r["Counter_Value"])
+            s, n = acc.get(name, (0.0, 0))
+            acc[name] = (s + v, n + 1)
+    return {k: (s / n, n) for k, (s, n) in acc.items()}
+
+
+def summarize_counters(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cal_bytes, N, out_json, out_md,
+                       commands, title):
+    """HBM traffic per dispatch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs
+    (KiB per dispatch), each scaled by the factor that maps the same counter
+    of a copy of known size (cal_bytes read and written, dns_copy_rows or a
+    device copy) to its bytes.  Keyed by the hash of the kernel sources
+    (comments removed) at the time of summarising."""
+    fetch, write = _counter_means(fetch_dir, "FETCH_SIZE"), _counter_means(write_dir, "WRITE_SIZE")
+    cf, cw = _counter_means(cal_fetch_dir, "FETCH_SIZE"), _counter_means(cal_write_dir, "WRITE_SIZE")
+    copy_f = max(cf.items(), key=lambda kv: kv[1][0])
+    copy_w = max(cw.items(), key=lambda kv: kv[1][0])
+    ff = cal_bytes / (copy_f[1][0] * 1024.0)
+    fw = cal_bytes / (copy_w[1][0] * 1024.0)
+    kernels = {}
+    for name in sorted(set(fetch) | set(write)):
+        fk = fetch.get(name, (0.0, 0))[0]
+        wk = write.get(name, (0.0, 0))[0]
+        kernels[name] = {"fetch_kib_raw": fk, "write_kib_raw": wk, "fetch_factor": ff, "write_factor": fw,
+                         "traffic_bytes_calibrated": fk * 1024.0 * ff + wk * 1024.0 * fw,
+                         "dispatches": max(fetch.get(name, (0, 0))[1], write.get(name, (0, 0))[1]),
+                         "alg_bytes": algorithmic_bytes(name)}
+    rec = {"source_sha256": kernel_source_hash(), "N": N, "calibration": {
+        "kernel_fetch": copy_f[0], "kernel_write": copy_w[0], "bytes_each_way": cal_bytes,
+        "fetch_factor": ff, "write_factor": fw}, "commands": commands, "kernels": kernels}
+    with open(out_json, "w") as f:
+        json.dump(rec, f, indent=1)
+    lines = [f"# {title}", "", "Commands (repository root, on the MI355X machine), one counter per run:", "", "```"]
+    lines += commands + ["```", "",
+                         f"Calibration: `{copy_f[0]}` moving {cal_bytes} bytes each way reads FETCH_SIZE "
+                         f"{copy_f[1][0]:.0f} KiB (factor {ff:.3f}) and WRITE_SIZE {copy_w[1][0]:.0f} KiB "
+                         f"(factor {fw:.3f}).", "",
+                         "| kernel | dispatches | FETCH_SIZE KiB (raw, mean) | WRITE_SIZE KiB (mean) | "
+                         "traffic GB (calibrated) | alg. GB | traffic / alg. |", "|---|---|---|---|---|---|---|"]
+    for name, v in sorted(kernels.items(), key=lambda kv: -kv[1]["traffic_bytes_calibrated"]):
+        alg = v["alg_bytes"]
+        ratio = f"{v['traffic_bytes_calibrated'] / alg:.3f}" if alg else ""
+        a_gb = f"{alg / 1e9:.3f}" if alg else ""
+        lines.append(f"| `{name}` | {v['dispatches']} | {v['fetch_kib_raw']:.0f} | {v['write_kib_raw']:.0f} | "
+                     f"{v['traffic_bytes_calibrated'] / 1e9:.3f} | {a_gb} | {ratio} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
     return 0
 
 
@@ -575,10 +750,27 @@ def main(argv=None):
     ap.add_argument("--ens-default-tiles", action="store_true", help="ensemble without the tile autotuner")
     ap.add_argument("--sweep", action="store_true", help="only time every kernel variant at --N")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
-                    help="only time a plain device copy of this many GiB (counter calibration)")
+                    help="only time a copy of this many GiB (counter calibration)")
+    ap.add_argument("--copy-row-bytes", type=int, default=0,
+                    help="with --calibrate-copy: rows of this many bytes (0 = plain device copy)")
+    ap.add_argument("--copy-pitch", type=int, default=0, help="with --copy-row-bytes: bytes from row to row")
+    ap.add_argument("--summarize-trace", nargs=4, metavar=("STATS_DIR", "OUT_MD", "COMMAND", "TITLE"),
+                    help="write a kernel-trace summary from rocprofv3 --stats output")
+    ap.add_argument("--summarize-counters", nargs=10,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR", "CAL_BYTES", "N", "OUT_JSON",
+                             "OUT_MD", "COMMANDS_FILE", "TITLE"),
+                    help="write an HBM-traffic summary from rocprofv3 FETCH_SIZE / WRITE_SIZE runs")
     a = ap.parse_args(argv)
+    if a.summarize_trace:
+        d, out, cmd, title = a.summarize_trace
+        return summarize_trace(d, out, cmd, title)
+    if a.summarize_counters:
+        fd, wd, cfd, cwd, cb, n, oj, om, cmds, title = a.summarize_counters
+        with open(cmds) as f:
+            commands = [ln.rstrip() for ln in f if ln.strip()]
+        return summarize_counters(fd, wd, cfd, cwd, int(cb), int(n), oj, om, commands, title)
     if a.calibrate_copy > 0:
-        return calibrate_copy(a.calibrate_copy)
+        return calibrate_copy(a.calibrate_copy, a.copy_row_bytes, a.copy_pitch)
     if a.sweep:
         for dt in ("f64", "f32"):
             sweep(a.N, dt)

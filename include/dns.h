@@ -335,6 +335,16 @@ int dns_plan_variants_ex(const dns_t* ctx, int pass, dns_variant* out, int max, 
 int dns_get_plan_ex(const dns_t* ctx, int* variants, int max, int* count);
 int dns_set_plan_ex(dns_t* ctx, const int* variants, int n);
 
+/* Measurement helper (not part of the method): copy nrows rows of
+ * row_bytes bytes (a multiple of 16) from src to dst, row r at byte offset
+ * r * pitch in both device buffers, each row read and written as one
+ * row_bytes request (16 bytes per thread), enqueued on `stream`.  A copy of
+ * known bytes with the row length of a pass's tiles calibrates the
+ * hardware's HBM byte counters for that request size.  DNS_E_INVAL for a
+ * row length that is not a positive multiple of 16 or a pitch shorter than
+ * the row. */
+int dns_copy_rows(const void* src, void* dst, size_t nrows, int row_bytes, size_t pitch, void* stream);
+
 /* dns_strerror: a static description of a status code.  dns_last_error:
  * the message of the context's last failure ("" if none); with NULL, the
  * message of the calling thread's last failed context-free call.

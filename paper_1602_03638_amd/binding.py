@@ -99,6 +99,7 @@ def load_library(path=LIB_PATH):
         "dns_set_plan": (I, [P, ctypes.POINTER(I), I]),
         "dns_plan_variants": (I, [P, I, ctypes.POINTER(I), I, ctypes.POINTER(I)]),
         "dns_plan_cache_entries": (I, []),
+        "dns_copy_rows": (I, [P, P, S, I, S, P]),
         "dns_plan_cache_save": (I, [ctypes.c_char_p]),
         "dns_plan_cache_load": (I, [ctypes.c_char_p]),
         "dns_set_schedule": (I, [P, I, I, I]),

@@ -94,6 +94,18 @@ void launch_diag_final(const double* part, int nparts, double inv_norm, double* 
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, part, nparts, inv_norm, out, hist, count, cap);
 }
 
+// Copy of nrows rows of row_bytes bytes (a multiple of 16), row r at byte
+// offset r * pitch in both buffers; one 16-byte vector per thread, so the
+// row_bytes / 16 threads of a row issue one row_bytes request.
+__global__ __launch_bounds__(256) void k_copy_rows(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                   size_t nrows, unsigned row_vecs, size_t pitch_vecs) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t r = i / row_vecs;
+    if (r >= nrows) return;
+    const size_t at = r * pitch_vecs + (i - r * row_vecs);
+    dst[at] = src[at];
+}
+
 }  // namespace dns
 
 // ---------------------------------------------------------------------------
@@ -1253,6 +1265,19 @@ int dns_autotune(dns_t* c, int reps) {
     c->w_ready = false;
     store_plan(c);
     return leave(c);
+}
+
+int dns_copy_rows(const void* src, void* dst, size_t nrows, int row_bytes, size_t pitch, void* stream) {
+    if (!src || !dst || row_bytes <= 0 || row_bytes % 16 != 0 || pitch < (size_t)row_bytes || pitch % 16 != 0)
+        return DNS_E_INVAL;
+    if (nrows == 0) return DNS_OK;
+    const unsigned vecs = (unsigned)(row_bytes / 16);
+    const size_t threads = nrows * vecs;
+    const size_t blocks = (threads + 255) / 256;
+    if (blocks > 0x7fffffffu) return DNS_E_INVAL;
+    hipLaunchKernelGGL(dns::k_copy_rows, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                       (const uint4*)src, (uint4*)dst, nrows, vecs, pitch / 16);
+    return hipGetLastError() == hipSuccess ? DNS_OK : DNS_E_HIP;
 }
 
 int dns_plan_cache_entries(void) {

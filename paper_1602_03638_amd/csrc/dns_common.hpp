@@ -188,7 +188,7 @@ template <int GRP> __device__ __forceinline__ int x_tile(int b, int main_tiles) 
 }
 // Tiles of width T (columns of type R) sharing one 128-byte line.
 template <typename R, int T> constexpr int line_group() {
-    return T * 2 * (int)sizeof(R) >= 128 ? 1 : 128 / (T * 2 * (int)sizeof(R));
+    return (T <= 0 || T * 2 * (int)sizeof(R) >= 128) ? 1 : 128 / (T * 2 * (int)sizeof(R));
 }
 
 // Workgroups of the standalone diagnostic reduction (fixed, so the summation

@@ -37,7 +37,7 @@ template <typename R, int N> struct Impl {
     // their 1024-thread shapes (128 registers per thread) only spill.
     template <int T> static constexpr bool xr_ok() {
         return x_ok<T>() && (sizeof(R) == 4 || GX * T <= 512) &&
-               (size_t)T * N * CB + 2 * 8 * (size_t)GX * T <= LDS_LIMIT;
+               (size_t)T * N * CB + 2 * 8 * (size_t)GX * T + (size_t)tw_size(N) * CB <= LDS_LIMIT;
     }
     // XCD-grouped tile order (x_tile): where an x tile's row segment is 32
     // or 64 bytes, from 256^3 up, with both tile counts multiples of 8 times
@@ -45,6 +45,13 @@ template <typename R, int N> struct Impl {
     template <int T> static constexpr bool pair_ok() {
         constexpr int grp = line_group<R, T>();
         return N >= 256 && (T * CB == 64 || T * CB == 32) && (XCOLS / T) % (8 * grp) == 0 &&
+               (N / T) % (8 * grp) == 0;
+    }
+    // the same for the y passes (128-byte y tiles hold one workgroup per CU
+    // at 512 and 1024: narrower grouped tiles fit two or three)
+    template <int T> static constexpr bool ypair_ok() {
+        constexpr int grp = line_group<R, T>();
+        return N >= 256 && (T * CB == 64 || T * CB == 32) && (N * ((N / 2) / T)) % (8 * grp) == 0 &&
                (N / T) % (8 * grp) == 0;
     }
     // y shapes with YE elements per thread; CURL: the vorticity-forming
@@ -95,10 +102,10 @@ template <typename R, int N> struct Impl {
         hipLaunchKernelGGL((k_xinv_curl<R, N, T, CY, PAIR>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0, s,
                            (const C*)U, (C*)W, (const C*)tw, b.sst, b.wst);
     }
-    template <int T, int DIR, int NF, int YE>
+    template <int T, int DIR, int NF, int YE, bool PAIR = false>
     static void ypass(void* W, const void* tw, const Batch& b, hipStream_t s) {
-        hipLaunchKernelGGL((k_yline<R, N, T, DIR, NF, YE>), dim3(y_tiles<R, N, T>(), b.members), dim3((N / YE) * T),
-                           0, s, (C*)W, (const C*)tw, b.wst);
+        hipLaunchKernelGGL((k_yline<R, N, T, DIR, NF, YE, PAIR>), dim3(y_tiles<R, N, T>(), b.members),
+                           dim3((N / YE) * T), 0, s, (C*)W, (const C*)tw, b.wst);
     }
     template <int DIR, int NF, bool CURL>
     static void ymfma(void* W, const void* tw, const void* roots, const void* tw2, const Batch& b, hipStream_t s) {
@@ -109,20 +116,27 @@ template <typename R, int N> struct Impl {
     }
     // inverse y pass of a stage with the vorticity combinations formed from
     // the x pass's five outputs
-    template <int T> static void yinv_curl(void* W, const void* tw, const Batch& b, hipStream_t s) {
-        hipLaunchKernelGGL((k_yinv_curl<R, N, T>), dim3(y_tiles<R, N, T>(), b.members), dim3((N / 8) * T), 0, s,
-                           (C*)W, (const C*)tw, b.wst);
+    template <int T, bool PAIR = false>
+    static void yinv_curl(void* W, const void* tw, const Batch& b, hipStream_t s) {
+        hipLaunchKernelGGL((k_yinv_curl<R, N, T, PAIR>), dim3(y_tiles<R, N, T>(), b.members), dim3((N / 8) * T), 0,
+                           s, (C*)W, (const C*)tw, b.wst);
     }
     template <int L> static void zcross(void* W, const void* tw, const Batch& b, hipStream_t s) {
         const R scale = (R)std::ldexp(1.0, -6 * ilog2(N));
         hipLaunchKernelGGL((k_zcross<R, N, L>), dim3((N * N) / L, b.members), dim3(G * L), 0, s, (C*)W,
                            (const C*)tw, scale, b.wst);
     }
+    // stages 3 and 4 (last of a step) have an instance with the fused
+    // diagnostics, launched when a.diag is set
     template <int T, bool PAIR, int ST>
     static void xrhs_st(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
                         const Batch& b, hipStream_t s) {
-        hipLaunchKernelGGL((k_xrhs<R, N, T, ST, PAIR>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0, s,
-                           (const C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a, b.sst, b.wst);
+        if (ST >= 3 && a.diag != nullptr)
+            hipLaunchKernelGGL((k_xrhs<R, N, T, ST, PAIR, ST >= 3>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0,
+                               s, (const C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a, b.sst, b.wst);
+        else
+            hipLaunchKernelGGL((k_xrhs<R, N, T, ST, PAIR, false>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0,
+                               s, (const C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a, b.sst, b.wst);
     }
     template <int T, bool PAIR>
     static void xrhs(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
@@ -140,8 +154,12 @@ template <typename R, int N> struct Impl {
     template <int T, bool CY, bool PAIR, int ST>
     static void xstage_st(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
                           const Batch& b, hipStream_t s) {
-        hipLaunchKernelGGL((k_xstage<R, N, T, ST, CY, PAIR>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0, s,
-                           (C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a, b.sst, b.wst);
+        if (ST >= 3 && a.diag != nullptr)
+            hipLaunchKernelGGL((k_xstage<R, N, T, ST, CY, PAIR, ST >= 3>), dim3(x_groups<T>(), b.members),
+                               dim3(GX * T), 0, s, (C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a, b.sst, b.wst);
+        else
+            hipLaunchKernelGGL((k_xstage<R, N, T, ST, CY, PAIR, false>), dim3(x_groups<T>(), b.members),
+                               dim3(GX * T), 0, s, (C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a, b.sst, b.wst);
     }
     template <int T, bool CY, bool PAIR>
     static void xstage(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
@@ -240,23 +258,26 @@ template <typename R, int N> struct Impl {
         }
     }
     // inverse y pass forming the vorticity (curl in y, 8 per thread)
-    template <int T> static void add_ycurl(Ops& o) {
+    template <int T, bool PAIR = false> static void add_ycurl(Ops& o) {
+        if constexpr (PAIR && !ypair_ok<T>()) return;
         if constexpr (y_ok<T, 8, true>()) {
-            int& n = push(o, P_YINV6, Variant{T, 0, 8, 1});
-            o.yinv6[n++] = &yinv_curl<T>;
+            int& n = push(o, P_YINV6, Variant{T, PAIR, 8, 1});
+            o.yinv6[n++] = &yinv_curl<T, PAIR>;
         }
     }
     // inverse y pass of the six fields the x pass wrote (curl in x)
-    template <int T, int YE> static void add_yinv(Ops& o) {
+    template <int T, int YE, bool PAIR = false> static void add_yinv(Ops& o) {
+        if constexpr (PAIR && !ypair_ok<T>()) return;
         if constexpr (T > 0 && y_ok<T, YE, false>()) {
-            int& n = push(o, P_YINV6, Variant{T, 0, YE, 0});
-            o.yinv6[n++] = &ypass<T, +1, 6, YE>;
+            int& n = push(o, P_YINV6, Variant{T, PAIR, YE, 0});
+            o.yinv6[n++] = &ypass<T, +1, 6, YE, PAIR>;
         }
     }
-    template <int T, int YE> static void add_yfwd(Ops& o) {
+    template <int T, int YE, bool PAIR = false> static void add_yfwd(Ops& o) {
+        if constexpr (PAIR && !ypair_ok<T>()) return;
         if constexpr (T > 0 && y_ok<T, YE, false>()) {
-            int& n = push(o, P_YFWD3, Variant{T, 0, YE, -1});
-            o.yfwd3[n++] = &ypass<T, -1, 3, YE>;
+            int& n = push(o, P_YFWD3, Variant{T, PAIR, YE, -1});
+            o.yfwd3[n++] = &ypass<T, -1, 3, YE, PAIR>;
         }
     }
     template <int L> static void add_z(Ops& o) {
@@ -300,10 +321,12 @@ template <typename R, int N> struct Impl {
             add_x<4, true, true>(o); add_x<8, true, true>(o);
             add_x<XD, false, false>(o);
             add_ycurl<4>(o); add_ycurl<8>(o); add_ycurl<16>(o); add_ycurl<32>(o);
+            add_ycurl<4, true>(o); add_ycurl<8, true>(o);
             add_yinv<y_default_width<8>(), 8>(o);
             add_yinv<y_default_width<16>(), 16>(o);
             add_yinv<y_default_width<32>(), 32>(o);
             add_yfwd<4, 8>(o); add_yfwd<8, 8>(o); add_yfwd<16, 8>(o); add_yfwd<32, 8>(o);
+            add_yfwd<4, 8, true>(o); add_yfwd<8, 8, true>(o);
             add_yfwd<y_default_width<16>(), 16>(o);
             add_yfwd<y_default_width<32>(), 32>(o);
         } else {
@@ -312,6 +335,12 @@ template <typename R, int N> struct Impl {
             add_x<4, false, true>(o); add_x<8, false, true>(o);
             add_yinv<4, YE0>(o); add_yinv<8, YE0>(o); add_yinv<16, YE0>(o); add_yinv<32, YE0>(o);
             add_yfwd<4, YE0>(o); add_yfwd<8, YE0>(o); add_yfwd<16, YE0>(o); add_yfwd<32, YE0>(o);
+            add_yinv<4, YE0, true>(o); add_yinv<8, YE0, true>(o);
+            add_yfwd<4, YE0, true>(o); add_yfwd<8, YE0, true>(o);
+            // the five-field schedule at the default x width (64-byte rows):
+            // the combining y pass holds 8 values per thread, 64-byte rows too
+            add_x<XD, true, false>(o); add_x<XD, true, true>(o);
+            add_ycurl<XD, false>(o); add_ycurl<XD, true>(o);
         }
         add_xr<4, false>(o); add_xr<8, false>(o); add_xr<16, false>(o); add_xr<32, false>(o);
         add_xr<4, true>(o); add_xr<8, true>(o);
@@ -319,7 +348,7 @@ template <typename R, int N> struct Impl {
         add_z<16>(o); add_z<32>(o); add_z<64>(o); add_z<128>(o);
         // defaults, the fastest measured on MI355X at 256^3, 512^3 and
         // 1024^3: 128-byte row segments in the x and y passes, four z lines
-        // per workgroup (eight for N = 256, two for N = 1024); for small N,
+        // per workgroup (eight for N = 256, one for N = 1024); for small N,
         // at least one full 64-lane wave per workgroup.  At 1024 the x
         // passes (64-byte rows) take the XCD-grouped tile order (stage pass
         // 41.2 -> 38.1 ms FP64, 24.4 -> 22.3 ms FP32); the FP32 forward y
@@ -332,7 +361,7 @@ template <typename R, int N> struct Impl {
         o.def[P_XSTAGE] = pick(o, P_XSTAGE, xw, cy, ye, pair);
         o.def[P_YINV6] = pick(o, P_YINV6, yw, cy, ye, pair);
         o.def[P_YFWD3] = pick(o, P_YFWD3, yw, cy, ye, pair);
-        o.def[P_ZCROSS] = pick(o, P_ZCROSS, std::max(N >= 1024 ? 2 : (N == 256 ? 8 : 4), 64 / G), cy, ye, pair);
+        o.def[P_ZCROSS] = pick(o, P_ZCROSS, std::max(N >= 1024 ? 1 : (N == 256 ? 8 : 4), 64 / G), cy, ye, pair);
         o.xinv3 = &xinv3;
         o.yinv3 = &yinv3;
         o.yfwd3s = &yfwd3s;

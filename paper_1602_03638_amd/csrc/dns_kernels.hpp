@@ -153,13 +153,12 @@ __device__ __forceinline__ void xinv_curl_store(cx<R> (&v)[3][x_elems<R>(N)],
     }
     fft_line<R, N, E, +1, true>(b, lt, T, twl, g);               // F(kx v_hat)
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        A(W + 3 * FS, m) = b[m];
-        b[m] = cscale<R>(v[2][m], (R)kfreq(g + m * G, N));
-    }
+    for (int m = 0; m < E; ++m) A(W + 3 * FS, m) = b[m];
     fft_line<R, N, E, +1, true>(v[1], lt, T, twl, g);            // V
 #pragma unroll
     for (int m = 0; m < E; ++m) A(W + FS, m) = v[1][m];
+#pragma unroll
+    for (int m = 0; m < E; ++m) b[m] = cscale<R>(v[2][m], (R)kfreq(g + m * G, N));
     fft_line<R, N, E, +1, true>(b, lt, T, twl, g);               // F(kx w_hat)
 #pragma unroll
     for (int m = 0; m < E; ++m) A(W + 4 * FS, m) = b[m];
@@ -376,7 +375,9 @@ __device__ __forceinline__ void yinv_curl_tile(cx<R>* __restrict__ W, const cx<R
 template <typename R, int N, int T> constexpr int y_main_tiles() { return N * ((N / 2) / T); }
 template <typename R, int N, int T> constexpr int y_tiles() { return y_main_tiles<R, N, T>() + N / T; }
 
-template <typename R, int N, int T, int DIR, int NF, int YE>
+// PAIR: the tiles of one 128-byte line (rows shorter than 128 bytes) go to
+// workgroups of one XCD, as in the x passes (x_tile).
+template <typename R, int N, int T, int DIR, int NF, int YE, bool PAIR = false>
 __global__ __launch_bounds__(N / YE * T)
 void k_yline(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
     W += blockIdx.y * wst;
@@ -388,19 +389,19 @@ void k_yline(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
         load_twiddles<R, N>(twl, tw);
         t = twl;
     }
-    const int b = blockIdx.x;
+    const int b = x_tile<PAIR ? line_group<R, T>() : 1>((int)blockIdx.x, y_main_tiles<R, N, T>());
     if (b < y_main_tiles<R, N, T>()) yline_tile<R, N, T, DIR, NF, false, YE>(W, t, lds, b);
     else yline_tile<R, N, T, DIR, NF, true, YE>(W, t, lds, b - y_main_tiles<R, N, T>());
 }
 
-template <typename R, int N, int T>
+template <typename R, int N, int T, bool PAIR = false>
 __global__ __launch_bounds__(N / 8 * T)
 void k_yinv_curl(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
     W += blockIdx.y * wst;
     __shared__ cx<R> lds[T * N];
     __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
     load_twiddles<R, N>(twl, tw);
-    const int b = blockIdx.x;
+    const int b = x_tile<PAIR ? line_group<R, T>() : 1>((int)blockIdx.x, y_main_tiles<R, N, T>());
     if (b < y_main_tiles<R, N, T>()) yinv_curl_tile<R, N, T, false>(W, twl, lds, b);
     else yinv_curl_tile<R, N, T, true>(W, twl, lds, b - y_main_tiles<R, N, T>());
 }
@@ -642,8 +643,9 @@ void k_zc2r(const cx<R>* __restrict__ W, R* __restrict__ u, const cx<R>* __restr
 // with cb = b_s dt (b = 1/2, 1/2, 1) and ca = dt/6.  Stage 4 is the whole
 // forward Euler step of the Sec. 3.1 main loop, u_hat += R dt:
 //   stage 4:  U0 = U0 + ca R, ca = dt                          (u_s = U0)
-// At the last stage of a step (3, or 4 for Euler) with diag != nullptr,
-// each workgroup also writes partial sums
+// At the last stage of a step (3, or 4 for Euler), in the kernel instance
+// with diagnostics (DIAG; launched when diag != nullptr), each workgroup also
+// writes partial sums
 // of w |u_hat|^2 and w |k x u_hat|^2 of the new state (w = 1 on the kz = 0
 // and kz = N/2 planes, 2 elsewhere) to diag[2 blockIdx], diag[2 blockIdx + 1].
 // ---------------------------------------------------------------------------
@@ -702,7 +704,7 @@ __device__ __forceinline__ void diag_mode(cx<R> v0, cx<R> v1, cx<R> v2, int kx, 
 // between elements keeps the loads from being batched.  Fewer registers than
 // the batched form, for 1024-thread shapes whose register budget is 128 per
 // thread.
-template <typename R, int N, int E, int STAGE, bool NYQ>
+template <typename R, int N, int E, int STAGE, bool NYQ, bool DIAG>
 __device__ __forceinline__ void rk_apply_elementwise(cx<R> (&nh)[3][E], const XCol<R, N, NYQ>& col, int g,
                                                      cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
                                                      cx<R>* __restrict__ Us, const StageArgs& sa,
@@ -755,9 +757,7 @@ __device__ __forceinline__ void rk_apply_elementwise(cx<R> (&nh)[3][E], const XC
             }
             nh[f][m] = v;
         }
-        if constexpr (STAGE >= 3) {
-            if (sa.diag != nullptr) diag_mode<R, N>(nh[0][m], nh[1][m], nh[2][m], kx, ky, kz, e_acc, w_acc);
-        }
+        if constexpr (STAGE >= 3 && DIAG) diag_mode<R, N>(nh[0][m], nh[1][m], nh[2][m], kx, ky, kz, e_acc, w_acc);
         asm volatile("" ::: "memory");
     }
 }
@@ -768,7 +768,7 @@ __device__ __forceinline__ void rk_apply_elementwise(cx<R> (&nh)[3][E], const XC
 // once; a compiler memory barrier after each field keeps the next field's
 // loads from being hoisted into the same batch (which would exhaust the
 // registers).
-template <typename R, int N, int E, int STAGE, bool NYQ>
+template <typename R, int N, int E, int STAGE, bool NYQ, bool DIAG>
 __device__ __forceinline__ void rk_apply_batched(cx<R> (&nh)[3][E], const XCol<R, N, NYQ>& col, int g,
                                                cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
                                                cx<R>* __restrict__ Us, const StageArgs& sa, double& e_acc,
@@ -781,13 +781,11 @@ __device__ __forceinline__ void rk_apply_batched(cx<R> (&nh)[3][E], const XCol<R
     const R nu = (R)sa.nu, ca = (R)sa.ca, cb = (R)sa.cb;
     const XAddr<R, N, NYQ> A(col, g);
 
-    R visc[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int kx = kfreq(g + m * G, N);
         const bool keep = keep_yz && (3 * abs(kx) < lim);
         project_mode<R>(nh[0][m], nh[1][m], nh[2][m], kx, ky, kz, keep);
-        visc[m] = nu * (R)(kx * kx + ky * ky + kz * kz);
     }
     const cx<R>* ps = (STAGE <= 0 || STAGE == 4) ? U0 : Us;  // u_s
     const cx<R>* po = (STAGE == 3) ? U1 : U0;                // second array of stages 1..3
@@ -802,8 +800,11 @@ __device__ __forceinline__ void rk_apply_batched(cx<R> (&nh)[3][E], const XCol<R
         }
 #pragma unroll
         for (int m = 0; m < E; ++m) {
-            // R = N_hat - nu |k|^2 u_s
-            const cx<R> r = csub<R>(nh[f][m], cscale<R>(us[m], visc[m]));
+            // R = N_hat - nu |k|^2 u_s (the factor recomputed per field from
+            // integers: cheaper than holding E values across the loads)
+            const int kx = kfreq(g + m * G, N);
+            const R visc = nu * (R)(kx * kx + ky * ky + kz * kz);
+            const cx<R> r = csub<R>(nh[f][m], cscale<R>(us[m], visc));
             cx<R> v;
             if constexpr (STAGE < 0) {
                 v = r;
@@ -829,25 +830,27 @@ __device__ __forceinline__ void rk_apply_batched(cx<R> (&nh)[3][E], const XCol<R
         }
         asm volatile("" ::: "memory");
     }
-    if constexpr (STAGE >= 3) {
-        if (sa.diag != nullptr) {
+    if constexpr (STAGE >= 3 && DIAG) {
 #pragma unroll
-            for (int m = 0; m < E; ++m)
-                diag_mode<R, N>(nh[0][m], nh[1][m], nh[2][m], kfreq(g + m * G, N), ky, kz, e_acc, w_acc);
-        }
+        for (int m = 0; m < E; ++m)
+            diag_mode<R, N>(nh[0][m], nh[1][m], nh[2][m], kfreq(g + m * G, N), ky, kz, e_acc, w_acc);
     }
 }
 
 // Register budget decides between the two forms of the update: the
 // batched one keeps more loads in flight, the per-element one fits the
-// 128-register budget of 1024-thread workgroups.
-template <typename R, int N, int E, int STAGE, bool NYQ, int NT>
+// 128-register budget of 1024-thread workgroups.  DIAG: the last stage of a
+// step also accumulates the diagnostic partial sums (a kernel instance of
+// its own, so that steps without diagnostics carry none of that code).
+template <typename R, int N, int E, int STAGE, bool NYQ, int NT, bool DIAG>
 __device__ __forceinline__ void rk_apply_stage(cx<R> (&nh)[3][E], const XCol<R, N, NYQ>& col, int g,
                                                cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
                                                cx<R>* __restrict__ Us, const StageArgs& sa, double& e_acc,
                                                double& w_acc) {
-    if constexpr (NT > 512) rk_apply_elementwise<R, N, E, STAGE, NYQ>(nh, col, g, U0, U1, Us, sa, e_acc, w_acc);
-    else rk_apply_batched<R, N, E, STAGE, NYQ>(nh, col, g, U0, U1, Us, sa, e_acc, w_acc);
+    if constexpr (NT > 512)
+        rk_apply_elementwise<R, N, E, STAGE, NYQ, DIAG>(nh, col, g, U0, U1, Us, sa, e_acc, w_acc);
+    else
+        rk_apply_batched<R, N, E, STAGE, NYQ, DIAG>(nh, col, g, U0, U1, Us, sa, e_acc, w_acc);
 }
 
 // Fixed-order tree reduction of the two diagnostic partial sums over a
@@ -874,10 +877,10 @@ __device__ __forceinline__ void diag_reduce(double (&red)[2][NT], double e_acc, 
     }
 }
 
-template <typename R, int N, int T, int STAGE, bool NYQ>
+template <typename R, int N, int T, int STAGE, bool NYQ, bool DIAG>
 __device__ __forceinline__ void xrhs_tile(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
                                           cx<R>* __restrict__ Us, const StageArgs& sa, cx<R>* lds, const cx<R>* twl,
-                                          double (&red)[2][N / x_elems<R>(N) * T], int tile) {
+                                          double (&red)[2][DIAG ? N / x_elems<R>(N) * T : 1], int tile) {
     constexpr int E = x_elems<R>(N), G = N / E;
     constexpr int NT = G * T;
     constexpr size_t FS = Lay<R, N>::FS;
@@ -891,13 +894,13 @@ __device__ __forceinline__ void xrhs_tile(const cx<R>* __restrict__ W, cx<R>* __
 #pragma unroll
     for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true>(nh[f], lds + t, T, twl, g);
     double e_acc = 0.0, w_acc = 0.0;
-    rk_apply_stage<R, N, E, STAGE, NYQ, NT>(nh, col, g, U0, U1, Us, sa, e_acc, w_acc);
-    if (STAGE >= 3 && sa.diag) diag_reduce<NT>(red, e_acc, w_acc, sa.diag, tile);
+    rk_apply_stage<R, N, E, STAGE, NYQ, NT, DIAG>(nh, col, g, U0, U1, Us, sa, e_acc, w_acc);
+    if constexpr (STAGE >= 3 && DIAG) diag_reduce<NT>(red, e_acc, w_acc, sa.diag, tile);
 }
 
 // The RK stage is a template parameter: one kernel per stage gives each
 // its own straight-line code and register allocation.
-template <typename R, int N, int T, int STAGE, bool PAIR>
+template <typename R, int N, int T, int STAGE, bool PAIR, bool DIAG>
 __global__ __launch_bounds__(N / x_elems<R>(N) * T)
 void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
             cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa, size_t sst, size_t wst) {
@@ -907,12 +910,12 @@ void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restri
     Us += blockIdx.y * sst;
     if (sa.diag) sa.diag += 2 * (size_t)gridDim.x * blockIdx.y;
     __shared__ cx<R> lds[T * N];
-    __shared__ double red[2][N / x_elems<R>(N) * T];
+    __shared__ double red[2][DIAG ? N / x_elems<R>(N) * T : 1];
     __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
     load_twiddles<R, N>(twl, tw);
     const int tile = x_tile<PAIR ? line_group<R, T>() : 1>((int)blockIdx.x, x_main_tiles<N, T>());
-    if (tile < x_main_tiles<N, T>()) xrhs_tile<R, N, T, STAGE, false>(W, U0, U1, Us, sa, lds, twl, red, tile);
-    else xrhs_tile<R, N, T, STAGE, true>(W, U0, U1, Us, sa, lds, twl, red, tile);
+    if (tile < x_main_tiles<N, T>()) xrhs_tile<R, N, T, STAGE, false, DIAG>(W, U0, U1, Us, sa, lds, twl, red, tile);
+    else xrhs_tile<R, N, T, STAGE, true, DIAG>(W, U0, U1, Us, sa, lds, twl, red, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -924,10 +927,11 @@ void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restri
 // before fields 0..4 are written; a workgroup owns its columns, so this is
 // safe in place.
 // ---------------------------------------------------------------------------
-template <typename R, int N, int T, int STAGE, bool NYQ, bool CY>
+template <typename R, int N, int T, int STAGE, bool NYQ, bool CY, bool DIAG>
 __device__ __forceinline__ void xstage_tile(cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
                                             cx<R>* __restrict__ Us, const StageArgs& sa, cx<R>* lds,
-                                            const cx<R>* twl, double (&red)[2][N / x_elems<R>(N) * T], int tile) {
+                                            const cx<R>* twl, double (&red)[2][DIAG ? N / x_elems<R>(N) * T : 1],
+                                            int tile) {
     constexpr int E = x_elems<R>(N), G = N / E;
     constexpr int NT = G * T;
     constexpr size_t FS = Lay<R, N>::FS;
@@ -944,14 +948,14 @@ __device__ __forceinline__ void xstage_tile(cx<R>* __restrict__ W, cx<R>* __rest
 #pragma unroll
     for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true>(u[f], lt, T, twl, g);
     double e_acc = 0.0, w_acc = 0.0;
-    rk_apply_stage<R, N, E, STAGE, NYQ, NT>(u, col, g, U0, U1, Us, sa, e_acc, w_acc);
-    if (STAGE >= 3 && sa.diag) diag_reduce<NT>(red, e_acc, w_acc, sa.diag, tile);
+    rk_apply_stage<R, N, E, STAGE, NYQ, NT, DIAG>(u, col, g, U0, U1, Us, sa, e_acc, w_acc);
+    if constexpr (STAGE >= 3 && DIAG) diag_reduce<NT>(red, e_acc, w_acc, sa.diag, tile);
 
     // inverse x transforms for the next stage's velocity and vorticity
     xinv_curl_store<R, N, T, NYQ, CY>(u, W, A, lt, twl, g, col.ky, col.kz);
 }
 
-template <typename R, int N, int T, int STAGE, bool CY, bool PAIR>
+template <typename R, int N, int T, int STAGE, bool CY, bool PAIR, bool DIAG>
 __global__ __launch_bounds__(N / x_elems<R>(N) * T)
 void k_xstage(cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
               cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa, size_t sst, size_t wst) {
@@ -961,14 +965,14 @@ void k_xstage(cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__
     Us += blockIdx.y * sst;
     if (sa.diag) sa.diag += 2 * (size_t)gridDim.x * blockIdx.y;
     __shared__ cx<R> lds[T * N];
-    __shared__ double red[2][N / x_elems<R>(N) * T];
+    __shared__ double red[2][DIAG ? N / x_elems<R>(N) * T : 1];
     __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
     load_twiddles<R, N>(twl, tw);
     const int tile = x_tile<PAIR ? line_group<R, T>() : 1>((int)blockIdx.x, x_main_tiles<N, T>());
     if (tile < x_main_tiles<N, T>())
-        xstage_tile<R, N, T, STAGE, false, CY>(W, U0, U1, Us, sa, lds, twl, red, tile);
+        xstage_tile<R, N, T, STAGE, false, CY, DIAG>(W, U0, U1, Us, sa, lds, twl, red, tile);
     else
-        xstage_tile<R, N, T, STAGE, true, CY>(W, U0, U1, Us, sa, lds, twl, red, tile);
+        xstage_tile<R, N, T, STAGE, true, CY, DIAG>(W, U0, U1, Us, sa, lds, twl, red, tile);
 }
 
 // ---------------------------------------------------------------------------

@@ -120,3 +120,67 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_kernel_names_and_algorithmic_bytes():
+    """Trace names reduce to the kernel instance; the algorithmic bytes of a
+    stage kernel follow from its template arguments (fields C = N^2 (N/2+1)
+    complex values)."""
+    C = bench.field_bytes(512, "f64")
+    name = bench.kernel_short_name("void dns::k_xstage<double, 512, 8, 1, true, false, false>(HIP_vector_type<double, 2u>*)")
+    assert name == "k_xstage<double, 512, 8, 1, true, false, false>"
+    assert bench.algorithmic_bytes(name) == (3 + 12 + 5) * C
+    assert bench.algorithmic_bytes("k_xstage<double, 512, 8, 3, false, true, true>") == (3 + 9 + 6) * C
+    assert bench.algorithmic_bytes("k_xrhs<double, 512, 8, 0, false, false>") == 9 * C
+    assert bench.algorithmic_bytes("k_yinv_curl<double, 512, 8, false>") == 11 * C
+    assert bench.algorithmic_bytes("k_yline<double, 512, 8, -1, 3, 8, false>") == 6 * C
+    assert bench.algorithmic_bytes("k_zcross<double, 512, 4>") == 9 * C
+    assert bench.algorithmic_bytes("k_xinv_curl<float, 1024, 8, false, true>") == 9 * bench.field_bytes(1024, "f32")
+    assert bench.algorithmic_bytes("k_layout<double, 512, true>") is None
+
+
+def _counter_csv(path, rows):
+    hdr = ('"Correlation_Id","Dispatch_Id","Agent_Id","Queue_Id","Process_Id","Thread_Id","Grid_Size",'
+           '"Kernel_Id","Kernel_Name","Workgroup_Size","LDS_Block_Size","Scratch_Size","VGPR_Count",'
+           '"Accum_VGPR_Count","SGPR_Count","Counter_Name","Counter_Value","Start_Timestamp","End_Timestamp"')
+    path.parent.mkdir(parents=True, exist_ok=True)
+    lines = [hdr] + [f'{i},{i},"Agent 1",1,1,1,1,1,"{k}",256,0,0,8,0,32,"{c}",{v},0,1'
+                     for i, (k, c, v) in enumerate(rows, 1)]
+    path.write_text("\n".join(lines) + "\n")
+
+
+def test_counter_summary_calibrates_and_keys_by_source(tmp_path):
+    """Counter summaries scale FETCH_SIZE and WRITE_SIZE by the factors a copy
+    of known size gives, average over dispatches, and carry the current
+    kernel-source hash (never keyed by hand)."""
+    k = "void dns::k_zcross<double, 512, 4>(HIP_vector_type<double, 2u>*, double, unsigned long)"
+    _counter_csv(tmp_path / "f" / "h" / "run_counter_collection.csv",
+                 [(k, "FETCH_SIZE", 3000000.0), (k, "FETCH_SIZE", 3000002.0)])
+    _counter_csv(tmp_path / "w" / "h" / "run_counter_collection.csv", [(k, "WRITE_SIZE", 3100000.0)])
+    _counter_csv(tmp_path / "cf" / "h" / "run_counter_collection.csv",
+                 [("dns::k_copy_rows(x)", "FETCH_SIZE", 524288.0)])
+    _counter_csv(tmp_path / "cw" / "h" / "run_counter_collection.csv",
+                 [("dns::k_copy_rows(x)", "WRITE_SIZE", 1048576.0)])
+    out_json, out_md = tmp_path / "t.json", tmp_path / "t.md"
+    bench.summarize_counters(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"), str(tmp_path / "cw"),
+                             1 << 30, 512, str(out_json), str(out_md), ["cmd a", "cmd b"], "title")
+    rec = json.loads(out_json.read_text())
+    assert rec["source_sha256"] == bench.kernel_source_hash()
+    v = rec["kernels"]["k_zcross<double, 512, 4>"]
+    assert abs(v["fetch_factor"] - 2.0) < 1e-12 and abs(v["write_factor"] - 1.0) < 1e-12
+    assert abs(v["traffic_bytes_calibrated"] - (3000001.0 * 2 + 3100000.0) * 1024) < 1e-3
+    assert v["dispatches"] == 2 and v["alg_bytes"] == 9 * bench.field_bytes(512, "f64")
+    assert "cmd a" in out_md.read_text()
+
+
+def test_trace_summary_table(tmp_path):
+    d = tmp_path / "s" / "h"
+    d.mkdir(parents=True)
+    (d / "run_kernel_stats.csv").write_text(
+        '"Name","Calls","TotalDurationNs","AverageNs","Percentage","MinNs","MaxNs","StdDev"\n'
+        '"void dns::k_zcross<double, 512, 4>(double*)",4,7200000,1800000.0,50.0,1790000,1810000,0.0\n')
+    out = tmp_path / "trace.md"
+    bench.summarize_trace(str(tmp_path / "s"), str(out), "rocprofv3 ...", "title")
+    text = out.read_text()
+    assert "`k_zcross<double, 512, 4>` | 4 | 1800.0" in text
+    assert f"{9 * bench.field_bytes(512, 'f64') / 1.8e-3 / 1e9:.0f}" in text

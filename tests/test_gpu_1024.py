@@ -129,19 +129,26 @@ def test_rhs_1024_band_limited_matches_oracle_128(dtype, tol, band_rhs):
 
 
 def test_rhs_1024_xcd_grouped_tiles_bitwise(band_rhs):
-    """The XCD-grouped x passes (both tiles of a 128-byte line on one XCD)
-    compute the same bits as the plain tile order: the right-hand side and
-    one RK4 step at 1024^3 FP32."""
+    """The XCD-grouped x and y passes (the tiles of a 128-byte line on one
+    XCD), and the five-field schedule (vorticity combined in the y pass)
+    compute the same bits as the default: the right-hand side and one RK4
+    step at 1024^3 FP32."""
     note("1024 fp32 xcd grouping bitwise")
     torch = torch_mod()
     from gpu_util import embed_on_device
     from paper_1602_03638_amd import Solver
     uh, _, nu = band_rhs
     outs = []
-    for pair in (False, True):
-        s = Solver(N, nu, DT, dtype="f32", xcd_pair=pair)
+    for pair in (False, True, "y", "curl_in_y"):
+        s = Solver(N, nu, DT, dtype="f32", xcd_pair=bool(pair), curl_in_y=True if pair == "curl_in_y" else None)
+        if pair == "y":
+            var = s.plan_variants_ex()
+            plan = s.plan_ex()
+            for p in ("yinv6", "yfwd3"):
+                plan[p] = [i for i, d in enumerate(var[p]) if d["xcd_pair"] == 1 and d["width"] == 8][0]
+            s.set_plan_ex(plan)
         sched = s.schedule()
-        assert sched["xstage"]["xcd_pair"] == int(pair) and sched["xrhs_rk4"]["xcd_pair"] == int(pair)
+        assert sched["xstage"]["xcd_pair"] == int(bool(pair)) and sched["xrhs_rk4"]["xcd_pair"] == int(bool(pair))
         dev = embed_on_device(uh.astype(np.complex64), N, "f32", 21)
         s.set_spectral(dev)
         r = s.rhs()
@@ -151,8 +158,9 @@ def test_rhs_1024_xcd_grouped_tiles_bitwise(band_rhs):
         del r
         s.close()
         torch.cuda.empty_cache()
-    assert torch.equal(outs[0][0], outs[1][0])
-    assert torch.equal(outs[0][1], outs[1][1])
+    for k in (1, 2, 3):
+        assert torch.equal(outs[0][0], outs[k][0]), k
+        assert torch.equal(outs[0][1], outs[k][1]), k
 
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 2e-6)])

@@ -480,3 +480,20 @@ def test_injected_launch_failure_reports_hip_error(monkeypatch):
     s.close()
     ok = _solver(16).set_spectral(to_dev(uh0, "f64")).step(1)
     assert np.isfinite(ok.energy())
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_nyquist_planes_of_masked_fields_stay_zero(dtype):
+    """A field inside the 2/3-rule mask keeps its kz = N/2 plane (and the
+    kx = -N/2, ky = -N/2 planes) exactly zero through RK4 steps: the mask
+    removes the nonlinear term there and the viscous term of a zero mode is
+    zero.  So the paper's pencil-solver choice of not storing the kz = N/2
+    plane (Sec. 3.3) would leave these runs bit for bit unchanged."""
+    note(f"nyquist planes stay zero {dtype}")
+    N = 64
+    s = _solver(N, 0.01, 0.005, dtype=dtype).init_random(1234, k0=4.0, energy=0.5).step(10)
+    uh = to_host(s.get_spectral())
+    assert np.count_nonzero(uh[:, :, :, N // 2]) == 0
+    assert np.count_nonzero(uh[:, N // 2, :, :]) == 0 and np.count_nonzero(uh[:, :, N // 2, :]) == 0
+    assert np.count_nonzero(uh) > 0
+    s.close()
