@@ -506,7 +506,8 @@ def gpu_clocks():
 def sweep(N, dtype, reps=2):
     """Time every variant of every pass (HIP events, mean over the launches
     of `reps` profiled steps) with the other passes at the default plan, and
-    the autotuner's choice; fused and unfused schedules."""
+    the autotuner's choice in its reproducible and fastest modes (with the
+    step time of each plan); fused and unfused schedules."""
     import torch
     import workloads
     from paper_1602_03638_amd import Solver
@@ -527,12 +528,21 @@ def sweep(N, dtype, reps=2):
                 s.profile_step(1)            # warm (rebuilds the fused work space)
                 res.append(dict(d, ms=round(s.profile_step(reps)[p], 4)))
             out["passes"][p] = res
+            progress(f"sweep {N}^3 {dtype} {p}: {len(res)} variants")
         s.set_plan_ex(base)
         key = "fused" if fuse else "unfused"
-        s.autotune()
-        out[f"autotuned_{key}"] = s.schedule()
-        s.profile_step(1)
-        out[f"autotuned_ms_{key}"] = {k: round(v, 4) for k, v in s.profile_step(reps).items()}
+        for mode, tag in (("reproducible", ""), ("fastest", "fastest_")):
+            s.autotune(mode=mode)
+            out[f"autotuned_{tag}{key}"] = s.schedule()
+            s.profile_step(1)
+            out[f"autotuned_{tag}ms_{key}"] = {k: round(v, 4) for k, v in s.profile_step(reps).items()}
+            s.step(1)
+            s.synchronize()
+            t0 = time.perf_counter()
+            s.step(10)
+            s.synchronize()
+            out[f"autotuned_{tag}step_ms_{key}"] = round((time.perf_counter() - t0) * 100.0, 4)
+            s.set_plan_ex(base)
         s.close()
     print(json.dumps(out), flush=True)
     return 0

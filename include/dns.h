@@ -77,7 +77,9 @@ typedef struct dns_opts {
     int history_cap;  /* capacity of the history buffer in steps; default 4096 */
     int use_graph;    /* 1 = replay each RK4 step as one captured HIP graph
                          (default), 0 = launch kernels one by one */
-    int autotune;     /* 1 = run dns_autotune at creation; default 0 */
+    int autotune;     /* 1 = tune the plan at creation in reproducible mode
+                         (dns_autotune), 2 = in fastest mode
+                         (dns_autotune_ex, DNS_TUNE_FASTEST); default 0 */
     int fuse;         /* 1 = fuse each stage's RHS/RK4 pass with the next
                          stage's inverse x pass (16 kernels per step, default);
                          0 = unfused schedule (20 kernels per step).  Both give
@@ -261,14 +263,19 @@ int dns_inverse(dns_t* ctx, const void* uhat_dev, void* u_dev);
 /* Execution plan.  Each of the six kernels (index order: inverse x pass
  * with curl, inverse y pass, fused z pass, forward y pass, forward x pass
  * with the RHS and RK4 update, and the latter fused with the next stage's
- * inverse x pass) has several variants
- * that differ only in how many FFT lines share a workgroup (the "width");
- * every variant performs the same arithmetic per line, so results are
- * bitwise identical whichever is chosen.
+ * inverse x pass) has several variants.  Most differ only in how many FFT
+ * lines share a workgroup (the "width") and in the schedule choices below;
+ * they perform the same arithmetic per line, so results are bitwise
+ * identical whichever is chosen.  The variants with another radix plan
+ * (dns_variant.radix != 0) compute the same transforms with other rounding.
  *
- * dns_autotune times every variant on the context's own buffers (reps
- * launches each, 0 = 3) and keeps the fastest; the velocity state is
- * preserved.  dns_get_plan writes the chosen widths (6 entries);
+ * dns_autotune times every variant of radix plan 0 on the context's own
+ * buffers (reps launches each, 0 = 3) and keeps the fastest, so the tuned
+ * plan gives the default plan's bits (reproducible mode); the velocity state
+ * is preserved.  dns_autotune_ex with mode DNS_TUNE_FASTEST also times the
+ * variants of the other radix plans and may choose them (results then agree
+ * with the default plan to rounding, not bitwise); DNS_TUNE_REPRODUCIBLE is
+ * dns_autotune.  dns_get_plan writes the chosen widths (6 entries);
  * dns_set_plan selects variants by width (DNS_E_INVAL if a width does not
  * exist for this N and dtype); dns_plan_variants lists the widths available
  * for one kernel (pass index 0..5).  With opts.mfma_dft the y passes run the
@@ -277,10 +284,10 @@ int dns_inverse(dns_t* ctx, const void* uhat_dev, void* u_dev);
  *
  * Tuned plans are cached for the life of the process, keyed by (device
  * identity: architecture, name and compute units; N, dtype, simulations per
- * launch), each as the descriptors of its variants (see dns_variant below):
- * dns_autotune stores its choice, and a context or ensemble created with
- * opts.autotune = 1 takes the cached plan when one exists instead of timing
- * again.  dns_plan_cache_entries returns the number of cached plans;
+ * launch, tuning mode), each as the descriptors of its variants (see
+ * dns_variant below): dns_autotune(_ex) stores its choice, and a context or
+ * ensemble created with opts.autotune = 1 (2) takes the cached plan of the
+ * reproducible (fastest) mode when one exists instead of timing again.  dns_plan_cache_entries returns the number of cached plans;
  * dns_plan_cache_clear empties the cache.  Persistence across processes:
  * dns_plan_cache_save writes the cache to a file (JSON, one plan per line),
  * dns_plan_cache_load adds a file's plans to the cache and returns how many
@@ -288,7 +295,10 @@ int dns_inverse(dns_t* ctx, const void* uhat_dev, void* u_dev);
  * variable DNS_PLAN_CACHE set to a path, the cache is loaded from it on
  * first use and saved to it after every autotune.  A stored plan whose
  * variants this build does not have is ignored.  All thread-safe. */
+#define DNS_TUNE_REPRODUCIBLE 0
+#define DNS_TUNE_FASTEST 1
 int dns_autotune(dns_t* ctx, int reps);
+int dns_autotune_ex(dns_t* ctx, int reps, int mode);
 int dns_get_plan(const dns_t* ctx, int* widths, int max, int* count);
 int dns_set_plan(dns_t* ctx, const int* widths, int n);
 int dns_plan_variants(const dns_t* ctx, int pass, int* widths, int max, int* count);
@@ -297,7 +307,7 @@ int dns_plan_cache_clear(void);
 int dns_plan_cache_save(const char* path);
 int dns_plan_cache_load(const char* path);
 
-/* Schedule of a step.  Besides the width, a pass variant fixes three choices
+/* Schedule of a step.  Besides the width, a pass variant fixes four choices
  * that change where work is done, never the arithmetic (results stay
  * bitwise identical):
  *  - y_elems: complex values per thread in the y passes (8, 16 or 32): the
@@ -311,9 +321,22 @@ int dns_plan_cache_load(const char* path);
  *  - xcd_pair: the device dispatches workgroup b to XCD b mod 8, each XCD
  *    with its own L2.  Where an x-pass tile's row segments are 64 bytes,
  *    1 = the two tiles of each 128-byte line go to workgroups b and b + 8
- *    (one XCD), 0 = to consecutive workgroups.
- * dns_set_schedule selects, for every pass, the variant of the current width
- * (else the nearest width) that runs the given schedule; y_elems 0,
+ *    (one XCD), 0 = to consecutive workgroups;
+ *  - lds_pad (z pass only, else 0): a line's element p sits in shared
+ *    memory at p + p / lds_pad (one unused slot after every lds_pad
+ *    elements; 0 = no padding; default 8), which spreads the strided
+ *    Stockham exchanges over the banks.
+ * and one that changes the rounding:
+ *  - radix: the radix plan of the line transforms (Stockham stages with
+ *    N = 2^l): 0 = radix-8 stages, then one radix-4 or radix-2 stage (the
+ *    default plan); 1 = that radix-4 or radix-2 stage first; 2 = radix-4
+ *    stages, the last one radix 8 where l is odd.  Plans 1 and 2 exist, at
+ *    the default shape of each pass, only for the N where they differ from
+ *    the plans before them; only dns_autotune_ex in fastest mode or an
+ *    explicit dns_set_plan_ex chooses them.
+ * dns_set_schedule selects, for every pass, the variant of radix plan 0 and
+ * the default pad of the current width (else the nearest width) that runs
+ * the given schedule; y_elems 0,
  * curl_in_y -1 and xcd_pair -1 take the defaults for N.  DNS_E_INVAL for an
  * invalid value, DNS_E_UNSUPPORTED for a schedule this N and dtype (or the
  * matrix-core option) do not provide.  Waits for the stream.
@@ -329,6 +352,8 @@ typedef struct dns_variant {
     int xcd_pair;
     int y_elems;
     int curl_in_y;
+    int radix;
+    int lds_pad;
 } dns_variant;
 int dns_set_schedule(dns_t* ctx, int y_elems, int curl_in_y, int xcd_pair);
 int dns_plan_variants_ex(const dns_t* ctx, int pass, dns_variant* out, int max, int* count);

@@ -45,7 +45,21 @@ class dns_opts(ctypes.Structure):
 
 class dns_variant(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int), ("xcd_pair", ctypes.c_int), ("y_elems", ctypes.c_int),
-                ("curl_in_y", ctypes.c_int)]
+                ("curl_in_y", ctypes.c_int), ("radix", ctypes.c_int), ("lds_pad", ctypes.c_int)]
+
+
+DNS_TUNE_REPRODUCIBLE, DNS_TUNE_FASTEST = 0, 1
+TUNE_MODES = {"reproducible": DNS_TUNE_REPRODUCIBLE, "fastest": DNS_TUNE_FASTEST}
+
+
+def _autotune_opt(autotune):
+    """opts.autotune for a constructor argument: False, True (reproducible),
+    "reproducible" or "fastest"."""
+    if autotune is False or autotune is None:
+        return 0
+    if autotune is True:
+        return 1
+    return {"reproducible": 1, "fastest": 2}[autotune]
 
 
 _lib = None
@@ -95,6 +109,7 @@ def load_library(path=LIB_PATH):
         "dns_init_velocity": (I, [P, I, ctypes.POINTER(D), I]),
         "dns_init_random": (I, [P, ctypes.c_ulonglong, D, D]),
         "dns_autotune": (I, [P, I]),
+        "dns_autotune_ex": (I, [P, I, I]),
         "dns_get_plan": (I, [P, ctypes.POINTER(I), I, ctypes.POINTER(I)]),
         "dns_set_plan": (I, [P, ctypes.POINTER(I), I]),
         "dns_plan_variants": (I, [P, I, ctypes.POINTER(I), I, ctypes.POINTER(I)]),
@@ -248,7 +263,7 @@ class Solver:
         o.diag_every = int(diag_every)
         o.use_graph = 1 if use_graph else 0
         o.history_cap = int(history_cap)
-        o.autotune = 1 if autotune else 0
+        o.autotune = _autotune_opt(autotune)
         o.fuse = 1 if fuse else 0
         o.integrator = INTEGRATORS[integrator]
         o.mfma_dft = 1 if mfma_dft else 0
@@ -405,8 +420,12 @@ class Solver:
 
     PASSES = ("xinv_curl", "yinv6", "zcross", "yfwd3", "xrhs_rk4", "xstage")
 
-    def autotune(self, reps=3):
-        _check(load_library().dns_autotune(self.handle, int(reps)), self.handle, "dns_autotune")
+    def autotune(self, reps=3, mode="reproducible"):
+        """Time the variants and keep the fastest plan.  mode "reproducible":
+        radix plan 0 only (the tuned plan gives the default plan's bits);
+        "fastest": the other radix plans too."""
+        _check(load_library().dns_autotune_ex(self.handle, int(reps), TUNE_MODES[mode]), self.handle,
+               "dns_autotune_ex")
         return self.plan()
 
     def plan(self):
@@ -432,15 +451,16 @@ class Solver:
         return self
 
     def plan_variants_ex(self):
-        """Every variant of every pass: {pass: [dict(width, xcd_pair, y_elems, curl_in_y)]}."""
+        """Every variant of every pass:
+        {pass: [dict(width, xcd_pair, y_elems, curl_in_y, radix, lds_pad)]}."""
         out = {}
         for i, name in enumerate(self.PASSES):
             arr = (dns_variant * 32)()
             n = ctypes.c_int()
             _check(load_library().dns_plan_variants_ex(self.handle, i, arr, 32, ctypes.byref(n)), self.handle,
                    "dns_plan_variants_ex")
-            out[name] = [dict(width=v.width, xcd_pair=v.xcd_pair, y_elems=v.y_elems, curl_in_y=v.curl_in_y)
-                         for v in arr[: n.value]]
+            out[name] = [dict(width=v.width, xcd_pair=v.xcd_pair, y_elems=v.y_elems, curl_in_y=v.curl_in_y,
+                              radix=v.radix, lds_pad=v.lds_pad) for v in arr[: n.value]]
         return out
 
     def plan_ex(self):
@@ -463,8 +483,9 @@ class Solver:
     def plan_with(self, p, v, base=None):
         """Variant indices of `base` (default: the current plan) with variant v
         for pass p; where v changes the curl placement, the other coupled
-        passes take a variant of that placement (same width when there is
-        one), so that the plan is consistent."""
+        passes take a variant of that placement (same width and radix plan
+        when there is one, else radix plan 0), so that the plan is
+        consistent."""
         base = dict(self.plan_ex() if base is None else base)
         var = self.plan_variants_ex()
         base[p] = v
@@ -473,13 +494,16 @@ class Solver:
             for q in self.COUPLED:
                 if q == p or var[q][base[q]]["curl_in_y"] == cy:
                     continue
+                cur = var[q][base[q]]
                 cands = [i for i, d in enumerate(var[q]) if d["curl_in_y"] == cy]
-                same = [i for i in cands if var[q][i]["width"] == var[q][base[q]]["width"]]
-                base[q] = (same or cands)[0]
+                rank = sorted(cands, key=lambda i: (var[q][i]["radix"] != cur["radix"],
+                                                    var[q][i]["width"] != cur["width"], var[q][i]["radix"] != 0))
+                base[q] = rank[0]
         return base
 
     def schedule(self):
-        """The current plan's descriptors: {pass: dict(width, xcd_pair, y_elems, curl_in_y)}."""
+        """The current plan's descriptors:
+        {pass: dict(width, xcd_pair, y_elems, curl_in_y, radix, lds_pad)}."""
         var = self.plan_variants_ex()
         return {p: var[p][i] for p, i in self.plan_ex().items()}
 
@@ -549,7 +573,7 @@ class Ensemble:
         o.dealias = {"text": DNS_DEALIAS_TEXT, "appendix": DNS_DEALIAS_APPENDIX}[dealias]
         o.use_graph = 1 if use_graph else 0
         o.fuse = 1 if fuse else 0
-        o.autotune = 1 if autotune else 0
+        o.autotune = _autotune_opt(autotune)
         o.integrator = INTEGRATORS[integrator]
         o.mfma_dft = 1 if mfma_dft else 0
         if stream is None:

@@ -42,11 +42,11 @@ void unit_root(long m, long n, double* re, double* im) {
     *im = (double)(-sinl(ang));
 }
 
-void make_twiddles(int N, double* out) {
-    const int ns = num_stages(N);
+void make_twiddles(int N, double* out, int rs) {
+    const int ns = num_stages(N, rs);
     for (int s = 1; s < ns; ++s) {
-        const int L = span_at(N, s), Rr = radix_at(N, s);
-        double* w = out + 2 * tw_offset(N, s);
+        const int L = span_at(N, s, rs), Rr = radix_at(N, s, rs);
+        double* w = out + 2 * tw_offset(N, s, rs);
         for (int j = 0; j < L; ++j)
             for (int r = 1; r < Rr; ++r) {
                 const int idx = j * (Rr - 1) + (r - 1);
@@ -233,11 +233,15 @@ const void* mfma_tw2(const dns_t* c) { return (const char*)c->mfma_tw + (size_t)
 // vorticity from the x pass's five fields, 0 = the x pass writes six.
 int plan_cy(const dns_t* c) { return c->ops->var[dns::P_XSTAGE][c->sel[dns::P_XSTAGE]].cy; }
 
+// Twiddle table of radix plan rs in the context's table.
+const void* tw_of(const dns_t* c, int rs) { return (const char*)c->tw + (size_t)c->ops->tw_base[rs] * c->cbytes; }
+
 // Launch one pass of stage `stage` for all members (member < 0, one batched
 // launch) or for one member only.  diag: fused diagnostic partials of
 // member 0; member m's sit 2 * groups * m doubles further.
 void launch_pass(dns_t* c, int pass, int variant, int stage, double* diag, hipStream_t s, int member = -1) {
     const dns::Ops* o = c->ops;
+    const void* tw = tw_of(c, o->var[pass][variant].rs);
     const int m = member < 0 ? 0 : member;
     const dns::Batch b = member < 0 ? c->batch() : dns::Batch{1, 0, 0};
     double* dg = diag ? diag + (size_t)2 * diag_groups(c) * m : nullptr;
@@ -246,30 +250,30 @@ void launch_pass(dns_t* c, int pass, int variant, int stage, double* diag, hipSt
             // the stage's velocity: U0 at RK4 stage 0, for the RHS alone and
             // for the Euler step; the stage velocity Us at RK4 stages 1..3
             const bool from_u0 = stage <= 0 || stage == 4;
-            o->xinv[variant](from_u0 ? c->U0(m) : c->Us(m), c->W(m), c->tw, b, s);
+            o->xinv[variant](from_u0 ? c->U0(m) : c->Us(m), c->W(m), tw, b, s);
             break;
         }
         case dns::P_YINV6:
             if (c->opts.mfma_dft)
                 o->ymfma_inv6[plan_cy(c)](c->W(m), c->tw, c->mfma_tw, mfma_tw2(c), b, s);
             else
-                o->yinv6[variant](c->W(m), c->tw, b, s);
+                o->yinv6[variant](c->W(m), tw, b, s);
             break;
-        case dns::P_ZCROSS: o->zcross[variant](c->W(m), c->tw, b, s); break;
+        case dns::P_ZCROSS: o->zcross[variant](c->W(m), tw, b, s); break;
         case dns::P_YFWD3:
             if (c->opts.mfma_dft)
                 o->ymfma_fwd3(c->W(m), c->tw, c->mfma_tw, mfma_tw2(c), b, s);
             else
-                o->yfwd3[variant](c->W(m), c->tw, b, s);
+                o->yfwd3[variant](c->W(m), tw, b, s);
             break;
         case dns::P_XRHS: {
             const dns::StageArgs a = stage_args(c, stage, dg);
-            o->xrhs[variant](c->W(m), c->U0(m), c->U1(m), c->Us(m), c->tw, a, b, s);
+            o->xrhs[variant](c->W(m), c->U0(m), c->U1(m), c->Us(m), tw, a, b, s);
             break;
         }
         default: {
             const dns::StageArgs a = stage_args(c, stage, dg);
-            o->xstage[variant](c->W(m), c->U0(m), c->U1(m), c->Us(m), c->tw, a, b, s);
+            o->xstage[variant](c->W(m), c->U0(m), c->U1(m), c->Us(m), tw, a, b, s);
         }
     }
 }
@@ -364,15 +368,16 @@ void release(dns_t* c) {
 }
 
 // Process-wide cache of autotuned plans, keyed by (device identity, N,
-// dtype, simulations per launch).  A plan is stored as the descriptor
-// (width, XCD grouping, y elements, curl placement) of the chosen variant of
-// every pass, so that a plan read back from a file written by another build
-// is used only where those variants still exist.  dns_autotune stores its
+// dtype, simulations per launch, tuning mode).  A plan is stored as the
+// descriptor (width, XCD grouping, y elements, curl placement, radix plan,
+// z-pass pad) of the chosen variant of every pass, so that a plan read back
+// from a file written by another build is used only where those variants
+// still exist.  dns_autotune stores its
 // result; a context created with opts.autotune takes a cached plan instead
 // of timing again.  With DNS_PLAN_CACHE set to a file path, the cache is
 // read from that file on first use and written back after every autotune;
 // dns_plan_cache_save / dns_plan_cache_load do the same explicitly.
-using PlanKey = std::tuple<std::string, int, int, int>;
+using PlanKey = std::tuple<std::string, int, int, int, int>;
 using Plan = std::array<dns::Variant, dns::P_COUNT>;
 std::mutex g_plan_mu;
 std::map<PlanKey, Plan> g_plans;
@@ -390,22 +395,24 @@ std::string device_identity() {
     return id;
 }
 
-PlanKey plan_key(const dns_t* c) { return PlanKey{device_identity(), c->N, c->dtype, c->members}; }
+PlanKey plan_key(const dns_t* c, int mode) { return PlanKey{device_identity(), c->N, c->dtype, c->members, mode}; }
 
 // Cache file: valid JSON, one plan per line.
 int plan_cache_write(const char* path) {
     const std::string tmp = std::string(path) + ".tmp";
     FILE* f = std::fopen(tmp.c_str(), "w");
     if (!f) return DNS_E_INVAL;
-    std::fprintf(f, "{\"format\": \"dns-plan-cache-1\", \"plans\": [\n");
+    std::fprintf(f, "{\"format\": \"dns-plan-cache-2\", \"plans\": [\n");
     size_t i = 0;
     for (const auto& kv : g_plans) {
-        std::fprintf(f, "{\"device\": \"%s\", \"N\": %d, \"dtype\": %d, \"members\": %d, \"variants\": [",
+        std::fprintf(f,
+                     "{\"device\": \"%s\", \"N\": %d, \"dtype\": %d, \"members\": %d, \"mode\": %d, "
+                     "\"variants\": [",
                      std::get<0>(kv.first).c_str(), std::get<1>(kv.first), std::get<2>(kv.first),
-                     std::get<3>(kv.first));
+                     std::get<3>(kv.first), std::get<4>(kv.first));
         for (int p = 0; p < dns::P_COUNT; ++p) {
             const dns::Variant& v = kv.second[p];
-            std::fprintf(f, "%s[%d, %d, %d, %d]", p ? ", " : "", v.width, v.pair, v.ye, v.cy);
+            std::fprintf(f, "%s[%d, %d, %d, %d, %d, %d]", p ? ", " : "", v.width, v.pair, v.ye, v.cy, v.rs, v.pad);
         }
         std::fprintf(f, "]}%s\n", ++i < g_plans.size() ? "," : "");
     }
@@ -428,7 +435,8 @@ int plan_cache_read(const char* path) {
         const char* q = std::strchr(d, '"');
         if (!q) continue;
         const std::string dev(d, q);
-        long v[3 + 4 * dns::P_COUNT];
+        constexpr int NV = 4 + 6 * dns::P_COUNT;   // N, dtype, members, mode, 6 per variant
+        long v[NV];
         int k = 0;
         for (const char* t = q + 1; *t && k < (int)(sizeof v / sizeof v[0]);) {
             if (*t == '-' || (*t >= '0' && *t <= '9')) {
@@ -439,11 +447,13 @@ int plan_cache_read(const char* path) {
                 ++t;
             }
         }
-        if (k != 3 + 4 * dns::P_COUNT) continue;
+        if (k != NV || (v[3] != DNS_TUNE_REPRODUCIBLE && v[3] != DNS_TUNE_FASTEST)) continue;
         Plan p;
-        for (int i = 0; i < dns::P_COUNT; ++i)
-            p[i] = dns::Variant{(int)v[3 + 4 * i], (int)v[4 + 4 * i], (int)v[5 + 4 * i], (int)v[6 + 4 * i]};
-        g_plans[PlanKey{dev, (int)v[0], (int)v[1], (int)v[2]}] = p;
+        for (int i = 0; i < dns::P_COUNT; ++i) {
+            const long* d = v + 4 + 6 * i;
+            p[i] = dns::Variant{(int)d[0], (int)d[1], (int)d[2], (int)d[3], (int)d[4], (int)d[5]};
+        }
+        g_plans[PlanKey{dev, (int)v[0], (int)v[1], (int)v[2], (int)v[3]}] = p;
         ++n;
     }
     std::fclose(f);
@@ -460,10 +470,10 @@ void plan_env_load() {
 
 bool plan_consistent(const dns_t* c, const int* sel);
 
-void store_plan(const dns_t* c) {
+void store_plan(const dns_t* c, int mode) {
     Plan p;
     for (int k = 0; k < dns::P_COUNT; ++k) p[k] = c->ops->var[k][c->sel[k]];
-    const PlanKey key = plan_key(c);
+    const PlanKey key = plan_key(c, mode);
     std::lock_guard<std::mutex> lock(g_plan_mu);
     plan_env_load();
     g_plans[key] = p;
@@ -471,8 +481,12 @@ void store_plan(const dns_t* c) {
     if (path && *path) (void)plan_cache_write(path);
 }
 
-bool load_plan(dns_t* c) {
-    const PlanKey key = plan_key(c);
+bool same_variant(const dns::Variant& a, const dns::Variant& b) {
+    return a.width == b.width && a.pair == b.pair && a.ye == b.ye && a.cy == b.cy && a.rs == b.rs && a.pad == b.pad;
+}
+
+bool load_plan(dns_t* c, int mode) {
+    const PlanKey key = plan_key(c, mode);
     std::lock_guard<std::mutex> lock(g_plan_mu);
     plan_env_load();
     auto it = g_plans.find(key);
@@ -483,7 +497,7 @@ bool load_plan(dns_t* c) {
         const dns::Variant& want = it->second[k];
         for (int v = 0; v < c->ops->nvar[k]; ++v) {
             const dns::Variant& d = c->ops->var[k][v];
-            if (d.width == want.width && d.pair == want.pair && d.ye == want.ye && d.cy == want.cy) sel[k] = v;
+            if (same_variant(d, want)) sel[k] = v;
         }
         if (sel[k] < 0) return false;   // a variant of another build
     }
@@ -492,11 +506,17 @@ bool load_plan(dns_t* c) {
     return true;
 }
 
-// Tuned plan for a new context: from the cache, else timed (and cached).
+// Tuned plan for a new context (opts.autotune 1: reproducible, 2: fastest):
+// from the cache, else timed (and cached).
 int tune_new(dns_t* c) {
-    if (load_plan(c)) return DNS_OK;
-    return dns_autotune(c, 3);
+    const int mode = c->opts.autotune == 2 ? DNS_TUNE_FASTEST : DNS_TUNE_REPRODUCIBLE;
+    if (load_plan(c, mode)) return DNS_OK;
+    return dns_autotune_ex(c, 3, mode);
 }
+
+// Variants a reproducible plan is made of: radix plan 0 and the standard
+// z-pass pad (their results are bitwise those of the default plan).
+bool reference_shape(int p, const dns::Variant& d) { return d.rs == 0 && d.pad == (p == dns::P_ZCROSS ? 8 : 0); }
 
 // A plan is consistent when the passes whose fields depend on the curl
 // placement (inverse x, inverse y, fused stage) agree on it, and, with the
@@ -522,6 +542,7 @@ int find_variant(const dns::Ops& o, int p, int w, int cy, int ye, int pair) {
     };
     for (int v = 0; v < o.nvar[p]; ++v) {
         const dns::Variant& d = o.var[p][v];
+        if (!reference_shape(p, d)) continue;
         if (d.cy >= 0 && d.cy != cy) continue;
         if (d.ye > 0 && d.ye != ye && !(p == dns::P_YINV6 && cy == 1)) continue;
         if (best < 0 || rank(d) > rank(o.var[p][best])) best = v;
@@ -561,7 +582,7 @@ int check_args(int N, double nu, double dt, int dtype, const dns_opts& o) {
         return DNS_E_INVAL;
     if (o.mfma_dft && (dtype != DNS_FP32 || N < 64)) return DNS_E_UNSUPPORTED;
     if ((o.y_elems != 0 && o.y_elems != 8 && o.y_elems != 16 && o.y_elems != 32) || o.curl_in_y < -1 ||
-        o.curl_in_y > 1 || o.xcd_pair < -1 || o.xcd_pair > 1)
+        o.curl_in_y > 1 || o.xcd_pair < -1 || o.xcd_pair > 1 || o.autotune < 0 || o.autotune > 2)
         return DNS_E_INVAL;
     return DNS_OK;
 }
@@ -683,7 +704,7 @@ int create_ctx(int N, double nu, double dt, int dtype, const dns_opts& o, hipStr
     // twiddles: long-double accurate, rounded to the context's precision
     const int ntw = c->ops->tw_count;
     std::vector<double> twd(2 * (size_t)ntw, 0.0);
-    dns::make_twiddles(N, twd.data());
+    for (int r = 0; r < dns::NRS; ++r) dns::make_twiddles(N, twd.data() + 2 * (size_t)c->ops->tw_base[r], r);
     if (dtype == DNS_FP64) {
         e = hipMemcpy(c->tw, twd.data(), (size_t)ntw * c->cbytes, hipMemcpyHostToDevice);
     } else {
@@ -723,7 +744,8 @@ int reset_counters(dns_t* c) {
 int set_velocity_m(dns_t* c, int m, const void* u) {
     c->w_ready = false;
     c->ops->zr2c(u, c->W(m), c->tw, c->s);
-    c->ops->yfwd3[c->sel[dns::P_YFWD3]](c->W(m), c->tw, dns::Batch{1, 0, 0}, c->s);
+    c->ops->yfwd3[c->sel[dns::P_YFWD3]](c->W(m), tw_of(c, c->ops->var[dns::P_YFWD3][c->sel[dns::P_YFWD3]].rs),
+                                        dns::Batch{1, 0, 0}, c->s);
     c->ops->xfwd3(c->W(m), c->U0(m), c->tw, c->s);
     return launched(c, "set_velocity");
 }
@@ -1079,7 +1101,8 @@ int dns_forward(dns_t* c, const void* u, void* uh) {
     if (r) return r;
     c->w_ready = false;
     c->ops->zr2c(u, c->W(), c->tw, c->s);
-    c->ops->yfwd3[c->sel[dns::P_YFWD3]](c->W(), c->tw, dns::Batch{1, 0, 0}, c->s);
+    c->ops->yfwd3[c->sel[dns::P_YFWD3]](c->W(), tw_of(c, c->ops->var[dns::P_YFWD3][c->sel[dns::P_YFWD3]].rs),
+                                        dns::Batch{1, 0, 0}, c->s);
     c->ops->xfwd3(c->W(), c->Us(), c->tw, c->s);
     c->ops->layout(c->Us(), uh, false, c->s);
     if ((r = launched(c, "forward"))) return r;
@@ -1211,17 +1234,24 @@ int dns_profile_step(dns_t* c, int nsteps, float* ms, const char** names, int ma
 // each placement the fastest variants of the inverse x, inverse y and stage
 // passes are summed with the weights of one step, and the cheaper placement
 // wins; the other passes take their fastest variant.
-int dns_autotune(dns_t* c, int reps) {
-    if (!c || reps < 0) return fail(c, DNS_E_INVAL, "bad argument");
+int dns_autotune(dns_t* c, int reps) { return dns_autotune_ex(c, reps, DNS_TUNE_REPRODUCIBLE); }
+
+int dns_autotune_ex(dns_t* c, int reps, int mode) {
+    if (!c || reps < 0 || (mode != DNS_TUNE_REPRODUCIBLE && mode != DNS_TUNE_FASTEST))
+        return fail(c, DNS_E_INVAL, "bad argument");
     if (reps == 0) reps = 3;
     int r = enter(c);
     if (r) return r;
     drop_graphs(c);
     const dns::Ops& o = *c->ops;
     std::vector<std::vector<float>> t(dns::P_COUNT);
+    // reproducible mode: radix plan 0 only (every such plan gives the
+    // default plan's bits)
+    auto allowed = [&](int p, int v) { return mode == DNS_TUNE_FASTEST || o.var[p][v].rs == 0; };
     for (int p = 0; p < dns::P_COUNT; ++p) {
         t[p].assign(o.nvar[p], 1e30f);
         for (int v = 0; v < o.nvar[p]; ++v) {
+            if (!allowed(p, v)) continue;
             launch_pass(c, p, v, 1, nullptr, c->s);                  // warm-up
             DNS_TRY(c, hipEventRecord(c->ev_prof[0], c->s));
             for (int i = 0; i < reps; ++i) launch_pass(c, p, v, 1, nullptr, c->s);
@@ -1238,7 +1268,7 @@ int dns_autotune(dns_t* c, int reps) {
         int best = -1;
         for (int v = 0; v < o.nvar[p]; ++v) {
             const int vc = o.var[p][v].cy;
-            if (cy >= 0 && vc >= 0 && vc != cy) continue;
+            if (!allowed(p, v) || (cy >= 0 && vc >= 0 && vc != cy)) continue;
             if (best < 0 || t[p][v] < t[p][best]) best = v;
         }
         return best;
@@ -1263,7 +1293,7 @@ int dns_autotune(dns_t* c, int reps) {
     if (plan_consistent(c, sel))
         for (int p = 0; p < dns::P_COUNT; ++p) c->sel[p] = sel[p];
     c->w_ready = false;
-    store_plan(c);
+    store_plan(c, mode);
     return leave(c);
 }
 
@@ -1335,10 +1365,15 @@ int dns_set_plan(dns_t* c, const int* widths, int n) {
         // the variant of that width with the current schedule
         const dns::Variant& cur = o.var[p][c->sel[p]];
         sel[p] = -1;
+        // (same radix plan and pad as the current variant where there is one)
+        auto rank = [&](const dns::Variant& d) {
+            return 2 * (d.rs == cur.rs && d.pad == cur.pad ? 1 : 0) + (d.pair == cur.pair ? 1 : 0);
+        };
         for (int v = 0; v < o.nvar[p]; ++v) {
             const dns::Variant& d = o.var[p][v];
             if (d.width != widths[p] || (d.cy >= 0 && d.cy != cy) || (d.ye > 0 && d.ye != cur.ye)) continue;
-            if (sel[p] < 0 || (d.pair == cur.pair && o.var[p][sel[p]].pair != cur.pair)) sel[p] = v;
+            if (!reference_shape(p, d) && !(d.rs == cur.rs && d.pad == cur.pad)) continue;
+            if (sel[p] < 0 || rank(d) > rank(o.var[p][sel[p]])) sel[p] = v;
         }
         if (sel[p] < 0) return fail(c, DNS_E_INVAL, "no variant of that width for this N, dtype and schedule");
     }
@@ -1355,10 +1390,12 @@ int dns_plan_variants(const dns_t* c, int pass, int* widths, int max, int* count
     for (int v = 0; v < o.nvar[pass]; ++v) {
         const dns::Variant& d = o.var[pass][v];
         if ((d.cy >= 0 && d.cy != cy) || (d.ye > 0 && d.ye != cur.ye)) continue;
+        if (!reference_shape(pass, d) && !(d.rs == cur.rs && d.pad == cur.pad)) continue;
         bool seen = false;
         for (int u = 0; u < v; ++u) {
             const dns::Variant& e = o.var[pass][u];
-            seen = seen || (e.width == d.width && (e.cy < 0 || e.cy == cy) && (e.ye <= 0 || e.ye == cur.ye));
+            seen = seen || (e.width == d.width && (e.cy < 0 || e.cy == cy) && (e.ye <= 0 || e.ye == cur.ye) &&
+                            (reference_shape(pass, e) || (e.rs == cur.rs && e.pad == cur.pad)));
         }
         if (seen) continue;
         if (n < max) widths[n] = d.width;
@@ -1376,6 +1413,8 @@ int dns_plan_variants_ex(const dns_t* c, int pass, dns_variant* out, int max, in
         out[v].xcd_pair = o.var[pass][v].pair;
         out[v].y_elems = o.var[pass][v].ye;
         out[v].curl_in_y = o.var[pass][v].cy;
+        out[v].radix = o.var[pass][v].rs;
+        out[v].lds_pad = o.var[pass][v].pad;
     }
     *count = o.nvar[pass];
     return DNS_OK;

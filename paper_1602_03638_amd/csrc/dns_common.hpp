@@ -19,27 +19,76 @@ template <typename R> using cx = typename cvec<R>::type;
 constexpr int ilog2(int n) { int m = 0; while ((1 << m) < n) ++m; return m; }
 
 // ---------------------------------------------------------------------------
-// Radix plan of a length-N Stockham FFT: radix-8 stages while three or more
-// factors of two remain, then one radix-4 or radix-2 stage.
+// Radix plans of a length-N Stockham FFT (N = 2^l), selected by RS:
+//   RS = 0: radix-8 stages while three or more factors of two remain, then
+//           one radix-4 or radix-2 stage (the reference plan: every default
+//           kernel uses it);
+//   RS = 1: the radix-4 or radix-2 stage first, then radix-8 stages;
+//   RS = 2: radix-4 stages, the last one radix 8 where l is odd.
+// The plans compute the same DFT with different rounding, so a plan with
+// RS != 0 is chosen only where the caller accepts results that are not
+// bitwise identical to the reference plan's.
 // ---------------------------------------------------------------------------
-constexpr int num_stages(int N) { return ilog2(N) / 3 + (ilog2(N) % 3 ? 1 : 0); }
-constexpr int radix_at(int N, int s) {
-    return s < ilog2(N) / 3 ? 8 : (ilog2(N) % 3 == 1 ? 2 : 4);
+constexpr int NRS = 3;
+constexpr int num_stages(int N, int RS = 0) {
+    const int l = ilog2(N);
+    if (RS == 2) return (l % 2) ? (l - 3) / 2 + 1 : l / 2;
+    return l / 3 + (l % 3 ? 1 : 0);
+}
+constexpr int radix_at(int N, int s, int RS = 0) {
+    const int l = ilog2(N), rem = l % 3;
+    if (RS == 1) return (rem != 0 && s == 0) ? (rem == 1 ? 2 : 4) : 8;
+    if (RS == 2) return s < ((l % 2) ? (l - 3) / 2 : l / 2) ? 4 : 8;
+    return s < l / 3 ? 8 : (rem == 1 ? 2 : 4);
 }
 // Length of the sub-transforms already formed before stage s.
-constexpr int span_at(int N, int s) {
+constexpr int span_at(int N, int s, int RS = 0) {
     int L = 1;
-    for (int i = 0; i < s; ++i) L *= radix_at(N, i);
+    for (int i = 0; i < s; ++i) L *= radix_at(N, i, RS);
     return L;
 }
-// Offset of stage s in the twiddle table; stage s stores
+// Offset of stage s in the twiddle table of plan RS; stage s stores
 // span_at(N,s) * (radix_at(N,s) - 1) factors (stage 0 stores none).
-constexpr int tw_offset(int N, int s) {
+constexpr int tw_offset(int N, int s, int RS = 0) {
     int off = 0;
-    for (int i = 1; i < s; ++i) off += span_at(N, i) * (radix_at(N, i) - 1);
+    for (int i = 1; i < s; ++i) off += span_at(N, i, RS) * (radix_at(N, i, RS) - 1);
     return off;
 }
-constexpr int tw_size(int N) { return tw_offset(N, num_stages(N)); }
+constexpr int tw_size(int N, int RS = 0) { return tw_offset(N, num_stages(N, RS), RS); }
+// The tables of all plans are stored one after the other (plan 0 first).
+constexpr int tw_base(int N, int RS) {
+    int off = 0;
+    for (int r = 0; r < RS; ++r) off += tw_size(N, r);
+    return off;
+}
+constexpr int tw_total(int N) { return tw_base(N, NRS); }
+constexpr int tw_size_max(int N) {
+    int m = 0;
+    for (int r = 0; r < NRS; ++r) m = tw_size(N, r) > m ? tw_size(N, r) : m;
+    return m;
+}
+// Plan RS differs from every plan with a smaller index (else it adds nothing).
+constexpr bool radix_plan_new(int N, int RS) {
+    for (int r = 0; r < RS; ++r) {
+        bool same = num_stages(N, r) == num_stages(N, RS);
+        for (int s = 0; same && s < num_stages(N, RS); ++s) same = radix_at(N, s, r) == radix_at(N, s, RS);
+        if (same) return false;
+    }
+    return true;
+}
+constexpr bool radix_plan_valid(int N, int RS) {
+    int p = 1;
+    for (int s = 0; s < num_stages(N, RS); ++s) {
+        const int r = radix_at(N, s, RS);
+        if (r != 2 && r != 4 && r != 8) return false;
+        p *= r;
+    }
+    return p == N;
+}
+static_assert(radix_plan_valid(8, 0) && radix_plan_valid(16, 1) && radix_plan_valid(32, 2) &&
+                  radix_plan_valid(512, 2) && radix_plan_valid(1024, 1) && radix_plan_valid(1024, 2) &&
+                  radix_plan_valid(128, 2) && radix_plan_valid(256, 1),
+              "radix plans multiply to N");
 
 // ---------------------------------------------------------------------------
 // Internal layout of one half-spectrum field of an N^3 grid (complex values

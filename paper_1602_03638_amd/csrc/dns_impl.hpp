@@ -35,9 +35,9 @@ template <typename R, int N> struct Impl {
     }
     // The RHS/RK4 passes hold three lines plus state per thread: in FP64
     // their 1024-thread shapes (128 registers per thread) only spill.
-    template <int T> static constexpr bool xr_ok() {
+    template <int T, int RS = 0> static constexpr bool xr_ok() {
         return x_ok<T>() && (sizeof(R) == 4 || GX * T <= 512) &&
-               (size_t)T * N * CB + 2 * 8 * (size_t)GX * T + (size_t)tw_size(N) * CB <= LDS_LIMIT;
+               (size_t)T * N * CB + 2 * 8 * (size_t)GX * T + (size_t)tw_size(N, RS) * CB <= LDS_LIMIT;
     }
     // XCD-grouped tile order (x_tile): where an x tile's row segment is 32
     // or 64 bytes, from 256^3 up, with both tile counts multiples of 8 times
@@ -56,14 +56,15 @@ template <typename R, int N> struct Impl {
     }
     // y shapes with YE elements per thread; CURL: the vorticity-forming
     // inverse pass (twiddles in shared memory)
-    template <int T, int YE, bool CURL> static constexpr bool y_ok() {
+    template <int T, int YE, bool CURL, int RS = 0> static constexpr bool y_ok() {
         return YE >= 8 && N % YE == 0 && T <= N / 2 && (N / YE) * T <= 1024 &&
-               ((size_t)T * N + (y_twiddles_in_lds(YE) || CURL ? (size_t)tw_size(N) : 0)) * CB <= LDS_LIMIT;
+               ((size_t)T * N + (y_twiddles_in_lds(YE) || CURL ? (size_t)tw_size(N, RS) : 0)) * CB <= LDS_LIMIT;
     }
     // z shapes: at least 16 threads, and up to 128 threads for small N
-    template <int L> static constexpr bool z_ok() {
+    // (ZP: one LDS pad slot after every 2^ZP elements of a line, 0 = none)
+    template <int L, int ZP = 3, int RS = 0> static constexpr bool z_ok() {
         return L <= N * N && G * L <= 1024 && G * L >= 16 && L <= (128 / G > 8 ? 128 / G : 8) &&
-               (size_t)L * padded_line<N>(true) * CB + (size_t)tw_size(N) * CB <= LDS_LIMIT;
+               (size_t)L * padded_line<N>(ZP) * CB + (size_t)tw_size(N, RS) * CB <= LDS_LIMIT;
     }
     template <int T> static constexpr int x_groups() { return XCOLS / T + N / T; }
 
@@ -97,14 +98,14 @@ template <typename R, int N> struct Impl {
     static constexpr int XD = x_default_width();
 
     // ---- pass launchers ----------------------------------------------------
-    template <int T, bool CY, bool PAIR>
+    template <int T, bool CY, bool PAIR, int RS = 0>
     static void xinv(const void* U, void* W, const void* tw, const Batch& b, hipStream_t s) {
-        hipLaunchKernelGGL((k_xinv_curl<R, N, T, CY, PAIR>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0, s,
+        hipLaunchKernelGGL((k_xinv_curl<R, N, T, CY, PAIR, RS>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0, s,
                            (const C*)U, (C*)W, (const C*)tw, b.sst, b.wst);
     }
-    template <int T, int DIR, int NF, int YE, bool PAIR = false>
+    template <int T, int DIR, int NF, int YE, bool PAIR = false, int RS = 0>
     static void ypass(void* W, const void* tw, const Batch& b, hipStream_t s) {
-        hipLaunchKernelGGL((k_yline<R, N, T, DIR, NF, YE, PAIR>), dim3(y_tiles<R, N, T>(), b.members),
+        hipLaunchKernelGGL((k_yline<R, N, T, DIR, NF, YE, PAIR, RS>), dim3(y_tiles<R, N, T>(), b.members),
                            dim3((N / YE) * T), 0, s, (C*)W, (const C*)tw, b.wst);
     }
     template <int DIR, int NF, bool CURL>
@@ -116,60 +117,61 @@ template <typename R, int N> struct Impl {
     }
     // inverse y pass of a stage with the vorticity combinations formed from
     // the x pass's five outputs
-    template <int T, bool PAIR = false>
+    template <int T, bool PAIR = false, int RS = 0>
     static void yinv_curl(void* W, const void* tw, const Batch& b, hipStream_t s) {
-        hipLaunchKernelGGL((k_yinv_curl<R, N, T, PAIR>), dim3(y_tiles<R, N, T>(), b.members), dim3((N / 8) * T), 0,
+        hipLaunchKernelGGL((k_yinv_curl<R, N, T, PAIR, RS>), dim3(y_tiles<R, N, T>(), b.members), dim3((N / 8) * T), 0,
                            s, (C*)W, (const C*)tw, b.wst);
     }
-    template <int L> static void zcross(void* W, const void* tw, const Batch& b, hipStream_t s) {
+    template <int L, int ZP = 3, int RS = 0>
+    static void zcross(void* W, const void* tw, const Batch& b, hipStream_t s) {
         const R scale = (R)std::ldexp(1.0, -6 * ilog2(N));
-        hipLaunchKernelGGL((k_zcross<R, N, L>), dim3((N * N) / L, b.members), dim3(G * L), 0, s, (C*)W,
+        hipLaunchKernelGGL((k_zcross<R, N, L, ZP, RS>), dim3((N * N) / L, b.members), dim3(G * L), 0, s, (C*)W,
                            (const C*)tw, scale, b.wst);
     }
     // stages 3 and 4 (last of a step) have an instance with the fused
     // diagnostics, launched when a.diag is set
-    template <int T, bool PAIR, int ST>
+    template <int T, bool PAIR, int ST, int RS>
     static void xrhs_st(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
                         const Batch& b, hipStream_t s) {
         if (ST >= 3 && a.diag != nullptr)
-            hipLaunchKernelGGL((k_xrhs<R, N, T, ST, PAIR, ST >= 3>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0,
+            hipLaunchKernelGGL((k_xrhs<R, N, T, ST, PAIR, ST >= 3, RS>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0,
                                s, (const C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a, b.sst, b.wst);
         else
-            hipLaunchKernelGGL((k_xrhs<R, N, T, ST, PAIR, false>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0,
+            hipLaunchKernelGGL((k_xrhs<R, N, T, ST, PAIR, false, RS>), dim3(x_groups<T>(), b.members), dim3(GX * T), 0,
                                s, (const C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a, b.sst, b.wst);
     }
-    template <int T, bool PAIR>
+    template <int T, bool PAIR, int RS = 0>
     static void xrhs(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
                      const Batch& b, hipStream_t s) {
         switch (a.stage) {
-            case 0: xrhs_st<T, PAIR, 0>(W, U0, U1, Us, tw, a, b, s); break;
-            case 1: xrhs_st<T, PAIR, 1>(W, U0, U1, Us, tw, a, b, s); break;
-            case 2: xrhs_st<T, PAIR, 2>(W, U0, U1, Us, tw, a, b, s); break;
-            case 3: xrhs_st<T, PAIR, 3>(W, U0, U1, Us, tw, a, b, s); break;
-            case 4: xrhs_st<T, PAIR, 4>(W, U0, U1, Us, tw, a, b, s); break;
-            default: xrhs_st<T, PAIR, -1>(W, U0, U1, Us, tw, a, b, s); break;
+            case 0: xrhs_st<T, PAIR, 0, RS>(W, U0, U1, Us, tw, a, b, s); break;
+            case 1: xrhs_st<T, PAIR, 1, RS>(W, U0, U1, Us, tw, a, b, s); break;
+            case 2: xrhs_st<T, PAIR, 2, RS>(W, U0, U1, Us, tw, a, b, s); break;
+            case 3: xrhs_st<T, PAIR, 3, RS>(W, U0, U1, Us, tw, a, b, s); break;
+            case 4: xrhs_st<T, PAIR, 4, RS>(W, U0, U1, Us, tw, a, b, s); break;
+            default: xrhs_st<T, PAIR, -1, RS>(W, U0, U1, Us, tw, a, b, s); break;
         }
     }
 
-    template <int T, bool CY, bool PAIR, int ST>
+    template <int T, bool CY, bool PAIR, int ST, int RS>
     static void xstage_st(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
                           const Batch& b, hipStream_t s) {
         if (ST >= 3 && a.diag != nullptr)
-            hipLaunchKernelGGL((k_xstage<R, N, T, ST, CY, PAIR, ST >= 3>), dim3(x_groups<T>(), b.members),
+            hipLaunchKernelGGL((k_xstage<R, N, T, ST, CY, PAIR, ST >= 3, RS>), dim3(x_groups<T>(), b.members),
                                dim3(GX * T), 0, s, (C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a, b.sst, b.wst);
         else
-            hipLaunchKernelGGL((k_xstage<R, N, T, ST, CY, PAIR, false>), dim3(x_groups<T>(), b.members),
+            hipLaunchKernelGGL((k_xstage<R, N, T, ST, CY, PAIR, false, RS>), dim3(x_groups<T>(), b.members),
                                dim3(GX * T), 0, s, (C*)W, (C*)U0, (C*)U1, (C*)Us, (const C*)tw, a, b.sst, b.wst);
     }
-    template <int T, bool CY, bool PAIR>
+    template <int T, bool CY, bool PAIR, int RS = 0>
     static void xstage(const void* W, void* U0, void* U1, void* Us, const void* tw, const StageArgs& a,
                        const Batch& b, hipStream_t s) {
         switch (a.stage) {
-            case 0: xstage_st<T, CY, PAIR, 0>(W, U0, U1, Us, tw, a, b, s); break;
-            case 1: xstage_st<T, CY, PAIR, 1>(W, U0, U1, Us, tw, a, b, s); break;
-            case 2: xstage_st<T, CY, PAIR, 2>(W, U0, U1, Us, tw, a, b, s); break;
-            case 3: xstage_st<T, CY, PAIR, 3>(W, U0, U1, Us, tw, a, b, s); break;
-            default: xstage_st<T, CY, PAIR, 4>(W, U0, U1, Us, tw, a, b, s); break;
+            case 0: xstage_st<T, CY, PAIR, 0, RS>(W, U0, U1, Us, tw, a, b, s); break;
+            case 1: xstage_st<T, CY, PAIR, 1, RS>(W, U0, U1, Us, tw, a, b, s); break;
+            case 2: xstage_st<T, CY, PAIR, 2, RS>(W, U0, U1, Us, tw, a, b, s); break;
+            case 3: xstage_st<T, CY, PAIR, 3, RS>(W, U0, U1, Us, tw, a, b, s); break;
+            default: xstage_st<T, CY, PAIR, 4, RS>(W, U0, U1, Us, tw, a, b, s); break;
         }
     }
 
@@ -234,57 +236,82 @@ template <typename R, int N> struct Impl {
         return n;
     }
     // x passes of width T with curl placement CY and XCD pairing PAIR
-    template <int T, bool CY, bool PAIR> static void add_x(Ops& o) {
+    // (RS: radix plan; plans other than 0 only where they differ from 0)
+    template <int T, bool CY, bool PAIR, int RS = 0> static void add_x(Ops& o) {
         if constexpr (T > 16 && N > 64) return;    // wide tiles only for small N
         if constexpr (PAIR && !pair_ok<T>()) return;
+        if constexpr (RS != 0 && !radix_plan_new(N, RS)) return;
         if constexpr (x_ok<T>()) {
-            int& n = push(o, P_XINV, Variant{T, PAIR, 0, CY});
-            o.xinv[n++] = &xinv<T, CY, PAIR>;
+            int& n = push(o, P_XINV, Variant{T, PAIR, 0, CY, RS, 0});
+            o.xinv[n++] = &xinv<T, CY, PAIR, RS>;
         }
-        if constexpr (xr_ok<T>()) {
-            int& k = push(o, P_XSTAGE, Variant{T, PAIR, 0, CY});
-            o.xstage[k] = &xstage<T, CY, PAIR>;
+        if constexpr (xr_ok<T, RS>()) {
+            int& k = push(o, P_XSTAGE, Variant{T, PAIR, 0, CY, RS, 0});
+            o.xstage[k] = &xstage<T, CY, PAIR, RS>;
             o.xstage_groups[k++] = x_groups<T>();
         }
     }
     // the RHS pass alone (independent of the curl placement)
-    template <int T, bool PAIR> static void add_xr(Ops& o) {
+    template <int T, bool PAIR, int RS = 0> static void add_xr(Ops& o) {
         if constexpr (T > 16 && N > 64) return;
         if constexpr (PAIR && !pair_ok<T>()) return;
-        if constexpr (xr_ok<T>()) {
-            int& n = push(o, P_XRHS, Variant{T, PAIR, 0, -1});
-            o.xrhs[n] = &xrhs<T, PAIR>;
+        if constexpr (RS != 0 && !radix_plan_new(N, RS)) return;
+        if constexpr (xr_ok<T, RS>()) {
+            int& n = push(o, P_XRHS, Variant{T, PAIR, 0, -1, RS, 0});
+            o.xrhs[n] = &xrhs<T, PAIR, RS>;
             o.xrhs_groups[n++] = x_groups<T>();
         }
     }
     // inverse y pass forming the vorticity (curl in y, 8 per thread)
-    template <int T, bool PAIR = false> static void add_ycurl(Ops& o) {
+    template <int T, bool PAIR = false, int RS = 0> static void add_ycurl(Ops& o) {
         if constexpr (PAIR && !ypair_ok<T>()) return;
-        if constexpr (y_ok<T, 8, true>()) {
-            int& n = push(o, P_YINV6, Variant{T, PAIR, 8, 1});
-            o.yinv6[n++] = &yinv_curl<T, PAIR>;
+        if constexpr (RS != 0 && !radix_plan_new(N, RS)) return;
+        if constexpr (T > 0 && y_ok<T, 8, true, RS>()) {
+            int& n = push(o, P_YINV6, Variant{T, PAIR, 8, 1, RS, 0});
+            o.yinv6[n++] = &yinv_curl<T, PAIR, RS>;
         }
     }
     // inverse y pass of the six fields the x pass wrote (curl in x)
-    template <int T, int YE, bool PAIR = false> static void add_yinv(Ops& o) {
+    template <int T, int YE, bool PAIR = false, int RS = 0> static void add_yinv(Ops& o) {
         if constexpr (PAIR && !ypair_ok<T>()) return;
-        if constexpr (T > 0 && y_ok<T, YE, false>()) {
-            int& n = push(o, P_YINV6, Variant{T, PAIR, YE, 0});
-            o.yinv6[n++] = &ypass<T, +1, 6, YE, PAIR>;
+        if constexpr (RS != 0 && !radix_plan_new(N, RS)) return;
+        if constexpr (T > 0 && y_ok<T, YE, false, RS>()) {
+            int& n = push(o, P_YINV6, Variant{T, PAIR, YE, 0, RS, 0});
+            o.yinv6[n++] = &ypass<T, +1, 6, YE, PAIR, RS>;
         }
     }
-    template <int T, int YE, bool PAIR = false> static void add_yfwd(Ops& o) {
+    template <int T, int YE, bool PAIR = false, int RS = 0> static void add_yfwd(Ops& o) {
         if constexpr (PAIR && !ypair_ok<T>()) return;
-        if constexpr (T > 0 && y_ok<T, YE, false>()) {
-            int& n = push(o, P_YFWD3, Variant{T, PAIR, YE, -1});
-            o.yfwd3[n++] = &ypass<T, -1, 3, YE, PAIR>;
+        if constexpr (RS != 0 && !radix_plan_new(N, RS)) return;
+        if constexpr (T > 0 && y_ok<T, YE, false, RS>()) {
+            int& n = push(o, P_YFWD3, Variant{T, PAIR, YE, -1, RS, 0});
+            o.yfwd3[n++] = &ypass<T, -1, 3, YE, PAIR, RS>;
         }
     }
-    template <int L> static void add_z(Ops& o) {
-        if constexpr (z_ok<L>()) {
-            int& n = push(o, P_ZCROSS, Variant{L, 0, 0, -1});
-            o.zcross[n++] = &zcross<L>;
+    template <int L, int ZP = 3, int RS = 0> static void add_z(Ops& o) {
+        if constexpr (RS != 0 && !radix_plan_new(N, RS)) return;
+        if constexpr (z_ok<L, ZP, RS>()) {
+            int& n = push(o, P_ZCROSS, Variant{L, 0, 0, -1, RS, ZP ? 1 << ZP : 0});
+            o.zcross[n++] = &zcross<L, ZP, RS>;
         }
+    }
+    // The default shape of every pass (as make() picks it) with radix plan RS.
+    static constexpr int ZD = (N >= 1024 ? 1 : (N == 256 ? 8 : 4)) > 64 / G ? (N >= 1024 ? 1 : (N == 256 ? 8 : 4))
+                                                                              : 64 / G;
+    static constexpr int YEF = (std::is_same_v<R, float> && N == 512) ? 16 : YE0;
+    template <int RS> static void add_radix_plan(Ops& o) {
+        constexpr bool XP = N >= 1024 && pair_ok<XD>();
+        add_x<XD, CY0, XP, RS>(o);
+        add_xr<XD, XP, RS>(o);
+        if constexpr (CY0) add_ycurl<y_default_width<8>(), false, RS>(o);
+        else add_yinv<y_default_width<YE0>(), YE0, false, RS>(o);
+        add_yfwd<y_default_width<YEF>(), YEF, false, RS>(o);
+        add_z<ZD, 3, RS>(o);
+    }
+    // Radix plan 0 and the standard z-pass pad: the variants a default or
+    // reproducible plan is made of.
+    static bool reference_shape(int p, const Variant& d) {
+        return d.rs == 0 && d.pad == (p == P_ZCROSS ? 8 : 0);
     }
     static int threads_per_line(int p, const Variant& d) {
         if (p == P_YINV6 || p == P_YFWD3) return N / d.ye;
@@ -298,6 +325,7 @@ template <typename R, int N> struct Impl {
         int best = -1;
         for (int v = 0; v < o.nvar[p]; ++v) {
             const Variant& d = o.var[p][v];
+            if (!reference_shape(p, d)) continue;
             if (d.width > w || threads_per_line(p, d) * d.width > MAXT) continue;
             if (d.cy >= 0 && d.cy != cy) continue;
             if (d.ye > 0 && !(p == P_YINV6 && cy == 1) && d.ye != ye) continue;
@@ -312,7 +340,8 @@ template <typename R, int N> struct Impl {
         o.N = N;
         o.real_size = sizeof(R);
         o.fs = Lay<R, N>::FS;
-        o.tw_count = tw_size(N) > 0 ? tw_size(N) : 1;
+        o.tw_count = tw_total(N) > 0 ? tw_total(N) : 1;
+        for (int r = 0; r < NRS; ++r) o.tw_base[r] = tw_base(N, r);
         if constexpr (CY0) {
             // below 1024: the vorticity in the y pass at every width; the
             // six-field x pass (curl in x) at the default width, with the
@@ -346,6 +375,13 @@ template <typename R, int N> struct Impl {
         add_xr<4, true>(o); add_xr<8, true>(o);
         add_z<1>(o); add_z<2>(o); add_z<4>(o); add_z<8>(o);
         add_z<16>(o); add_z<32>(o); add_z<64>(o); add_z<128>(o);
+        // LDS pad of the z pass at its default width: none, every 4 and
+        // every 16 elements (bitwise neutral: only shared-memory addresses)
+        add_z<ZD, 0>(o); add_z<ZD, 2>(o); add_z<ZD, 4>(o);
+        // the other radix plans at the default shapes (not bitwise
+        // identical to plan 0: chosen only by a tuning in fastest mode)
+        add_radix_plan<1>(o);
+        add_radix_plan<2>(o);
         // defaults, the fastest measured on MI355X at 256^3, 512^3 and
         // 1024^3: 128-byte row segments in the x and y passes, four z lines
         // per workgroup (eight for N = 256, one for N = 1024); for small N,

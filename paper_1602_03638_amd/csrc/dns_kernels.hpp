@@ -106,7 +106,7 @@ template <int N, int T> constexpr int x_main_tiles() { return (N * (N / 2)) / T;
 // ---------------------------------------------------------------------------
 // Inverse x transforms of the velocity held in v[3] (x-spectral), written to
 // W as above.  Shared by the first stage's pass and the fused stage pass.
-template <typename R, int N, int T, bool NYQ, bool CY>
+template <typename R, int N, int T, bool NYQ, bool CY, int RS = 0>
 __device__ __forceinline__ void xinv_curl_store(cx<R> (&v)[3][x_elems<R>(N)],
                                                 cx<R>* __restrict__ W, const XAddr<R, N, NYQ>& A, cx<R>* lt,
                                                 const cx<R>* twl, int g, int iky, int ikz) {
@@ -116,25 +116,25 @@ __device__ __forceinline__ void xinv_curl_store(cx<R> (&v)[3][x_elems<R>(N)],
         // the six fields u, v, w, omega (combinations formed here)
         const R ky = (R)iky, kz = (R)ikz;
         cx<R> b[E];
-        fft_line<R, N, E, +1, true>(v[0], lt, T, twl, g);        // U
+        fft_line<R, N, E, +1, true, 0, RS>(v[0], lt, T, twl, g);        // U
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             A(W, m) = v[0][m];
             b[m] = cscale<R>(v[1][m], (R)kfreq(g + m * G, N));
         }
-        fft_line<R, N, E, +1, true>(b, lt, T, twl, g);           // F(kx v_hat)
+        fft_line<R, N, E, +1, true, 0, RS>(b, lt, T, twl, g);           // F(kx v_hat)
 #pragma unroll
         for (int m = 0; m < E; ++m) A(W + 5 * FS, m) = cmuli<R>(csub<R>(b[m], cscale<R>(v[0][m], ky)));
-        fft_line<R, N, E, +1, true>(v[1], lt, T, twl, g);        // V
+        fft_line<R, N, E, +1, true, 0, RS>(v[1], lt, T, twl, g);        // V
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             A(W + FS, m) = v[1][m];
             b[m] = cscale<R>(v[2][m], (R)kfreq(g + m * G, N));
         }
-        fft_line<R, N, E, +1, true>(b, lt, T, twl, g);           // F(kx w_hat)
+        fft_line<R, N, E, +1, true, 0, RS>(b, lt, T, twl, g);           // F(kx w_hat)
 #pragma unroll
         for (int m = 0; m < E; ++m) A(W + 4 * FS, m) = cmuli<R>(csub<R>(cscale<R>(v[0][m], kz), b[m]));
-        fft_line<R, N, E, +1, true>(v[2], lt, T, twl, g);        // W
+        fft_line<R, N, E, +1, true, 0, RS>(v[2], lt, T, twl, g);        // W
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             A(W + 2 * FS, m) = v[2][m];
@@ -145,29 +145,29 @@ __device__ __forceinline__ void xinv_curl_store(cx<R> (&v)[3][x_elems<R>(N)],
     // at most three lines live: U is transformed and stored before the
     // first kx product is formed
     cx<R> b[E];
-    fft_line<R, N, E, +1, true>(v[0], lt, T, twl, g);            // U
+    fft_line<R, N, E, +1, true, 0, RS>(v[0], lt, T, twl, g);            // U
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         A(W, m) = v[0][m];
         b[m] = cscale<R>(v[1][m], (R)kfreq(g + m * G, N));
     }
-    fft_line<R, N, E, +1, true>(b, lt, T, twl, g);               // F(kx v_hat)
+    fft_line<R, N, E, +1, true, 0, RS>(b, lt, T, twl, g);               // F(kx v_hat)
 #pragma unroll
     for (int m = 0; m < E; ++m) A(W + 3 * FS, m) = b[m];
-    fft_line<R, N, E, +1, true>(v[1], lt, T, twl, g);            // V
+    fft_line<R, N, E, +1, true, 0, RS>(v[1], lt, T, twl, g);            // V
 #pragma unroll
     for (int m = 0; m < E; ++m) A(W + FS, m) = v[1][m];
 #pragma unroll
     for (int m = 0; m < E; ++m) b[m] = cscale<R>(v[2][m], (R)kfreq(g + m * G, N));
-    fft_line<R, N, E, +1, true>(b, lt, T, twl, g);               // F(kx w_hat)
+    fft_line<R, N, E, +1, true, 0, RS>(b, lt, T, twl, g);               // F(kx w_hat)
 #pragma unroll
     for (int m = 0; m < E; ++m) A(W + 4 * FS, m) = b[m];
-    fft_line<R, N, E, +1, true>(v[2], lt, T, twl, g);            // W
+    fft_line<R, N, E, +1, true, 0, RS>(v[2], lt, T, twl, g);            // W
 #pragma unroll
     for (int m = 0; m < E; ++m) A(W + 2 * FS, m) = v[2][m];
 }
 
-template <typename R, int N, int T, bool NYQ, bool CY>
+template <typename R, int N, int T, bool NYQ, bool CY, int RS = 0>
 __device__ __forceinline__ void xinv_curl_tile(const cx<R>* __restrict__ U, cx<R>* __restrict__ W,
                                                cx<R>* lds, const cx<R>* twl, int tile) {
     constexpr int E = x_elems<R>(N), G = N / E;
@@ -180,21 +180,21 @@ __device__ __forceinline__ void xinv_curl_tile(const cx<R>* __restrict__ U, cx<R
     for (int f = 0; f < 3; ++f)
 #pragma unroll
         for (int m = 0; m < E; ++m) v[f][m] = A(U + f * FS, m);
-    xinv_curl_store<R, N, T, NYQ, CY>(v, W, A, lds + t, twl, g, col.ky, col.kz);
+    xinv_curl_store<R, N, T, NYQ, CY, RS>(v, W, A, lds + t, twl, g, col.ky, col.kz);
 }
 
-template <typename R, int N, int T, bool CY, bool PAIR>
+template <typename R, int N, int T, bool CY, bool PAIR, int RS = 0>
 __global__ __launch_bounds__(N / x_elems<R>(N) * T)
 void k_xinv_curl(const cx<R>* __restrict__ U, cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t sst,
                  size_t wst) {
     U += blockIdx.y * sst;
     W += blockIdx.y * wst;
     __shared__ cx<R> lds[T * N];
-    __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
-    load_twiddles<R, N>(twl, tw);
+    __shared__ cx<R> twl[tw_size(N, RS) > 0 ? tw_size(N, RS) : 1];
+    load_twiddles<R, N, RS>(twl, tw);
     const int tile = x_tile<PAIR ? line_group<R, T>() : 1>((int)blockIdx.x, x_main_tiles<N, T>());
-    if (tile < x_main_tiles<N, T>()) xinv_curl_tile<R, N, T, false, CY>(U, W, lds, twl, tile);
-    else xinv_curl_tile<R, N, T, true, CY>(U, W, lds, twl, tile);
+    if (tile < x_main_tiles<N, T>()) xinv_curl_tile<R, N, T, false, CY, RS>(U, W, lds, twl, tile);
+    else xinv_curl_tile<R, N, T, true, CY, RS>(U, W, lds, twl, tile);
 }
 
 // Plain inverse (DIR = +1) or forward (DIR = -1) x transform of NF fields
@@ -287,7 +287,7 @@ template <typename R, int N, int T, bool NYQ, int YE> struct YTile {
 static_assert((size_t)Lay<double, 1024>::XP * sizeof(double2) < (size_t(1) << 32),
               "y-tile byte offsets within a plane must fit 32 bits");
 
-template <typename R, int N, int T, int DIR, int NF, bool NYQ, int YE>
+template <typename R, int N, int T, int DIR, int NF, bool NYQ, int YE, int RS = 0>
 __device__ __forceinline__ void yline_tile(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, cx<R>* lds,
                                            int tile) {
     using Y = YTile<R, N, T, NYQ, YE>;
@@ -305,7 +305,7 @@ __device__ __forceinline__ void yline_tile(cx<R>* __restrict__ W, const cx<R>* _
         cx<R> a[E];
 #pragma unroll
         for (int m = 0; m < E; ++m) a[m] = y.template el<NT>(F, m);
-        fft_line<R, N, E, DIR, TWL>(a, lds + y.lo, Y::PS, tw, y.g);
+        fft_line<R, N, E, DIR, TWL, 0, RS>(a, lds + y.lo, Y::PS, tw, y.g);
 #pragma unroll
         for (int m = 0; m < E; ++m) y.template el<NT>(F, m) = a[m];
     }
@@ -321,7 +321,7 @@ __device__ __forceinline__ void yline_tile(cx<R>* __restrict__ W, const cx<R>* _
 // are no longer needed: omega_z -> field 5, omega_y -> 4, u -> 0,
 // omega_x -> 3, v -> 1, w -> 2 (each thread reads and writes only its own
 // elements).
-template <typename R, int N, int T, bool NYQ>
+template <typename R, int N, int T, bool NYQ, int RS = 0>
 __device__ __forceinline__ void yinv_curl_tile(cx<R>* __restrict__ W, const cx<R>* twl, cx<R>* lds, int tile) {
     using Y = YTile<R, N, T, NYQ, 8>;
     constexpr int E = Y::E, G = Y::G;
@@ -340,7 +340,7 @@ __device__ __forceinline__ void yinv_curl_tile(cx<R>* __restrict__ W, const cx<R
     }
 #pragma unroll
     for (int m = 0; m < E; ++m) a[m] = cmuli<R>(csub<R>(a[m], cscale<R>(u[m], (R)kfreq(y.g + m * G, N))));
-    fft_line<R, N, E, +1, TWL>(a, lt, Y::PS, tw, y.g);                    // omega_z
+    fft_line<R, N, E, +1, TWL, 0, RS>(a, lt, Y::PS, tw, y.g);                    // omega_z
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         y.el(F5, m) = a[m];
@@ -348,26 +348,26 @@ __device__ __forceinline__ void yinv_curl_tile(cx<R>* __restrict__ W, const cx<R
     }
 #pragma unroll
     for (int m = 0; m < E; ++m) a[m] = cmuli<R>(csub<R>(cscale<R>(u[m], kz), a[m]));
-    fft_line<R, N, E, +1, TWL>(a, lt, Y::PS, tw, y.g);                    // omega_y
+    fft_line<R, N, E, +1, TWL, 0, RS>(a, lt, Y::PS, tw, y.g);                    // omega_y
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         y.el(F4, m) = a[m];
         a[m] = y.el(F1, m);
         b[m] = y.el(F2, m);
     }
-    fft_line<R, N, E, +1, TWL>(u, lt, Y::PS, tw, y.g);                    // u
+    fft_line<R, N, E, +1, TWL, 0, RS>(u, lt, Y::PS, tw, y.g);                    // u
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         y.el(W, m) = u[m];
         u[m] = cmuli<R>(csub<R>(cscale<R>(b[m], (R)kfreq(y.g + m * G, N)), cscale<R>(a[m], kz)));
     }
-    fft_line<R, N, E, +1, TWL>(u, lt, Y::PS, tw, y.g);                    // omega_x
+    fft_line<R, N, E, +1, TWL, 0, RS>(u, lt, Y::PS, tw, y.g);                    // omega_x
 #pragma unroll
     for (int m = 0; m < E; ++m) y.el(F3, m) = u[m];
-    fft_line<R, N, E, +1, TWL>(a, lt, Y::PS, tw, y.g);                    // v
+    fft_line<R, N, E, +1, TWL, 0, RS>(a, lt, Y::PS, tw, y.g);                    // v
 #pragma unroll
     for (int m = 0; m < E; ++m) y.el(F1, m) = a[m];
-    fft_line<R, N, E, +1, TWL>(b, lt, Y::PS, tw, y.g);                    // w
+    fft_line<R, N, E, +1, TWL, 0, RS>(b, lt, Y::PS, tw, y.g);                    // w
 #pragma unroll
     for (int m = 0; m < E; ++m) y.el(F2, m) = b[m];
 }
@@ -377,33 +377,33 @@ template <typename R, int N, int T> constexpr int y_tiles() { return y_main_tile
 
 // PAIR: the tiles of one 128-byte line (rows shorter than 128 bytes) go to
 // workgroups of one XCD, as in the x passes (x_tile).
-template <typename R, int N, int T, int DIR, int NF, int YE, bool PAIR = false>
+template <typename R, int N, int T, int DIR, int NF, int YE, bool PAIR = false, int RS = 0>
 __global__ __launch_bounds__(N / YE * T)
 void k_yline(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
     W += blockIdx.y * wst;
     __shared__ cx<R> lds[T * N];
     constexpr bool TWL = y_twiddles_in_lds(YE);
-    __shared__ cx<R> twl[TWL ? tw_size(N) : 1];
+    __shared__ cx<R> twl[TWL && tw_size(N, RS) > 0 ? tw_size(N, RS) : 1];
     const cx<R>* t = tw;
     if constexpr (TWL) {
-        load_twiddles<R, N>(twl, tw);
+        load_twiddles<R, N, RS>(twl, tw);
         t = twl;
     }
     const int b = x_tile<PAIR ? line_group<R, T>() : 1>((int)blockIdx.x, y_main_tiles<R, N, T>());
-    if (b < y_main_tiles<R, N, T>()) yline_tile<R, N, T, DIR, NF, false, YE>(W, t, lds, b);
-    else yline_tile<R, N, T, DIR, NF, true, YE>(W, t, lds, b - y_main_tiles<R, N, T>());
+    if (b < y_main_tiles<R, N, T>()) yline_tile<R, N, T, DIR, NF, false, YE, RS>(W, t, lds, b);
+    else yline_tile<R, N, T, DIR, NF, true, YE, RS>(W, t, lds, b - y_main_tiles<R, N, T>());
 }
 
-template <typename R, int N, int T, bool PAIR = false>
+template <typename R, int N, int T, bool PAIR = false, int RS = 0>
 __global__ __launch_bounds__(N / 8 * T)
 void k_yinv_curl(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, size_t wst) {
     W += blockIdx.y * wst;
     __shared__ cx<R> lds[T * N];
-    __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
-    load_twiddles<R, N>(twl, tw);
+    __shared__ cx<R> twl[tw_size(N, RS) > 0 ? tw_size(N, RS) : 1];
+    load_twiddles<R, N, RS>(twl, tw);
     const int b = x_tile<PAIR ? line_group<R, T>() : 1>((int)blockIdx.x, y_main_tiles<R, N, T>());
-    if (b < y_main_tiles<R, N, T>()) yinv_curl_tile<R, N, T, false>(W, twl, lds, b);
-    else yinv_curl_tile<R, N, T, true>(W, twl, lds, b - y_main_tiles<R, N, T>());
+    if (b < y_main_tiles<R, N, T>()) yinv_curl_tile<R, N, T, false, RS>(W, twl, lds, b);
+    else yinv_curl_tile<R, N, T, true, RS>(W, twl, lds, b - y_main_tiles<R, N, T>());
 }
 
 // Load element k (0 <= k < N) of the Hermitian extension of a half-spectrum
@@ -453,16 +453,16 @@ __device__ __forceinline__ void zsplit(cx<R> pk, cx<R> pnk, cx<R>& A, cx<R>& B) 
 // spectra of c into fields 0..2 of W (in place: a workgroup owns its lines).
 // scale = N^-6 (exact power of two) restores the inverse transforms' 1/N^3.
 // ---------------------------------------------------------------------------
-template <typename R, int N, int L>
+template <typename R, int N, int L, int ZP = 3, int RS = 0>
 __global__ __launch_bounds__(N / 8 * L)
 void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale, size_t wst) {
     W += blockIdx.y * wst;
     constexpr int E = 8, G = N / E;
     constexpr size_t FS = Lay<R, N>::FS;
-    constexpr int LP = padded_line<N>(true);
+    constexpr int LP = padded_line<N>(ZP);
     constexpr bool SIO = stream_io<R>(N);
     __shared__ cx<R> lds[L * LP];
-    __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
+    __shared__ cx<R> twl[tw_size(N, RS) > 0 ? tw_size(N, RS) : 1];
     const int g = threadIdx.x % G, l = threadIdx.x / G;
     const size_t line = (size_t)blockIdx.x * L + l;
     const size_t zr = Lay<R, N>::row(line);   // start of the line's iz row
@@ -488,7 +488,7 @@ void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale, size
             yn[p] = gload<cx<R>, SIO>(FY + NQ + line);
         }
     }
-    load_twiddles<R, N>(twl, tw);
+    load_twiddles<R, N, RS>(twl, tw);
     cx<R> z[3][E];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
@@ -509,7 +509,7 @@ void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale, size
         __syncthreads();
     }
 #pragma unroll
-    for (int p = 0; p < 3; ++p) fft_line<R, N, E, +1, true, true>(z[p], my, 1, twl, g);
+    for (int p = 0; p < 3; ++p) fft_line<R, N, E, +1, true, ZP, RS>(z[p], my, 1, twl, g);
     // z[0] = (u, v), z[1] = (w, omega_x), z[2] = (omega_y, omega_z)
     cx<R> P[E], Q[E];
 #pragma unroll
@@ -519,8 +519,8 @@ void k_zcross(cx<R>* __restrict__ W, const cx<R>* __restrict__ tw, R scale, size
         P[m] = {(v * oz - w * oy) * scale, (w * ox - u * oz) * scale};
         Q[m] = {(u * oy - v * ox) * scale, R(0)};
     }
-    fft_line<R, N, E, -1, true, true>(Q, my, 1, twl, g);
-    fft_line<R, N, E, -1, true, true>(P, my, 1, twl, g);
+    fft_line<R, N, E, -1, true, ZP, RS>(Q, my, 1, twl, g);
+    fft_line<R, N, E, -1, true, ZP, RS>(P, my, 1, twl, g);
     // c2: Q_k is its half spectrum directly
 #pragma unroll
     for (int m = 0; m < E / 2; ++m) gstore<cx<R>, SIO>(W + 2 * FS + zr + g + m * G, Q[m]);
@@ -553,7 +553,7 @@ void k_zr2c(const R* __restrict__ u, cx<R>* __restrict__ W, const cx<R>* __restr
     constexpr int E = 8, G = N / E;
     constexpr size_t FS = Lay<R, N>::FS;
     constexpr size_t PS = (size_t)N * N * N;
-    constexpr int LP = padded_line<N>(true);
+    constexpr int LP = padded_line<N>(3);
     __shared__ cx<R> lds[L * LP];
     const int g = threadIdx.x % G, l = threadIdx.x / G;
     const size_t line = (size_t)blockIdx.x * L + l;
@@ -567,8 +567,8 @@ void k_zr2c(const R* __restrict__ u, cx<R>* __restrict__ W, const cx<R>* __restr
         P[m] = {u[o], u[PS + o]};
         Q[m] = {u[2 * PS + o], R(0)};
     }
-    fft_line<R, N, E, -1, false, true>(Q, my, 1, tw, g);
-    fft_line<R, N, E, -1, false, true>(P, my, 1, tw, g);
+    fft_line<R, N, E, -1, false, 3>(Q, my, 1, tw, g);
+    fft_line<R, N, E, -1, false, 3>(P, my, 1, tw, g);
 #pragma unroll
     for (int m = 0; m < E / 2; ++m) W[2 * FS + zr + g + m * G] = Q[m];
     if (g == 0) W[2 * FS + NQ + line] = Q[E / 2];
@@ -599,7 +599,7 @@ void k_zc2r(const cx<R>* __restrict__ W, R* __restrict__ u, const cx<R>* __restr
     constexpr int E = 8, G = N / E;
     constexpr size_t FS = Lay<R, N>::FS;
     constexpr size_t PS = (size_t)N * N * N;
-    constexpr int LP = padded_line<N>(true);
+    constexpr int LP = padded_line<N>(3);
     __shared__ cx<R> lds[L * LP];
     const int g = threadIdx.x % G, l = threadIdx.x / G;
     const size_t line = (size_t)blockIdx.x * L + l;
@@ -610,8 +610,8 @@ void k_zc2r(const cx<R>* __restrict__ W, R* __restrict__ u, const cx<R>* __restr
         a[m] = zpair_load<R, N>(W, W + FS, line, g + m * G);
         b[m] = zline_load<R, N>(W + 2 * FS, line, g + m * G);
     }
-    fft_line<R, N, E, +1, false, true>(a, my, 1, tw, g);
-    fft_line<R, N, E, +1, false, true>(b, my, 1, tw, g);
+    fft_line<R, N, E, +1, false, 3>(a, my, 1, tw, g);
+    fft_line<R, N, E, +1, false, 3>(b, my, 1, tw, g);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const size_t o = line * N + g + m * G;
@@ -877,7 +877,7 @@ __device__ __forceinline__ void diag_reduce(double (&red)[2][NT], double e_acc, 
     }
 }
 
-template <typename R, int N, int T, int STAGE, bool NYQ, bool DIAG>
+template <typename R, int N, int T, int STAGE, bool NYQ, bool DIAG, int RS = 0>
 __device__ __forceinline__ void xrhs_tile(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
                                           cx<R>* __restrict__ Us, const StageArgs& sa, cx<R>* lds, const cx<R>* twl,
                                           double (&red)[2][DIAG ? N / x_elems<R>(N) * T : 1], int tile) {
@@ -892,7 +892,7 @@ __device__ __forceinline__ void xrhs_tile(const cx<R>* __restrict__ W, cx<R>* __
 #pragma unroll
         for (int m = 0; m < E; ++m) nh[f][m] = XAddr<R, N, NYQ>(col, g)(W + f * FS, m);
 #pragma unroll
-    for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true>(nh[f], lds + t, T, twl, g);
+    for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true, 0, RS>(nh[f], lds + t, T, twl, g);
     double e_acc = 0.0, w_acc = 0.0;
     rk_apply_stage<R, N, E, STAGE, NYQ, NT, DIAG>(nh, col, g, U0, U1, Us, sa, e_acc, w_acc);
     if constexpr (STAGE >= 3 && DIAG) diag_reduce<NT>(red, e_acc, w_acc, sa.diag, tile);
@@ -900,7 +900,7 @@ __device__ __forceinline__ void xrhs_tile(const cx<R>* __restrict__ W, cx<R>* __
 
 // The RK stage is a template parameter: one kernel per stage gives each
 // its own straight-line code and register allocation.
-template <typename R, int N, int T, int STAGE, bool PAIR, bool DIAG>
+template <typename R, int N, int T, int STAGE, bool PAIR, bool DIAG, int RS = 0>
 __global__ __launch_bounds__(N / x_elems<R>(N) * T)
 void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
             cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa, size_t sst, size_t wst) {
@@ -911,11 +911,13 @@ void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restri
     if (sa.diag) sa.diag += 2 * (size_t)gridDim.x * blockIdx.y;
     __shared__ cx<R> lds[T * N];
     __shared__ double red[2][DIAG ? N / x_elems<R>(N) * T : 1];
-    __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
-    load_twiddles<R, N>(twl, tw);
+    __shared__ cx<R> twl[tw_size(N, RS) > 0 ? tw_size(N, RS) : 1];
+    load_twiddles<R, N, RS>(twl, tw);
     const int tile = x_tile<PAIR ? line_group<R, T>() : 1>((int)blockIdx.x, x_main_tiles<N, T>());
-    if (tile < x_main_tiles<N, T>()) xrhs_tile<R, N, T, STAGE, false, DIAG>(W, U0, U1, Us, sa, lds, twl, red, tile);
-    else xrhs_tile<R, N, T, STAGE, true, DIAG>(W, U0, U1, Us, sa, lds, twl, red, tile);
+    if (tile < x_main_tiles<N, T>())
+        xrhs_tile<R, N, T, STAGE, false, DIAG, RS>(W, U0, U1, Us, sa, lds, twl, red, tile);
+    else
+        xrhs_tile<R, N, T, STAGE, true, DIAG, RS>(W, U0, U1, Us, sa, lds, twl, red, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -927,7 +929,7 @@ void k_xrhs(const cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restri
 // before fields 0..4 are written; a workgroup owns its columns, so this is
 // safe in place.
 // ---------------------------------------------------------------------------
-template <typename R, int N, int T, int STAGE, bool NYQ, bool CY, bool DIAG>
+template <typename R, int N, int T, int STAGE, bool NYQ, bool CY, bool DIAG, int RS = 0>
 __device__ __forceinline__ void xstage_tile(cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
                                             cx<R>* __restrict__ Us, const StageArgs& sa, cx<R>* lds,
                                             const cx<R>* twl, double (&red)[2][DIAG ? N / x_elems<R>(N) * T : 1],
@@ -946,16 +948,16 @@ __device__ __forceinline__ void xstage_tile(cx<R>* __restrict__ W, cx<R>* __rest
         for (int m = 0; m < E; ++m) u[f][m] = A(W + f * FS, m);
     cx<R>* lt = lds + t;
 #pragma unroll
-    for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true>(u[f], lt, T, twl, g);
+    for (int f = 0; f < 3; ++f) fft_line<R, N, E, -1, true, 0, RS>(u[f], lt, T, twl, g);
     double e_acc = 0.0, w_acc = 0.0;
     rk_apply_stage<R, N, E, STAGE, NYQ, NT, DIAG>(u, col, g, U0, U1, Us, sa, e_acc, w_acc);
     if constexpr (STAGE >= 3 && DIAG) diag_reduce<NT>(red, e_acc, w_acc, sa.diag, tile);
 
     // inverse x transforms for the next stage's velocity and vorticity
-    xinv_curl_store<R, N, T, NYQ, CY>(u, W, A, lt, twl, g, col.ky, col.kz);
+    xinv_curl_store<R, N, T, NYQ, CY, RS>(u, W, A, lt, twl, g, col.ky, col.kz);
 }
 
-template <typename R, int N, int T, int STAGE, bool CY, bool PAIR, bool DIAG>
+template <typename R, int N, int T, int STAGE, bool CY, bool PAIR, bool DIAG, int RS = 0>
 __global__ __launch_bounds__(N / x_elems<R>(N) * T)
 void k_xstage(cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__ U1,
               cx<R>* __restrict__ Us, const cx<R>* __restrict__ tw, StageArgs sa, size_t sst, size_t wst) {
@@ -966,13 +968,13 @@ void k_xstage(cx<R>* __restrict__ W, cx<R>* __restrict__ U0, cx<R>* __restrict__
     if (sa.diag) sa.diag += 2 * (size_t)gridDim.x * blockIdx.y;
     __shared__ cx<R> lds[T * N];
     __shared__ double red[2][DIAG ? N / x_elems<R>(N) * T : 1];
-    __shared__ cx<R> twl[tw_size(N) > 0 ? tw_size(N) : 1];
-    load_twiddles<R, N>(twl, tw);
+    __shared__ cx<R> twl[tw_size(N, RS) > 0 ? tw_size(N, RS) : 1];
+    load_twiddles<R, N, RS>(twl, tw);
     const int tile = x_tile<PAIR ? line_group<R, T>() : 1>((int)blockIdx.x, x_main_tiles<N, T>());
     if (tile < x_main_tiles<N, T>())
-        xstage_tile<R, N, T, STAGE, false, CY, DIAG>(W, U0, U1, Us, sa, lds, twl, red, tile);
+        xstage_tile<R, N, T, STAGE, false, CY, DIAG, RS>(W, U0, U1, Us, sa, lds, twl, red, tile);
     else
-        xstage_tile<R, N, T, STAGE, true, CY, DIAG>(W, U0, U1, Us, sa, lds, twl, red, tile);
+        xstage_tile<R, N, T, STAGE, true, CY, DIAG, RS>(W, U0, U1, Us, sa, lds, twl, red, tile);
 }
 
 // ---------------------------------------------------------------------------

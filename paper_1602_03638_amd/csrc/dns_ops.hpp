@@ -1,16 +1,18 @@
 // Host-side launch table of the kernels for one (real type, N) pair, with
-// the variants the autotuner chooses between.  Every variant of a pass runs
-// the same per-line arithmetic, so all variants give bitwise identical
-// results; they differ in how many lines share a workgroup (width), in the
-// order in which workgroups take tiles (XCD pairing), in how many elements a
-// y-pass thread holds, and in which kernel forms the vorticity combinations.
+// the variants the autotuner chooses between.  The variants of radix plan 0
+// run the same per-line arithmetic, so they give bitwise identical results;
+// they differ in how many lines share a workgroup (width), in the order in
+// which workgroups take tiles (XCD pairing), in how many elements a y-pass
+// thread holds, in which kernel forms the vorticity combinations, and in the
+// shared-memory padding of the z pass.  Variants of another radix plan
+// compute the same transforms with other rounding.
 #pragma once
 
 #include "dns_common.hpp"
 
 namespace dns {
 
-constexpr int MAXV = 16;   // variants per pass
+constexpr int MAXV = 24;   // variants per pass
 
 // Descriptor of one variant of a pass.
 struct Variant {
@@ -19,6 +21,9 @@ struct Variant {
     int ye;      // y passes: complex values per thread (8, 16, 32); 0 for other passes
     int cy;      // 1: vorticity formed in the inverse y pass (five x-pass fields), 0: in the
                  // x pass (six fields); -1 for passes that do not depend on it
+    int rs;      // radix plan of the line transforms (radix_at; 0 = the reference plan)
+    int pad;     // z pass: one shared-memory pad slot after every `pad` elements of a
+                 // line (0 = none; 8 by default); 0 for other passes
 };
 
 // The kernels of a stage: the inverse x pass with the curl (first stage
@@ -41,7 +46,8 @@ struct Ops {
     int N;
     size_t real_size;      // bytes of one real value
     size_t fs;             // complex values of one field in the internal layout
-    int tw_count;          // complex entries of the twiddle table
+    int tw_count;          // complex entries of the twiddle tables (all radix plans)
+    int tw_base[NRS];      // first entry of radix plan r's table
     // variants of the passes of one RK4 stage; var[p][v] describes variant v
     // of pass p
     int nvar[P_COUNT];
@@ -80,9 +86,9 @@ template <typename R, int N> const Ops* ops_table();
 const Ops* ops_f64(int N);
 const Ops* ops_f32(int N);
 
-// Twiddle table of the length-N plan (forward direction), long-double
-// accurate, rounded to double.
-void make_twiddles(int N, double* re_im);
+// Twiddle table of the length-N transform with radix plan rs (forward
+// direction), long-double accurate, rounded to double.
+void make_twiddles(int N, double* re_im, int rs = 0);
 
 void launch_diag_final(const double* part, int nparts, double inv_norm, double* out,
                        double* hist, int* count, int cap, hipStream_t s);

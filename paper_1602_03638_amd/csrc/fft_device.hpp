@@ -90,20 +90,22 @@ template <typename R, int RAD, int DIR> __device__ __forceinline__ void dft_smal
 // stage (keeps it out of registers, which matters where a kernel holds
 // several lines per thread); otherwise it is read from global memory and
 // the compiler may keep it in registers across transforms.
-// PAD: element p of a contiguous line (ps = 1) is stored at p + p/8, so that
-// the stride-8 Stockham writes of 16-byte elements spread over all banks.
-template <int N> constexpr int padded_line(bool pad) { return pad ? N + N / 8 : N; }
-template <bool PAD> __device__ __forceinline__ int lds_index(int p) { return PAD ? p + (p >> 3) : p; }
+// PAD: element p of a contiguous line (ps = 1) is stored at p + (p >> PAD)
+// (one unused slot after every 2^PAD elements; 0 = none), so that the
+// strided Stockham writes spread over the LDS banks.
+// RS: the radix plan (radix_at).
+template <int N> constexpr int padded_line(int pad) { return pad ? N + (N >> pad) : N; }
+template <int PAD> __device__ __forceinline__ int lds_index(int p) { return PAD ? p + (p >> PAD) : p; }
 
-template <typename R, int N, int E, int DIR, int S, bool TWL = false, bool PAD = false>
+template <typename R, int N, int E, int DIR, int S, bool TWL = false, int PAD = 0, int RS = 0>
 struct FftStage {
     static __device__ __forceinline__ void run(cx<R> (&v)[E], cx<R>* lds, int ps,
                                                const cx<R>* __restrict__ tw, int g) {
         constexpr int G = N / E;
-        constexpr int RAD = radix_at(N, S);
-        constexpr int L = span_at(N, S);
+        constexpr int RAD = radix_at(N, S, RS);
+        constexpr int L = span_at(N, S, RS);
         constexpr int Q = E / RAD;
-        constexpr bool LAST = (S == num_stages(N) - 1);
+        constexpr bool LAST = (S == num_stages(N, RS) - 1);
         static_assert(E % RAD == 0, "radix must divide the per-thread element count");
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -114,7 +116,7 @@ struct FftStage {
             for (int r = 0; r < RAD; ++r) x[r] = v[q + r * Q];
             if constexpr (L > 1) {
                 if constexpr (TWL) asm volatile("" ::: "memory");
-                const cx<R>* w = tw + tw_offset(N, S) + j * (RAD - 1);
+                const cx<R>* w = tw + tw_offset(N, S, RS) + j * (RAD - 1);
 #pragma unroll
                 for (int r = 1; r < RAD; ++r)
                     x[r] = (DIR < 0) ? cmul<R>(x[r], w[r - 1]) : cmulc<R>(x[r], w[r - 1]);
@@ -134,24 +136,25 @@ struct FftStage {
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = lds[lds_index<PAD>(g + m * G) * ps];
             __syncthreads();
-            FftStage<R, N, E, DIR, S + 1, TWL, PAD>::run(v, lds, ps, tw, g);
+            FftStage<R, N, E, DIR, S + 1, TWL, PAD, RS>::run(v, lds, ps, tw, g);
         }
     }
 };
 
-// Transform the line held in v (natural distribution in, natural out).
+// Transform the line held in v (natural distribution in, natural out) with
+// radix plan RS, whose twiddle table tw is.
 // Every thread of the workgroup must call this (it contains barriers).
-template <typename R, int N, int E, int DIR, bool TWL = false, bool PAD = false>
+template <typename R, int N, int E, int DIR, bool TWL = false, int PAD = 0, int RS = 0>
 __device__ __forceinline__ void fft_line(cx<R> (&v)[E], cx<R>* lds, int ps,
                                          const cx<R>* __restrict__ tw, int g) {
-    FftStage<R, N, E, DIR, 0, TWL, PAD>::run(v, lds, ps, tw, g);
+    FftStage<R, N, E, DIR, 0, TWL, PAD, RS>::run(v, lds, ps, tw, g);
 }
 
-// Copy the twiddle table into shared memory (all threads of the workgroup
-// call this; ends with a barrier).
-template <typename R, int N>
+// Copy the twiddle table of plan RS into shared memory (all threads of the
+// workgroup call this; ends with a barrier).
+template <typename R, int N, int RS = 0>
 __device__ __forceinline__ void load_twiddles(cx<R>* twl, const cx<R>* __restrict__ tw) {
-    for (int i = threadIdx.x; i < tw_size(N); i += blockDim.x) twl[i] = tw[i];
+    for (int i = threadIdx.x; i < tw_size(N, RS); i += blockDim.x) twl[i] = tw[i];
     __syncthreads();
 }
 

@@ -126,21 +126,34 @@ def test_plan_cache_file_round_trip(tmp_path):
     lib.dns_plan_cache_clear()
     src = tmp_path / "plans.json"
     src.write_text(
-        '{"format": "dns-plan-cache-1", "plans": [\n'
-        '{"device": "gfx950|MI355X|256", "N": 512, "dtype": 0, "members": 1, "variants": '
+        '{"format": "dns-plan-cache-2", "plans": [\n'
+        '{"device": "gfx950|MI355X|256", "N": 512, "dtype": 0, "members": 1, "mode": 0, "variants": '
+        '[[8, 0, 0, 1, 0, 0], [8, 0, 8, 1, 0, 0], [4, 0, 0, -1, 0, 8], [8, 0, 8, -1, 0, 0], [8, 0, 0, -1, 0, 0], '
+        '[8, 0, 0, 1, 0, 0]]},\n'
+        '{"device": "gfx950|MI355X|256", "N": 512, "dtype": 0, "members": 1, "mode": 1, "variants": '
+        '[[8, 0, 0, 1, 2, 0], [8, 0, 8, 1, 2, 0], [4, 0, 0, -1, 0, 16], [8, 0, 8, -1, 2, 0], [8, 0, 0, -1, 0, 0], '
+        '[8, 0, 0, 1, 2, 0]]},\n'
+        '{"device": "gfx950|MI355X|256", "N": 1024, "dtype": 1, "members": 1, "mode": 0, "variants": '
+        '[[8, 1, 0, 0, 0, 0], [16, 0, 32, 0, 0, 0], [2, 0, 0, -1, 0, 8], [16, 0, 32, -1, 0, 0], [8, 1, 0, -1, 0, 0], '
+        '[8, 1, 0, 0, 0, 0]]},\n'
+        # a line of the earlier four-field format and one with an unknown mode are skipped
+        '{"device": "gfx950|MI355X|256", "N": 256, "dtype": 0, "members": 1, "variants": '
         '[[8, 0, 0, 1], [8, 0, 8, 1], [4, 0, 0, -1], [8, 0, 8, -1], [8, 0, 0, -1], [8, 0, 0, 1]]},\n'
-        '{"device": "gfx950|MI355X|256", "N": 1024, "dtype": 1, "members": 1, "variants": '
-        '[[8, 1, 0, 0], [16, 0, 32, 0], [2, 0, 0, -1], [16, 0, 32, -1], [8, 1, 0, -1], [8, 1, 0, 0]]}\n'
+        '{"device": "gfx950|MI355X|256", "N": 128, "dtype": 0, "members": 1, "mode": 5, "variants": '
+        '[[8, 0, 0, 1, 0, 0], [8, 0, 8, 1, 0, 0], [4, 0, 0, -1, 0, 8], [8, 0, 8, -1, 0, 0], [8, 0, 0, -1, 0, 0], '
+        '[8, 0, 0, 1, 0, 0]]}\n'
         ']}\n')
-    assert dns.plan_cache_load(str(src)) == 2
-    assert dns.plan_cache_entries() == 2
+    assert dns.plan_cache_load(str(src)) == 3
+    assert dns.plan_cache_entries() == 3
     out = tmp_path / "out.json"
     dns.plan_cache_save(str(out))
     rec = json.loads(out.read_text())
-    assert rec["format"] == "dns-plan-cache-1" and len(rec["plans"]) == 2
-    by_n = {p["N"]: p for p in rec["plans"]}
-    assert by_n[1024]["variants"][0] == [8, 1, 0, 0] and by_n[1024]["dtype"] == 1
-    assert by_n[512]["variants"][1] == [8, 0, 8, 1] and by_n[512]["device"] == "gfx950|MI355X|256"
+    assert rec["format"] == "dns-plan-cache-2" and len(rec["plans"]) == 3
+    by_key = {(p["N"], p["mode"]): p for p in rec["plans"]}
+    assert by_key[(1024, 0)]["variants"][0] == [8, 1, 0, 0, 0, 0] and by_key[(1024, 0)]["dtype"] == 1
+    assert by_key[(512, 0)]["variants"][1] == [8, 0, 8, 1, 0, 0]
+    assert by_key[(512, 0)]["device"] == "gfx950|MI355X|256"
+    assert by_key[(512, 1)]["variants"][2] == [4, 0, 0, -1, 0, 16] and by_key[(512, 1)]["variants"][0][4] == 2
     with pytest.raises(dns.DnsError):
         dns.plan_cache_load(str(tmp_path / "missing.json"))
     dns.plan_cache_clear()
