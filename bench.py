@@ -744,6 +744,56 @@ def summarize_counters(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cal_b
     return 0
 
 
+def summarize_tg_long(out_md, ref_path, f32_path, coarse_path):
+    """Table of the Taylor-Green Re = 1600 runs to t = 20 (bench.py --tg-long
+    output files): E, Omega and the dissipation 2 nu Omega of the reference
+    run at chosen times, the FP32 run's and the coarser grid's relative
+    differences, the enstrophy peaks, step times and the largest relative
+    energy-budget residuals."""
+    runs = []
+    for path in (ref_path, f32_path, coarse_path):
+        with open(path) as f:
+            runs.append(json.load(f))
+    ref, f32, coarse = runs
+    commands = [f"python -u bench.py --tg-long {r['N']} {r['dtype']} {r['steps']} --tg-long-out {path}"
+                for r, path in zip(runs, (ref_path, f32_path, coarse_path))]
+    commands.append(f"python bench.py --summarize-tg-long {out_md} {ref_path} {f32_path} {coarse_path}")
+
+    def at(r, t):
+        n = int(round(t / r["dt"]))
+        return r["energy"][n], r["enstrophy"][n]
+
+    def peak(r):
+        W = r["enstrophy"]
+        i = max(range(len(W)), key=lambda k: W[k])
+        return i * r["dt"], W[i]
+
+    def name(r):
+        return f"{r['N']}^3 {'FP64' if r['dtype'] == 'f64' else 'FP32'}"
+    lines = ["# Taylor-Green vortex, Re = 1600, t = 0 -> 20 (20 000 RK4 steps, E and Omega every step)", "",
+             "Commands (repository root, on the MI355X machine):", "", "```"] + commands + ["```", "",
+             f"nu = {ref['nu']}, dt = {ref['dt']}, N/3 dealias, Taylor-Green initial field.", "",
+             "| run | ms/step | E(t = 20) | enstrophy peak | at t | max relative budget residual |",
+             "|---|---|---|---|---|---|"]
+    for r in runs:
+        tp, wp = peak(r)
+        lines.append(f"| {name(r)} | {r['ms_per_step']:.3f} | {r['energy'][-1]:.9f} | {wp:.5f} | {tp:.3f} | "
+                     f"{r['max_rel_budget_residual']:.2e} |")
+    lines += ["", "Budget residual per step: |(E_{n+1} - E_n)/dt + nu (Omega_n + Omega_{n+1})| / "
+              "(nu (Omega_n + Omega_{n+1})) (the semi-discrete system has dE/dt = -2 nu Omega).", "",
+              f"| t | E ({name(ref)}) | Omega | 2 nu Omega | E rel. diff. {name(f32)} | E rel. diff. {name(coarse)} | "
+              f"Omega rel. diff. {name(coarse)} |", "|---|---|---|---|---|---|---|"]
+    for t in (0, 2, 4, 6, 8, 9, 10, 12, 16, 20):
+        e, w = at(ref, t)
+        e32, _ = at(f32, t)
+        ec, wc = at(coarse, t)
+        lines.append(f"| {t} | {e:.6f} | {w:.5f} | {2 * ref['nu'] * w:.6f} | {abs(e32 - e) / e:.1e} | "
+                     f"{abs(ec - e) / e:.1e} | {abs(wc - w) / w:.1e} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -781,7 +831,11 @@ def main(argv=None):
                     metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR", "CAL_BYTES", "N", "OUT_JSON",
                              "OUT_MD", "COMMANDS_FILE", "TITLE"),
                     help="write an HBM-traffic summary from rocprofv3 FETCH_SIZE / WRITE_SIZE runs")
+    ap.add_argument("--summarize-tg-long", nargs=4, metavar=("OUT_MD", "REF_JSON", "F32_JSON", "COARSE_JSON"),
+                    help="write the table of three --tg-long runs (reference, FP32, coarser grid)")
     a = ap.parse_args(argv)
+    if a.summarize_tg_long:
+        return summarize_tg_long(*a.summarize_tg_long)
     if a.summarize_trace:
         d, out, cmd, title = a.summarize_trace
         return summarize_trace(d, out, cmd, title)
