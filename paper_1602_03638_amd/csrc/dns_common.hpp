@@ -202,6 +202,16 @@ template <typename R> constexpr int default_y_elems(int N) { return N >= 1024 ? 
 // line).
 constexpr bool y_twiddles_in_lds(int E) { return E > 8; }
 
+// The plain y pass loads the next field's values before the current
+// field's transform (one more line held per thread) where registers are free
+// to do so: FP64 with 8 values per thread below 1024, whose 512-thread
+// workgroups hold one per CU at any register count up to 256 (512^3 forward
+// y pass 1.245 -> 1.206 ms).  FP32 shapes at 128-byte rows are 1024-thread
+// workgroups with 128 registers per thread; 1024-point lines need more
+// registers for the transform itself.  (The vorticity-forming inverse y pass
+// measured slower with its loads moved earlier: 2.235 -> 2.265 ms.)
+template <typename R> constexpr bool y_prefetch(int N, int E) { return sizeof(R) == 8 && E == 8 && N < 1024; }
+
 // Where the vorticity combinations i (ky w - kz v), i (kz u - kx w),
 // i (kx v - ky u) are formed (a plan choice, bitwise neutral: the same
 // operations in another kernel).  With 8 elements per y-line thread the

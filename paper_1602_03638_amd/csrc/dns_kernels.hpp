@@ -299,15 +299,37 @@ __device__ __forceinline__ void yline_tile(cx<R>* __restrict__ W, const cx<R>* _
     // 64-byte FP32 rows measured 763 -> 1079 us per 512^3 launch streaming
     constexpr bool NT = false;
     const Y y(tile);
+    if constexpr (!y_prefetch<R>(N, YE)) {
 #pragma unroll 1
-    for (int f = 0; f < NF; ++f) {
-        cx<R>* F = W + f * FS;
-        cx<R> a[E];
+        for (int f = 0; f < NF; ++f) {
+            cx<R>* F = W + f * FS;
+            cx<R> a[E];
 #pragma unroll
-        for (int m = 0; m < E; ++m) a[m] = y.template el<NT>(F, m);
-        fft_line<R, N, E, DIR, TWL, 0, RS>(a, lds + y.lo, Y::PS, tw, y.g);
+            for (int m = 0; m < E; ++m) a[m] = y.template el<NT>(F, m);
+            fft_line<R, N, E, DIR, TWL, 0, RS>(a, lds + y.lo, Y::PS, tw, y.g);
 #pragma unroll
-        for (int m = 0; m < E; ++m) y.template el<NT>(F, m) = a[m];
+            for (int m = 0; m < E; ++m) y.template el<NT>(F, m) = a[m];
+        }
+    } else {
+        // the next field's values are loaded before this field's transform
+        cx<R> a[E], b[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) a[m] = y.template el<NT>(W, m);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            cx<R>* F = W + f * FS;
+            if (f + 1 < NF) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) b[m] = y.template el<NT>(F + FS, m);
+            }
+            fft_line<R, N, E, DIR, TWL, 0, RS>(a, lds + y.lo, Y::PS, tw, y.g);
+#pragma unroll
+            for (int m = 0; m < E; ++m) y.template el<NT>(F, m) = a[m];
+            if (f + 1 < NF) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) a[m] = b[m];
+            }
+        }
     }
 }
 

@@ -184,3 +184,29 @@ def test_trace_summary_table(tmp_path):
     text = out.read_text()
     assert "`k_zcross<double, 512, 4>` | 4 | 1800.0" in text
     assert f"{9 * bench.field_bytes(512, 'f64') / 1.8e-3 / 1e9:.0f}" in text
+
+
+def test_long_run_summary(tmp_path):
+    """The Taylor-Green long-run table: times, peaks, budget residuals, the
+    relative differences of the FP32 and coarse runs, and the commands that
+    reproduce the runs."""
+    def run(N, dtype, scale, peak_at):
+        steps, dt = 20000, 1e-3
+        E = [0.125 * scale * (1.0 - 0.8 * n / steps) for n in range(steps + 1)]
+        W = [0.375 + 10.0 * (1.0 - abs(n - peak_at) / steps) for n in range(steps + 1)]
+        rec = {"N": N, "dtype": dtype, "nu": 1 / 1600, "dt": dt, "steps": steps, "ms_per_step": 1.5,
+               "energy": E, "enstrophy": W, "max_rel_budget_residual": 2e-7}
+        path = tmp_path / f"run_{N}_{dtype}.json"
+        path.write_text(json.dumps(rec))
+        return str(path)
+    ref, f32, coarse = run(512, "f64", 1.0, 8976), run(512, "f32", 1.0 + 1e-5, 8976), run(256, "f64", 1.01, 8884)
+    out = tmp_path / "long.md"
+    assert bench.summarize_tg_long(str(out), ref, f32, coarse) == 0
+    text = out.read_text()
+    assert f"python -u bench.py --tg-long 512 f32 20000 --tg-long-out {f32}" in text
+    assert f"python bench.py --summarize-tg-long {out} {ref} {f32} {coarse}" in text
+    assert "| 512^3 FP64 | 1.500 | 0.025000000 | 10.37500 | 8.976 | 2.00e-07 |" in text
+    assert "| 256^3 FP64 | 1.500 |" in text and "| 8.884 |" in text
+    # t = 0 row: E, Omega, 2 nu Omega and the relative differences (1e-5 and 1e-2)
+    row0 = [ln for ln in text.splitlines() if ln.startswith("| 0 |")][0]
+    assert row0.startswith("| 0 | 0.125000 |") and "1.0e-05" in row0 and "1.0e-02" in row0
