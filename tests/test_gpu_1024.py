@@ -11,6 +11,8 @@ the mathematics at any size, and the oracle at a size it can evaluate:
     N^3 a e^{i phi} / 2 at k and zero at every other stored mode (closed form
     of the DFT, which pins axis order, sign and normalisation), and the
     inverse transform of that spectrum is the sum of cosines;
+  * dns_rhs of the Taylor-Green field equals the exact DFT of its
+    closed-form initial tendency (curl, cross product and projection);
   * the random initial field has E = 0.5 and the semi-discrete energy budget
     dE/dt = -2 nu Omega holds over RK4 steps (trapezoid rule);
   * FP32 and FP64 runs from the same spectrum agree in energy to 1e-5.
@@ -126,6 +128,94 @@ def test_rhs_1024_band_limited_matches_oracle_128(dtype, tol, band_rhs):
     note(f"band rhs 1024 {dtype}")
     check_band_rhs(N, dtype, band_rhs, tol)
     torch_mod().cuda.empty_cache()
+
+
+def _trig_modes(terms):
+    """Half-spectrum DFT / N^3 of a sum of separable trigonometric terms
+    (component, coefficient, (kind, a) per axis), as {(component, kx, ky, kz):
+    value} over kz >= 0.  The Fourier coefficients of the factors are
+    cos(a x): 1/2 at +-a; sin(a x): -i/2 at +a, +i/2 at -a; 1: 1 at 0."""
+    def coeffs(kind, a):
+        if a == 0:
+            return {0: 1.0}
+        return {a: 0.5, -a: 0.5} if kind == "c" else {a: -0.5j, -a: 0.5j}
+    modes = {}
+    for c, coef, fx, fy, fz in terms:
+        for kx, ax in coeffs(*fx).items():
+            for ky, ay in coeffs(*fy).items():
+                for kz, az in coeffs(*fz).items():
+                    if kz >= 0:
+                        key = (c, kx, ky, kz)
+                        modes[key] = modes.get(key, 0.0) + coef * ax * ay * az
+    return modes
+
+
+# Taylor-Green field u0 = (sin x cos y cos z, -cos x sin y cos z, 0) and the
+# closed form of its nonlinear tendency at t = 0 (the form pinned for the
+# oracle in oracle_pins.tg_initial_tendency_error): the projected
+# -u0.grad u0 - grad p0 = (-sin 2x cos 2z, -sin 2y cos 2z,
+# (cos 2x + cos 2y) sin 2z) / 8; the right-hand side adds -nu |k|^2 u_hat.
+TG_U = [(0, 1.0, ("s", 1), ("c", 1), ("c", 1)), (1, -1.0, ("c", 1), ("s", 1), ("c", 1))]
+TG_N = [(0, -1 / 8, ("s", 2), ("c", 0), ("c", 2)), (1, -1 / 8, ("c", 0), ("s", 2), ("c", 2)),
+        (2, 1 / 8, ("c", 2), ("c", 0), ("s", 2)), (2, 1 / 8, ("c", 0), ("c", 2), ("s", 2))]
+
+
+def _check_sparse(got, modes, n3):
+    """Largest deviation of `got` from the sparse spectrum N^3 * modes (every
+    other stored mode must be zero), relative to its largest coefficient;
+    `got` is overwritten."""
+    scale = n3 * max(abs(v) for v in modes.values())
+    err = 0.0
+    for (c, kx, ky, kz), v in modes.items():
+        ix, iy = kx % N, ky % N
+        err = max(err, abs(complex(got[c, ix, iy, kz].item()) - n3 * v))
+        got[c, ix, iy, kz] = 0
+    return err / scale, float(got.abs().max().item()) / scale
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 2e-5)])
+def test_rhs_1024_taylor_green_closed_form(dtype, tol):
+    """dns_init_velocity(Taylor-Green) and dns_rhs at 1024^3 in the default
+    schedule, every stored mode against closed forms: the spectrum u_hat
+    against the exact DFT of the field, and the nonlinear part
+    RHS + nu |k|^2 u_hat (with the context's own u_hat) against the exact DFT
+    of the closed-form initial tendency (zero at every other stored mode, the
+    Nyquist planes included).  The nonlinear part is compared separately
+    because outside the 2/3 mask the right-hand side is -nu |k|^2 u_hat
+    alone, which scales the transform's rounding there by up to 3 nu (N/2)^2.
+    This pins the curl, the cross product and the projection of the 1024^3
+    code by a result fixed by the mathematics.  The bound is a maximum over
+    all 1.6e9 stored modes relative to the largest coefficient: the rounding
+    of sampled sines and cosines is shared between points a quarter period
+    apart (sin(x + pi/2) = cos x), so it concentrates at kx = +-N/4 next to
+    the field's own ky, kz (measured 1.2e-14 FP64, 8.6e-6 FP32 there; the
+    ratio of the two is that of the precisions)."""
+    note(f"1024 {dtype} Taylor-Green closed-form tendency")
+    torch = torch_mod()
+    from paper_1602_03638_amd import Solver
+    nu = 0.0173
+    s = Solver(N, nu, DT, dtype=dtype)
+    s.init_velocity("taylor_green")
+    uh = s.get_spectral()
+    got = s.rhs()
+    s.close()
+    torch.cuda.empty_cache()
+    real = torch.float64 if dtype == "f64" else torch.float32
+    k = torch.fft.fftfreq(N, 1.0 / N, dtype=torch.float64, device="cuda")
+    kz = torch.arange(N // 2 + 1, dtype=torch.float64, device="cuda")
+    k2 = ((k * k)[:, None, None] + (k * k)[None, :, None] + (kz * kz)[None, None, :]).to(real)
+    for c in range(3):
+        got[c] += (nu * k2) * uh[c]     # N_hat = RHS + nu |k|^2 u_hat
+    del k2
+    n3 = float(N) ** 3
+    eu = _check_sparse(uh, _trig_modes(TG_U), n3)
+    del uh
+    en = _check_sparse(got, _trig_modes(TG_N), n3)
+    del got
+    torch.cuda.empty_cache()
+    note(f"  u_hat: {eu[0]:.2e} at its modes, {eu[1]:.2e} elsewhere; "
+         f"nonlinear part: {en[0]:.2e} at its modes, {en[1]:.2e} elsewhere")
+    assert max(eu) <= tol and max(en) <= tol
 
 
 def test_rhs_1024_xcd_grouped_tiles_bitwise(band_rhs):
