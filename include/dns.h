@@ -276,9 +276,11 @@ int dns_inverse(dns_t* ctx, const void* uhat_dev, void* u_dev);
  * variants of the other radix plans and may choose them (results then agree
  * with the default plan to rounding, not bitwise); DNS_TUNE_REPRODUCIBLE is
  * dns_autotune.  dns_get_plan writes the chosen widths (6 entries);
- * dns_set_plan selects variants by width (DNS_E_INVAL if a width does not
- * exist for this N and dtype); dns_plan_variants lists the widths available
- * for one kernel (pass index 0..5).  With opts.mfma_dft the y passes run the
+ * dns_set_plan selects variants by width, keeping the current schedule and,
+ * where such a variant exists, the current radix plan and pad (else plan 0
+ * and the default pad); DNS_E_INVAL if a width does not exist for this N and
+ * dtype.  dns_plan_variants lists the widths available for one kernel (pass
+ * index 0..5) with the current schedule.  With opts.mfma_dft the y passes run the
  * matrix-core kernel, which has a single shape; their widths then only
  * matter for a later context without the option.
  *
@@ -287,7 +289,8 @@ int dns_inverse(dns_t* ctx, const void* uhat_dev, void* u_dev);
  * launch, tuning mode), each as the descriptors of its variants (see
  * dns_variant below): dns_autotune(_ex) stores its choice, and a context or
  * ensemble created with opts.autotune = 1 (2) takes the cached plan of the
- * reproducible (fastest) mode when one exists instead of timing again.  dns_plan_cache_entries returns the number of cached plans;
+ * reproducible (fastest) mode when one exists instead of timing again.
+ * dns_plan_cache_entries returns the number of cached plans;
  * dns_plan_cache_clear empties the cache.  Persistence across processes:
  * dns_plan_cache_save writes the cache to a file (JSON, one plan per line),
  * dns_plan_cache_load adds a file's plans to the cache and returns how many
@@ -319,9 +322,10 @@ int dns_plan_cache_load(const char* path);
  *    products; 1 = the inverse y pass combines them from the x pass's five
  *    fields, 0 = the x pass writes all six;
  *  - xcd_pair: the device dispatches workgroup b to XCD b mod 8, each XCD
- *    with its own L2.  Where an x-pass tile's row segments are 64 bytes,
- *    1 = the two tiles of each 128-byte line go to workgroups b and b + 8
- *    (one XCD), 0 = to consecutive workgroups;
+ *    with its own L2.  Where an x- or y-pass tile's row segments are
+ *    shorter than 128 bytes (32 or 64; N >= 256), 1 = the two or four tiles
+ *    of each 128-byte line go to workgroups b, b + 8, ... (one XCD), 0 = to
+ *    consecutive workgroups;
  *  - lds_pad (z pass only, else 0): a line's element p sits in shared
  *    memory at p + p / lds_pad (one unused slot after every lds_pad
  *    elements; 0 = no padding; default 8), which spreads the strided
@@ -336,14 +340,15 @@ int dns_plan_cache_load(const char* path);
  *    explicit dns_set_plan_ex chooses them.
  * dns_set_schedule selects, for every pass, the variant of radix plan 0 and
  * the default pad of the current width (else the nearest width) that runs
- * the given schedule; y_elems 0,
- * curl_in_y -1 and xcd_pair -1 take the defaults for N.  DNS_E_INVAL for an
+ * the given schedule; y_elems 0, curl_in_y -1 and xcd_pair -1 take the
+ * defaults for N.  DNS_E_INVAL for an
  * invalid value, DNS_E_UNSUPPORTED for a schedule this N and dtype (or the
  * matrix-core option) do not provide.  Waits for the stream.
  *
  * dns_plan_variants_ex lists every variant of one pass (index order of
  * dns_get_plan) with its descriptor (y_elems 0 for passes other than the y
- * passes; curl_in_y -1 for passes that do not depend on it).
+ * passes; curl_in_y -1 for passes that do not depend on it; radix and
+ * lds_pad as above).
  * dns_get_plan_ex / dns_set_plan_ex read and install a plan as one variant
  * index per pass; DNS_E_INVAL if an index is out of range or the inverse x,
  * inverse y and stage passes disagree on curl_in_y. */
