@@ -90,3 +90,19 @@ def embed_on_device(uh_small, n, dtype, kb):
     for c in range(3):
         out[c][bi] = torch.from_numpy(np.ascontiguousarray(box[c])).to(cdt).cuda()
     return out
+
+
+def radix_plan(s, rs):
+    """Variant indices of the solver's current plan with every pass that has a
+    variant of radix plan rs at its current shape switched to it, and the
+    passes switched."""
+    var, plan = s.plan_variants_ex(), s.plan_ex()
+    moved = []
+    for p, i in plan.items():
+        cur = var[p][i]
+        keys = ("width", "xcd_pair", "y_elems", "curl_in_y")
+        hit = [j for j, d in enumerate(var[p]) if d["radix"] == rs and all(d[k] == cur[k] for k in keys)]
+        if hit:
+            plan[p] = hit[0]
+            moved.append(p)
+    return plan, moved

@@ -218,6 +218,16 @@ def test_rhs_1024_taylor_green_closed_form(dtype, tol):
     assert max(eu) <= tol and max(en) <= tol
 
 
+@pytest.mark.parametrize("rs", [1, 2])
+def test_rhs_1024_radix_plans_match_oracle_128(rs, band_rhs):
+    """The other radix plans at 1024 (1: 1024 = 2 8 8 8, 2: 1024 = 4^5) on
+    every pass, FP32: the band-limited right-hand side element by element
+    against the oracle at 128^3, to the default plan's tolerance."""
+    note(f"band rhs 1024 f32 radix plan {rs}")
+    check_band_rhs(N, "f32", band_rhs, 5e-6, radix=rs)
+    torch_mod().cuda.empty_cache()
+
+
 def test_rhs_1024_xcd_grouped_tiles_bitwise(band_rhs):
     """The XCD-grouped x and y passes (the tiles of a 128-byte line on one
     XCD), and the five-field schedule (vorticity combined in the y pass)

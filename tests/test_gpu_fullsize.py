@@ -14,7 +14,8 @@ import numpy as np
 import pytest
 
 import workloads
-from gpu_util import band_limited_spectrum, box_index, embed_low_modes, embed_on_device, note, to_dev, to_host
+from gpu_util import (band_limited_spectrum, box_index, embed_low_modes, embed_on_device, note, radix_plan,
+                      to_dev, to_host)
 from oracle import spectral
 
 pytestmark = pytest.mark.gpu
@@ -110,12 +111,14 @@ def band_rhs():
     return uh, r, nu
 
 
-def check_band_rhs(N, dtype, band_rhs, tol, **sched):
+def check_band_rhs(N, dtype, band_rhs, tol, radix=0, **sched):
     """dns_rhs at N^3 of the band-limited field against the oracle's 128^3
     right-hand side: every mode of the box |k_i| <= 2 KB element by element
     (scaled by (N/128)^3), and every mode outside the box (the zero high
     modes, the masked modes and the Nyquist planes) zero to rounding.
-    Returns the relative L2 error over all stored modes."""
+    radix != 0: every pass that has a variant of that radix plan at its
+    default shape runs it.  Returns the relative L2 error over all stored
+    modes."""
     torch = __import__("torch")
     uh, ref, nu = band_rhs
     src = uh if dtype == "f64" else uh.astype(np.complex64).astype(np.complex128)
@@ -123,6 +126,11 @@ def check_band_rhs(N, dtype, band_rhs, tol, **sched):
         ref = spectral.rhs(src, nu, spectral.wavenumber_mesh(N_ORACLE), spectral.dealias_mask(N_ORACLE))
     from paper_1602_03638_amd import Solver
     s = Solver(N, nu, 1e-3, dtype=dtype, **sched)
+    if radix:
+        plan, moved = radix_plan(s, radix)
+        assert moved, f"no variant of radix plan {radix} at N={N}"
+        s.set_plan_ex(plan)
+        note(f"  radix plan {radix} on {', '.join(moved)}")
     dev = embed_on_device(src, N, dtype, KB)
     s.set_spectral(dev)
     del dev
@@ -155,6 +163,15 @@ def test_rhs_512_band_limited_matches_oracle_128(dtype, tol, band_rhs):
     of the benchmark: default plan)."""
     note(f"band rhs 512 {dtype}")
     check_band_rhs(512, dtype, band_rhs, tol)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 5e-6)])
+def test_rhs_512_radix4_plan_matches_oracle_128(dtype, tol, band_rhs):
+    """The radix-4 plan (512 = 4 4 4 8, radix plan 2, the one that differs
+    from the default at 512) on every pass at the benchmark's size: the same
+    element-by-element comparison with the oracle at 128^3."""
+    note(f"band rhs 512 {dtype} radix plan 2")
+    check_band_rhs(512, dtype, band_rhs, tol, radix=2)
 
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 5e-6)])

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import workloads
-from gpu_util import note, rel_l2, spectral_rel_l2, to_dev, to_host
+from gpu_util import note, radix_plan, rel_l2, spectral_rel_l2, to_dev, to_host
 from oracle import ic, spectral
 
 pytestmark = pytest.mark.gpu
@@ -260,21 +260,6 @@ def test_every_plan_variant_is_bitwise_identical(N, dtype):
     s.close()
 
 
-def _radix_plan(s, rs):
-    """The current plan with every pass that has a variant of radix plan rs
-    at its current shape switched to it; the passes switched."""
-    var, plan = s.plan_variants_ex(), s.plan_ex()
-    moved = []
-    for p, i in plan.items():
-        cur = var[p][i]
-        keys = ("width", "xcd_pair", "y_elems", "curl_in_y")
-        hit = [j for j, d in enumerate(var[p]) if d["radix"] == rs and all(d[k] == cur[k] for k in keys)]
-        if hit:
-            plan[p] = hit[0]
-            moved.append(p)
-    return plan, moved
-
-
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("N", [16, 32, 128])
 @pytest.mark.parametrize("rs", [1, 2])
@@ -288,7 +273,7 @@ def test_radix_plans_match_oracle(N, dtype, rs):
     nu = 0.0137
     uh = _rhs_input(N, seed=90 + N + rs)
     s = _solver(N, nu=nu, dtype=dtype)
-    plan, moved = _radix_plan(s, rs)
+    plan, moved = radix_plan(s, rs)
     l = int(np.log2(N))
     distinct = (rs == 1 and l % 3 != 0) or (rs == 2 and l not in (3, 5))
     assert bool(moved) == distinct, (moved, distinct)
