@@ -241,3 +241,24 @@ def test_ensemble_one_graph_launch_equals_replays():
         assert np.array_equal(to_host(a.get_spectral(j)), to_host(b.get_spectral(j))), j
     a.close()
     b.close()
+
+
+def test_ensemble_tuned_modes():
+    """Ensembles tuned at creation: in reproducible mode every member keeps
+    the untuned ensemble's bits; in fastest mode (radix plans allowed) every
+    member agrees with them to rounding (FP32 relative L2 <= 2e-6 after 3
+    steps)."""
+    note("ensemble tuned reproducible / fastest")
+    Ns = [32, 64, 32, 128]
+    nu, dt = 0.01, 0.005
+    runs = {}
+    for mode in (False, "reproducible", "fastest"):
+        e = _ensemble(Ns, [nu] * len(Ns), [dt] * len(Ns), dtype="f32", autotune=mode)
+        for j in range(len(Ns)):
+            e.init_random(j, 1200 + j)
+        e.step(3)
+        runs[mode] = [to_host(e.get_spectral(j)) for j in range(len(Ns))]
+        e.close()
+    for j in range(len(Ns)):
+        assert np.array_equal(runs["reproducible"][j], runs[False][j]), j
+        assert spectral_rel_l2(runs["fastest"][j], runs[False][j]) <= 2e-6, j
