@@ -294,10 +294,12 @@ __device__ __forceinline__ void yline_tile(cx<R>* __restrict__ W, const cx<R>* _
     constexpr int E = Y::E;
     constexpr size_t FS = Lay<R, N>::FS;
     constexpr bool TWL = y_twiddles_in_lds(YE);
-    // plain accesses: the forward pass, and the inverse pass of the
-    // standalone transform (stage passes below 1024 use k_yinv_curl), whose
-    // 64-byte FP32 rows measured 763 -> 1079 us per 512^3 launch streaming
-    constexpr bool NT = false;
+    // Streaming (non-temporal) accesses only where the next field's loads
+    // are issued ahead (FP64, 8 per thread, 256^3 and 512^3: forward pass
+    // 1.211 -> 1.182 ms per 512^3 launch); plain elsewhere: without the
+    // prefetch the forward pass measured 1.23 -> 1.44 ms streaming, and the
+    // standalone inverse's 64-byte FP32 rows 763 -> 1079 us.
+    constexpr bool NT = y_prefetch<R>(N, YE) && stream_io<R>(N);
     const Y y(tile);
     if constexpr (!y_prefetch<R>(N, YE)) {
 #pragma unroll 1
