@@ -568,3 +568,30 @@ def test_nyquist_planes_of_masked_fields_stay_zero(dtype):
     assert np.count_nonzero(uh[:, N // 2, :, :]) == 0 and np.count_nonzero(uh[:, :, N // 2, :]) == 0
     assert np.count_nonzero(uh) > 0
     s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_variant_tables(dtype):
+    """The plan dimensions each size offers: radix plan 1 (remainder stage
+    first) exactly where log2 N is not a multiple of 3, plan 2 (radix-4
+    stages) where it differs from plans 0 and 1 (not at 8 and 32), each on
+    every pass; the z pass with no pad and pads 4, 8 and 16 at its default
+    width; defaults on plan 0 with the z pad 8; every descriptor's radix and
+    pad in range."""
+    note(f"variant tables {dtype}")
+    for N in (8, 16, 32, 64, 128, 256):
+        s = _solver(N, dtype=dtype)
+        var, sched = s.plan_variants_ex(), s.schedule()
+        l = N.bit_length() - 1
+        want = {1: l % 3 != 0, 2: N not in (8, 32)}
+        for rs, present in want.items():
+            for p, vs in var.items():
+                assert any(d["radix"] == rs for d in vs) == present, (N, p, rs)
+        zw = sched["zcross"]["width"]
+        pads = {d["lds_pad"] for d in var["zcross"] if d["width"] == zw and d["radix"] == 0}
+        assert pads == {0, 4, 8, 16}, (N, pads)
+        assert all(d["radix"] == 0 for d in sched.values()) and sched["zcross"]["lds_pad"] == 8
+        for p, vs in var.items():
+            assert all(d["radix"] in (0, 1, 2) for d in vs)
+            assert all(d["lds_pad"] == 0 for d in vs) or p == "zcross"
+        s.close()
